@@ -1,0 +1,74 @@
+"""FP64 reference for the time-spectral GLS convection-diffusion equation
+(section "Convection-diffusion in multiple dimensions", eq. 3D-weak and
+eq. 3D-weak-def), assembled as a sparse complex matrix.
+
+TEST INFRASTRUCTURE ONLY (pins the GLS machinery: convergence rates of the
+error estimate's remarks and the identity of Lemma 1).
+
+A source term f is allowed so that manufactured solutions can be used; it
+enters as (w, f) + (L(w), tau f), which keeps the method consistent.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sps
+import scipy.sparse.linalg as spla
+
+from .tsref import QP_BARY, geometry, toeplitz, tau_from_velocity, omega_diag
+
+
+def element_matrices(xyz, tets, uq, kappa, omega, C_I=3.0):
+    """B[e, a, b] (N x N complex) of b(N_a e, N_b e') and tau per qp.
+
+    uq: (E, 4, 3, N) complex velocity modes at the quadrature points.
+    """
+    grads, vol, G = geometry(xyz, tets)
+    N = uq.shape[-1]
+    K = (N - 1) // 2
+    Om = np.diag(omega_diag(K, omega))
+    w = vol / 4.0
+    A = toeplitz(uq)                                               # (E,4,3,N,N)
+    tau = tau_from_velocity(uq, G[:, None], kappa, C_I)            # (E,4,N,N)
+    AdN = np.einsum("eqimn,ebi->eqbmn", A, grads, optimize=True)  # A_i dN_b/dx_i
+    T = np.einsum("qb,mn->qbmn", QP_BARY, Om)[None] + AdN          # Omega N_b + A.grad N_b
+    P = -np.einsum("qa,mn->qamn", QP_BARY, Om)[None] + AdN         # adjoint test operator
+    I = np.eye(N)
+    B = (np.einsum("e,qa,eqbmn->eabmn", w, QP_BARY, T, optimize=True)
+         + kappa * np.einsum("e,eak,ebk,mn->eabmn", vol, grads, grads, I, optimize=True)
+         + np.einsum("e,eqamk,eqkl,eqbln->eabmn", w, P, tau, T, optimize=True))
+    return B, tau, P, w
+
+
+def assemble(xyz, tets, B):
+    E, _, _, N, _ = B.shape
+    n = xyz.shape[0]
+    rows = (tets[:, :, None, None, None] * N + np.arange(N)[None, None, None, :, None])
+    cols = (tets[:, None, :, None, None] * N + np.arange(N)[None, None, None, None, :])
+    rows = np.broadcast_to(rows, B.shape).ravel()
+    cols = np.broadcast_to(cols, B.shape).ravel()
+    return sps.csr_matrix((B.ravel(), (rows, cols)), shape=(n * N, n * N))
+
+
+def source_vector(xyz, tets, P, tau, w, fq):
+    """(w, f) + (L(w), tau f): fq (E, 4, N) source modes at the qp."""
+    N = fq.shape[-1]
+    tf = np.einsum("eqmn,eqn->eqm", tau, fq)
+    Fe = (np.einsum("e,qa,eqm->eam", w, QP_BARY, fq)
+          + np.einsum("e,eqamn,eqn->eam", w, P, tf, optimize=True))
+    F = np.zeros((xyz.shape[0], N), dtype=complex)
+    np.add.at(F, tets, Fe)
+    return F.ravel()
+
+
+def solve_dirichlet(Amat, F, n_nodes, N, bnodes, gvals):
+    """Solve with phi = g on bnodes (rows replaced, columns moved to the rhs)."""
+    phi = np.zeros((n_nodes, N), dtype=complex)
+    phi[bnodes] = gvals
+    fixed = np.zeros(n_nodes * N, dtype=bool)
+    fixed.reshape(n_nodes, N)[bnodes] = True
+    free = ~fixed
+    rhs = F - Amat @ phi.ravel()
+    sol = spla.spsolve(Amat[free][:, free].tocsc(), rhs[free])
+    out = phi.ravel().copy()
+    out[free] = sol
+    return out.reshape(n_nodes, N)
