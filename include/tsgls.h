@@ -1,0 +1,170 @@
+/*
+ * tsgls.h -- C ABI of the MI355X (gfx950) library for the stabilized
+ * time-spectral Galerkin/least-squares (GLS) finite element method for
+ * time-periodic incompressible Navier-Stokes on linear tetrahedra
+ * (Esmaily & Jia, arXiv:2311.09465).
+ *
+ * What it computes (paper references are to that article):
+ *   residual  -- eq. Rmc (momentum rows r^m for non-Dirichlet nodes,
+ *                continuity rows r^c for all nodes) plus the backflow
+ *                stabilization term of the section "Stabilizing simulations
+ *                in the presence of backflow" and the Neumann traction term;
+ *   linearize -- freezes the convection matrices A_i and the stabilization
+ *                matrix tau = [A_i G_ij A_j + C_I nu^2 G_ij G_ij I]^(-1/2)
+ *                (eq. 3D-tau, nu = mu/rho) at every volume quadrature point,
+ *                and |A_n|_- at every Neumann-face quadrature point;
+ *   jv        -- the tangent-vector product: eq. K_mat ("Picard": A and tau
+ *                frozen, remark 5 after eq. K_mat), optionally without the
+ *                least-squares part of G_i and D_i (section "Exploiting the
+ *                structure of H"), or with the derivative of A_i kept
+ *                ("Newton", tau still frozen); optional pseudo-time mass
+ *                shift c1 rho / dt (N_A, N_B), c1 = 1.5 (section
+ *                "Pseudo-time stepping");
+ *   solve     -- Newton-Raphson (eq. NR) with right-Jacobi-preconditioned
+ *                restarted GMRES, stopped at ||r|| <= rtol ||r^0|| (remarks
+ *                after eq. K_mat).
+ *
+ * Conventions shared by every entry point
+ *   Mode count   K = number of harmonics (the paper's N is K+1).
+ *   State layout y[n_nodes][4][2K+2] float64, fields (u1, u2, u3, p);
+ *                slot 2k = Re c_k, slot 2k+1 = Im c_k, k = 0..K, where a real
+ *                periodic field is f(t) = sum_{|k|<=K} c_k exp(i k omega t)
+ *                (real-valued unknowns of the section "Using real-valued
+ *                unknowns"; slot 1 (Im c_0) is ignored on input and written
+ *                as 0 on output).  Residual and tangent outputs use the same
+ *                layout: slot 2k = Re r_k, 2k+1 = Im r_k.
+ *   Dirichlet    velocity values are part of y (the paper's implementation
+ *                builds them into the unknown vector); momentum rows of
+ *                Dirichlet nodes are written as 0, and jv treats the
+ *                Dirichlet velocity entries of its input as 0.
+ *   Memory       mesh and boundary-data arrays passed to create/set_* are
+ *                HOST pointers and are copied; y, r, v, Jv, d are DEVICE
+ *                pointers (float64, n_nodes*4*(2K+2) entries) owned by the
+ *                caller.  The library owns everything it allocates.
+ *   Streams      all device work is enqueued on the hip_stream given to
+ *                tsgls_create (NULL = default stream).  residual / linearize
+ *                / jv / jacobi_diag return without synchronizing; solve
+ *                synchronizes before it returns.
+ *   Errors       every call returns TSGLS_OK (0) or a negative code; the
+ *                message of the last error is in tsgls_last_error(ctx).
+ *                solve may return TSGLS_NOT_CONVERGED (+1) with y and the
+ *                statistics written.  No exception crosses this boundary.
+ */
+#ifndef TSGLS_H
+#define TSGLS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TSGLS_OK 0
+#define TSGLS_NOT_CONVERGED 1
+#define TSGLS_EINVAL (-1)      /* null pointer, bad size, K or nu out of range */
+#define TSGLS_EHIP (-2)        /* a HIP runtime call failed */
+#define TSGLS_ENOMEM (-3)      /* device or host allocation failed */
+#define TSGLS_EMESH (-4)       /* non-positive tet volume, bad index, degenerate face */
+#define TSGLS_ENONFINITE (-5)  /* NaN/Inf in the residual or a Krylov quantity */
+#define TSGLS_ESTATE (-6)      /* jv / jacobi_diag before linearize */
+
+/* Tangent variants (jv, jacobi_diag, solve). */
+#define TSGLS_JAC_PICARD 0       /* eq. K_mat: A_i and tau frozen (paper's tangent) */
+#define TSGLS_JAC_PICARD_NOLS 1  /* eq. K_mat with least-squares terms of G_i, D_i dropped */
+#define TSGLS_JAC_NEWTON 2       /* A_i(u) differentiated, tau and |A_n|_- frozen */
+
+typedef struct tsgls_ctx tsgls_ctx;
+
+typedef struct {
+  double rho;            /* density > 0 */
+  double mu;             /* dynamic viscosity > 0; nu = mu/rho enters tau */
+  double omega;          /* base angular frequency 2 pi / T */
+  int K;                 /* harmonics, 0 <= K; compiled set in tsgls_supported_K */
+  double C_I;            /* tau diffusive constant, 3 for linear tets */
+  double backflow_beta;  /* backflow coefficient beta in [0, 1] */
+} tsgls_params;
+
+typedef struct {
+  double rtol;       /* Newton stop: ||r|| <= rtol ||r^0||, e.g. 1e-8 */
+  double lin_rtol;   /* GMRES relative tolerance, e.g. 0.05 */
+  int restart;       /* Krylov dimension, e.g. 100 (1..1000) */
+  int max_newton;    /* Newton / pseudo-time iterations */
+  int max_matvec;    /* tangent products per linear solve */
+  int jacobian;      /* TSGLS_JAC_* */
+  double dt_pseudo;  /* pseudo-time step; <= 0 disables the mass shift */
+  int verbose;       /* 1: one line per Newton step on stderr */
+} tsgls_solve_opts;
+
+typedef struct {
+  int newton_iters;
+  int matvecs;
+  int status;             /* TSGLS_OK or TSGLS_NOT_CONVERGED */
+  double rel_residual;    /* ||r|| / ||r^0|| at return */
+  double r0_norm;         /* ||r^0|| (Euclidean norm of the masked slot vector) */
+  double seconds;         /* wall time of the solve */
+  double history[64];     /* ||r||/||r^0|| after each Newton step (first 64) */
+} tsgls_solve_stats;
+
+/* Harmonic counts compiled into this library: writes up to cap values into
+ * out, returns how many exist. */
+int tsgls_supported_K(int* out, int cap);
+
+/* Create a context for one mesh.  xyz: host [n_nodes][3]; tets: host
+ * [n_tets][4] 0-based, positively oriented (TSGLS_EMESH otherwise).  The
+ * library colours the elements (no two elements of a colour share a node)
+ * and computes the element geometry on the device. */
+int tsgls_create(const double* xyz, int64_t n_nodes, const int32_t* tets,
+                 int64_t n_tets, const tsgls_params* params, void* hip_stream,
+                 tsgls_ctx** out);
+
+/* Nodes whose three velocity components are prescribed (host, n entries,
+ * each in [0, n_nodes)).  Replaces any earlier set. */
+int tsgls_set_dirichlet(tsgls_ctx* ctx, const int32_t* nodes, int64_t n);
+
+/* Neumann (outflow) faces: host tris [nf][3] node ids, ordered so that
+ * (x1-x0) x (x2-x0) points out of the domain; h: host [nf][2K+2] traction
+ * modes per face (slot layout, constant over the face) or NULL for h = 0.
+ * Replaces any earlier set. */
+int tsgls_set_neumann(tsgls_ctx* ctx, const int32_t* tris, int64_t nf,
+                      const double* h);
+
+/* r = residual(y) (eq. Rmc + backflow + Neumann traction), masked.
+ * Does not change the linearization used by jv. */
+int tsgls_residual(tsgls_ctx* ctx, const double* y, double* r);
+
+/* Freeze A_i, tau (and, for the Newton tangent, tau L_i(u)) at y.  If r is
+ * not NULL the residual at y is written there as a by-product. */
+int tsgls_linearize(tsgls_ctx* ctx, const double* y, double* r);
+
+/* Jv = J v with the last linearization; variant TSGLS_JAC_*; dt_pseudo > 0
+ * adds the pseudo-time mass shift.  v and Jv must not alias. */
+int tsgls_jv(tsgls_ctx* ctx, const double* v, double* Jv, int jacobian,
+             double dt_pseudo);
+
+/* d = diagonal of the Picard tangent (with the mass shift if dt_pseudo > 0),
+ * 1 on masked slots. */
+int tsgls_jacobi_diag(tsgls_ctx* ctx, double* d, double dt_pseudo);
+
+/* Copy the frozen tau of the last linearize to HOST memory tau_out
+ * [n_tets][4][n(n+1)/2], input element order, n = 2K+1, upper triangle row
+ * by row, in the real orthonormal basis (c_0, sqrt2 Re c_1, sqrt2 Im c_1,
+ * ..., sqrt2 Re c_K, sqrt2 Im c_K). */
+int tsgls_get_tau(tsgls_ctx* ctx, double* tau_out);
+
+/* Newton-GMRES from y (device, in: initial guess, out: solution).  stats is
+ * a host pointer (may be NULL). */
+int tsgls_solve(tsgls_ctx* ctx, double* y, const tsgls_solve_opts* opts,
+                tsgls_solve_stats* stats);
+
+/* Introspection: n_colors, element and node counts, bytes held on device. */
+int tsgls_info(const tsgls_ctx* ctx, int64_t* n_colors, int64_t* n_tets,
+               int64_t* n_nodes, int64_t* device_bytes);
+
+const char* tsgls_last_error(const tsgls_ctx* ctx);
+
+void tsgls_destroy(tsgls_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TSGLS_H */

@@ -1,0 +1,193 @@
+"""Python binding of libtsgls.so (include/tsgls.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts numpy/torch
+arguments to pointers and raises on error codes.  Device vectors are torch
+float64 CUDA tensors of shape (n_nodes, 4, 2K+2), contiguous.  The library
+is loaded from this package directory; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtsgls.so")
+
+TSGLS_OK = 0
+TSGLS_NOT_CONVERGED = 1
+JAC = {"picard": 0, "picard_nols": 1, "newton": 2}
+ERRORS = {-1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "EMESH", -5: "ENONFINITE", -6: "ESTATE"}
+
+
+class Params(C.Structure):
+    _fields_ = [("rho", C.c_double), ("mu", C.c_double), ("omega", C.c_double), ("K", C.c_int),
+                ("C_I", C.c_double), ("backflow_beta", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("lin_rtol", C.c_double), ("restart", C.c_int),
+                ("max_newton", C.c_int), ("max_matvec", C.c_int), ("jacobian", C.c_int),
+                ("dt_pseudo", C.c_double), ("verbose", C.c_int)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("newton_iters", C.c_int), ("matvecs", C.c_int), ("status", C.c_int),
+                ("rel_residual", C.c_double), ("r0_norm", C.c_double), ("seconds", C.c_double),
+                ("history", C.c_double * 64)]
+
+
+class TsglsError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libtsgls.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise TsglsError(f"{LIB_PATH} not found: build it with "
+                             "`python -m paper_2311_09465_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        P, D, I64, I32 = C.c_void_p, C.c_double, C.c_int64, C.c_int
+        L.tsgls_supported_K.argtypes = [C.POINTER(C.c_int), I32]
+        L.tsgls_create.argtypes = [P, I64, P, I64, C.POINTER(Params), P, C.POINTER(P)]
+        L.tsgls_set_dirichlet.argtypes = [P, P, I64]
+        L.tsgls_set_neumann.argtypes = [P, P, I64, P]
+        L.tsgls_residual.argtypes = [P, P, P]
+        L.tsgls_linearize.argtypes = [P, P, P]
+        L.tsgls_jv.argtypes = [P, P, P, I32, D]
+        L.tsgls_jacobi_diag.argtypes = [P, P, D]
+        L.tsgls_get_tau.argtypes = [P, P]
+        L.tsgls_solve.argtypes = [P, P, C.POINTER(SolveOpts), C.POINTER(SolveStats)]
+        L.tsgls_info.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]
+        L.tsgls_last_error.argtypes = [P]
+        L.tsgls_last_error.restype = C.c_char_p
+        L.tsgls_destroy.argtypes = [P]
+        L.tsgls_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def supported_K():
+    buf = (C.c_int * 64)()
+    n = lib().tsgls_supported_K(buf, 64)
+    return [buf[i] for i in range(min(n, 64))]
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+class Solver:
+    """One mesh on the current GPU.  Mirrors the C ABI one call to one call."""
+
+    def __init__(self, xyz, tets, K, rho, mu, omega, C_I=3.0, backflow_beta=0.5, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise TsglsError("no GPU visible: the library runs on MI355X only")
+        self.K = int(K)
+        self.n_nodes = int(xyz.shape[0])
+        self.n_tets = int(tets.shape[0])
+        self.shape = (self.n_nodes, 4, 2 * self.K + 2)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        p = Params(rho, mu, omega, self.K, C_I, backflow_beta)
+        xa, xp = _host(xyz, np.float64)
+        ta, tp = _host(tets, np.int32)
+        h = C.c_void_p()
+        rc = lib().tsgls_create(xp, self.n_nodes, tp, self.n_tets, C.byref(p),
+                                C.c_void_p(self._stream.cuda_stream), C.byref(h))
+        self._h = h
+        if rc != TSGLS_OK:
+            msg = lib().tsgls_last_error(h).decode() if h.value else ""
+            if h.value:
+                lib().tsgls_destroy(h)
+            self._h = C.c_void_p()
+            raise TsglsError(f"tsgls_create: {ERRORS.get(rc, rc)}: {msg}")
+
+    @classmethod
+    def from_problem(cls, prob, **kw):
+        s = cls(prob.mesh.xyz, prob.mesh.tets, prob.K, prob.rho, prob.mu, prob.omega,
+                prob.C_I, prob.backflow_beta, **kw)
+        s.set_dirichlet(prob.dirichlet_nodes)
+        s.set_neumann(prob.neumann_tris, prob.neumann_h)
+        return s
+
+    def _check(self, rc, what):
+        if rc < 0:
+            raise TsglsError(f"{what}: {ERRORS.get(rc, rc)}: {lib().tsgls_last_error(self._h).decode()}")
+        return rc
+
+    def _vec(self, t, name):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                and t.is_contiguous() and tuple(t.shape) == self.shape):
+            raise TsglsError(f"{name} must be a contiguous float64 CUDA tensor of shape {self.shape}")
+        return _ptr(t)
+
+    def set_dirichlet(self, nodes):
+        a, p = _host(nodes, np.int32)
+        self._check(lib().tsgls_set_dirichlet(self._h, p, a.size), "set_dirichlet")
+
+    def set_neumann(self, tris, h=None):
+        a, p = _host(np.asarray(tris).reshape(-1, 3), np.int32)
+        hp = None
+        if h is not None:
+            ha, hp = _host(h, np.float64)
+        self._check(lib().tsgls_set_neumann(self._h, p, a.shape[0], hp), "set_neumann")
+
+    def residual(self, y, r):
+        self._check(lib().tsgls_residual(self._h, self._vec(y, "y"), self._vec(r, "r")), "residual")
+
+    def linearize(self, y, r=None):
+        rp = self._vec(r, "r") if r is not None else None
+        self._check(lib().tsgls_linearize(self._h, self._vec(y, "y"), rp), "linearize")
+
+    def jv(self, v, out, jacobian="picard", dt_pseudo=0.0):
+        self._check(lib().tsgls_jv(self._h, self._vec(v, "v"), self._vec(out, "Jv"),
+                                   JAC[jacobian], float(dt_pseudo or 0.0)), "jv")
+
+    def jacobi_diag(self, d, dt_pseudo=0.0):
+        self._check(lib().tsgls_jacobi_diag(self._h, self._vec(d, "d"), float(dt_pseudo or 0.0)),
+                    "jacobi_diag")
+
+    def get_tau(self):
+        n = 2 * self.K + 1
+        out = np.empty((self.n_tets, 4, n * (n + 1) // 2))
+        self._check(lib().tsgls_get_tau(self._h, out.ctypes.data_as(C.c_void_p)), "get_tau")
+        return out
+
+    def solve(self, y, rtol=1e-8, lin_rtol=0.05, restart=100, max_newton=50, max_matvec=10000,
+              jacobian="picard", dt_pseudo=0.0, verbose=False):
+        o = SolveOpts(rtol, lin_rtol, restart, max_newton, max_matvec, JAC[jacobian],
+                      float(dt_pseudo or 0.0), int(verbose))
+        st = SolveStats()
+        rc = self._check(lib().tsgls_solve(self._h, self._vec(y, "y"), C.byref(o), C.byref(st)), "solve")
+        return dict(status=rc, newton_iters=st.newton_iters, matvecs=st.matvecs,
+                    rel_residual=st.rel_residual, r0_norm=st.r0_norm, seconds=st.seconds,
+                    history=list(st.history[:min(64, st.newton_iters)]))
+
+    def info(self):
+        a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(lib().tsgls_info(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)), "info")
+        return dict(n_colors=a.value, n_tets=b.value, n_nodes=c.value, device_bytes=d.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().tsgls_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,224 @@
+// gfx950 kernels of the Neumann-face terms: backflow stabilization
+// -(rho beta / 2)(w, |A_n|_- u)_Gamma_h with |A_n|_- = (A_n - |A_n|)/2
+// (section "Stabilizing simulations in the presence of backflow") and the
+// traction term -(w, h n)_Gamma_h of eq. Rmc.  3-point degree-2 rule per face.
+#include "common.cuh"
+#include "internal.h"
+
+namespace tsgls {
+
+template <int K>
+struct FaceCfg {
+  static constexpr int n = Dim<K>::n, M = Dim<K>::M;
+  static constexpr int NP = np_of(n);
+  static constexpr int per_group = 2 * n * n + M;
+  static constexpr int G0 = 256 / NP;
+  static constexpr int Gmem = 32768 / (per_group * 8);
+  static constexpr int G = G0 < Gmem ? G0 : (Gmem < 1 ? 1 : Gmem);
+  static constexpr int BLOCK = G * NP < 64 ? 64 : G * NP;
+  static constexpr int GB = BLOCK / NP;
+};
+
+// One group of NP lanes per (face, face point).  A_n = A(u.n) in the
+// orthonormal basis; one-sided Jacobi on A_n + sigma I (sigma > ||A_n||, so
+// the shifted matrix is SPD) gives eigenpairs; lambda = ||w_c|| - sigma.
+template <int K>
+__global__ void __launch_bounds__(FaceCfg<K>::BLOCK)
+k_face_lin(DevView v, const double* __restrict__ UTs, double* __restrict__ aneg) {
+  using C = FaceCfg<K>;
+  constexpr int n = C::n, M = C::M, NP = C::NP, P = Dim<K>::P, GB = C::GB;
+  __shared__ double sUn[GB][M], sQ[GB][n * n], sL[GB][n];
+  const double* __restrict__ F = v.F;
+  const int g = threadIdx.x / NP, c = threadIdx.x % NP;
+  const int64_t gq = (int64_t)blockIdx.x * GB + g;
+  const int64_t f = gq / 3;
+  const int q = (int)(gq % 3);
+  const bool valid = f < v.n_faces;
+  if (valid) {
+    const double nx = v.fgeo[f * 4 + 0], ny = v.fgeo[f * 4 + 1], nz = v.fgeo[f * 4 + 2];
+    for (int s = c; s < M; s += NP) {
+      double un = 0.0;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const double* ut = UTs + (int64_t)v.fconn[f * 3 + b] * 3 * M + s;
+        un += flam(q, b) * (nx * ut[0] + ny * ut[M] + nz * ut[2 * M]);
+      }
+      sUn[g][s] = un;
+    }
+  }
+  __syncthreads();
+  double w[n];
+#pragma unroll
+  for (int a = 0; a < n; ++a) w[a] = 0.0;
+  if (valid && c < n) {
+    const double invM = 1.0 / M;
+#pragma unroll 1
+    for (int s = 0; s < M; ++s) {
+      const double t = sUn[g][s] * F[c * M + s] * invM;
+#pragma unroll
+      for (int a = 0; a < n; ++a) w[a] = fma(t, F[a * M + s], w[a]);
+    }
+  }
+  double cn = 0.0;
+#pragma unroll
+  for (int a = 0; a < n; ++a) cn = fma(w[a], w[a], cn);
+  const double sigma = 1.01 * sqrt(group_sum<NP>(cn)) + 1e-300;
+#pragma unroll
+  for (int a = 0; a < n; ++a)
+    if (a == c && valid) w[a] += sigma;
+  jacobi_columns<n, NP>(w, c);
+  double l2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < n; ++a) l2 = fma(w[a], w[a], l2);
+  const double nrm = sqrt(l2);
+  if (valid && c < n) {
+    const double lam = nrm - sigma;
+    sL[g][c] = lam < 0.0 ? lam : 0.0;
+#pragma unroll
+    for (int a = 0; a < n; ++a) sQ[g][c * n + a] = nrm > 0.0 ? w[a] / nrm : 0.0;
+  }
+  __syncthreads();
+  if (valid) {
+    double* out = aneg + (f * 3 + q) * P;
+    for (int p = c; p < P; p += NP) {
+      int r, cc;
+      packed_rc<n>(p, r, cc);
+      double acc = 0.0;
+      for (int k = 0; k < n; ++k) acc = fma(sL[g][k] * sQ[g][k * n + r], sQ[g][k * n + cc], acc);
+      out[p] = acc;
+    }
+  }
+}
+
+// Thread per (face, face node, velocity component); faces of one colour share
+// no node.  resid != 0: input is the state (unmasked) and the traction term is
+// included; otherwise the input is a direction (Dirichlet entries masked).
+template <int K>
+__global__ void k_face_apply(DevView v, const double* __restrict__ Y, int resid,
+                             const double* __restrict__ an, double* __restrict__ out,
+                             int64_t begin, int64_t end) {
+  constexpr int n = Dim<K>::n, S = Dim<K>::S, P = Dim<K>::P;
+  const int64_t idx = begin * 9 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= end * 9) return;
+  const int64_t f = idx / 9;
+  const int a = (int)((idx / 3) % 3), i = (int)(idx % 3);
+  const int64_t node = v.fconn[f * 3 + a];
+  if (v.nflag[node] & 1) return;
+  const double area = v.fgeo[f * 4 + 3];
+  double xb[3][n];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int64_t nb = v.fconn[f * 3 + b];
+    const bool z = !resid && (v.nflag[nb] & 1);
+#pragma unroll
+    for (int m = 0; m < n; ++m) xb[b][m] = z ? 0.0 : slot_x(Y + (nb * 4 + i) * S, m);
+  }
+  double o[n];
+#pragma unroll
+  for (int m = 0; m < n; ++m) o[m] = 0.0;
+  const double coef = -0.5 * v.rho * v.beta * area / 3.0;
+#pragma unroll 1
+  for (int q = 0; q < 3; ++q) {
+    double uq[n];
+#pragma unroll
+    for (int m = 0; m < n; ++m) uq[m] = flam(q, 0) * xb[0][m] + flam(q, 1) * xb[1][m] + flam(q, 2) * xb[2][m];
+    const double* tp = an + (f * 3 + q) * P;
+    const double lw = coef * flam(q, a);
+    int p = 0;
+#pragma unroll
+    for (int r = 0; r < n; ++r)
+#pragma unroll
+      for (int cc = r; cc < n; ++cc) {
+        const double t = lw * tp[p++];
+        o[r] = fma(t, uq[cc], o[r]);
+        if (cc != r) o[cc] = fma(t, uq[r], o[cc]);
+      }
+  }
+  if (resid && v.fh) {
+    const double ni = v.fgeo[f * 4 + i];
+#pragma unroll
+    for (int m = 0; m < n; ++m) o[m] -= area / 3.0 * v.fh[f * n + m] * ni;
+  }
+  double* op = out + (node * 4 + i) * S;
+  op[0] += o[0];
+#pragma unroll
+  for (int m = 1; m < n; ++m) op[m + 1] += o[m] * TS_RS2;
+}
+
+template <int K>
+__global__ void k_face_diag(DevView v, double* __restrict__ d, int64_t begin, int64_t end) {
+  constexpr int n = Dim<K>::n, S = Dim<K>::S, P = Dim<K>::P;
+  const int64_t idx = begin * 3 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= end * 3) return;
+  const int64_t f = idx / 3;
+  const int a = (int)(idx % 3);
+  const int64_t node = v.fconn[f * 3 + a];
+  const double area = v.fgeo[f * 4 + 3];
+  const double coef = -0.5 * v.rho * v.beta * area / 3.0;
+  double o[n];
+#pragma unroll
+  for (int m = 0; m < n; ++m) o[m] = 0.0;
+  for (int q = 0; q < 3; ++q) {
+    const double* tp = v.aneg + (f * 3 + q) * P;
+    const double l = flam(q, a);
+    int p = 0;
+#pragma unroll
+    for (int r = 0; r < n; ++r) {
+      o[r] += coef * l * l * tp[p];
+      p += n - r;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double* op = d + (node * 4 + i) * S;
+    op[0] += o[0];
+#pragma unroll
+    for (int m = 1; m < n; ++m) op[m + 1] += o[m];
+  }
+}
+
+#define TSGLS_FOR_EACH_K(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(11) X(15)
+
+hipError_t launch_face_lin(const DevView& v, const double* UTs, double* aneg, hipStream_t st) {
+  if (v.n_faces == 0) return hipSuccess;
+  switch (v.K) {
+#define CASE(k)                                                                        \
+  case k: {                                                                            \
+    const int64_t groups = v.n_faces * 3;                                              \
+    const unsigned grid = (unsigned)((groups + FaceCfg<k>::GB - 1) / FaceCfg<k>::GB);  \
+    k_face_lin<k><<<grid, FaceCfg<k>::BLOCK, 0, st>>>(v, UTs, aneg);                   \
+    break;                                                                             \
+  }
+    TSGLS_FOR_EACH_K(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_face_apply(const DevView& v, const double* Y, int resid, const double* an,
+                             double* out, int64_t begin, int64_t end, hipStream_t st) {
+  if (end <= begin) return hipSuccess;
+  const unsigned grid = (unsigned)(((end - begin) * 9 + 127) / 128);
+  switch (v.K) {
+#define CASE(k) case k: k_face_apply<k><<<grid, 128, 0, st>>>(v, Y, resid, an, out, begin, end); break;
+    TSGLS_FOR_EACH_K(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_face_diag(const DevView& v, double* d, int64_t begin, int64_t end, hipStream_t st) {
+  if (end <= begin) return hipSuccess;
+  const unsigned grid = (unsigned)(((end - begin) * 3 + 127) / 128);
+  switch (v.K) {
+#define CASE(k) case k: k_face_diag<k><<<grid, 128, 0, st>>>(v, d, begin, end); break;
+    TSGLS_FOR_EACH_K(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace tsgls

@@ -1,0 +1,622 @@
+// Host side of the library: context, mesh checks, element/face colouring,
+// the public C ABI (include/tsgls.h) and the Newton-GMRES driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tsgls.h"
+#include "internal.h"
+
+using namespace tsgls;
+
+struct tsgls_ctx {
+  tsgls_params p{};
+  hipStream_t st = nullptr;
+  int K = 0, n = 1, S = 2, M = 1, P = 1;
+  int64_t nn = 0, E = 0, nf = 0;
+  std::vector<int64_t> coff;    // colour offsets, elements
+  std::vector<int64_t> fcoff;   // colour offsets, faces
+  std::vector<int32_t> perm;    // sorted position -> input element index
+  std::vector<double> hxyz;     // host copy of the coordinates (face geometry)
+  int32_t* conn = nullptr;
+  double* geo = nullptr;
+  uint8_t* nflag = nullptr;
+  double* F = nullptr;
+  double* UT = nullptr;
+  double* VT = nullptr;
+  double* tau = nullptr;
+  double* Z = nullptr;
+  double* rs = nullptr;         // scratch residual for linearize
+  int32_t* fconn = nullptr;
+  double* fgeo = nullptr;
+  double* fh = nullptr;
+  double* aneg = nullptr;
+  // residual-only scratch (keeps the linearization intact)
+  double* UTr = nullptr;
+  double* taur = nullptr;
+  double* anegr = nullptr;
+  // Krylov workspace
+  int m_alloc = 0;
+  double* V = nullptr;
+  double* kx = nullptr;
+  double* kt = nullptr;
+  double* kt2 = nullptr;
+  double* minv = nullptr;
+  double* partial = nullptr;
+  double* dh = nullptr;
+  bool linearized = false;
+  size_t dev_bytes = 0;
+  std::vector<void*> allocs;
+  std::string err;
+};
+
+namespace {
+
+int fail(tsgls_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(ctx, TSGLS_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));         \
+  } while (0)
+
+#define CHK(call)                    \
+  do {                               \
+    int rc_ = (call);                \
+    if (rc_ != TSGLS_OK) return rc_; \
+  } while (0)
+
+template <class T>
+int dalloc(tsgls_ctx* c, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) return fail(c, TSGLS_ENOMEM, "hipMalloc(%zu bytes): %s", count * sizeof(T), hipGetErrorString(e));
+  c->allocs.push_back(q);
+  c->dev_bytes += count * sizeof(T);
+  *p = static_cast<T*>(q);
+  return TSGLS_OK;
+}
+
+void dfree(tsgls_ctx* c, void* p) {
+  if (!p) return;
+  auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+  if (it != c->allocs.end()) c->allocs.erase(it);
+  (void)hipFree(p);
+}
+
+// Greedy colouring in the given order: an item gets the lowest colour not
+// used by an already coloured item that shares a node.
+int colour(tsgls_ctx* c, const int32_t* items, int64_t count, int per, int64_t nn,
+           std::vector<int32_t>& col, int& ncol) {
+  constexpr int W = 8;  // up to 512 colours
+  std::vector<uint64_t> used((size_t)nn * W, 0);
+  col.assign(count, 0);
+  ncol = 0;
+  for (int64_t e = 0; e < count; ++e) {
+    uint64_t m[W] = {0};
+    for (int b = 0; b < per; ++b) {
+      const uint64_t* u = &used[(size_t)items[e * per + b] * W];
+      for (int w = 0; w < W; ++w) m[w] |= u[w];
+    }
+    int cidx = -1;
+    for (int w = 0; w < W && cidx < 0; ++w)
+      if (~m[w]) cidx = w * 64 + __builtin_ctzll(~m[w]);
+    if (cidx < 0) return fail(c, TSGLS_EMESH, "more than %d colours needed", W * 64);
+    col[e] = cidx;
+    ncol = std::max(ncol, cidx + 1);
+    for (int b = 0; b < per; ++b) used[(size_t)items[e * per + b] * W + cidx / 64] |= 1ull << (cidx % 64);
+  }
+  return TSGLS_OK;
+}
+
+DevView view(const tsgls_ctx* c) {
+  DevView v{};
+  v.K = c->K;
+  v.n_nodes = c->nn;
+  v.n_tets = c->E;
+  v.n_faces = c->nf;
+  v.conn = c->conn;
+  v.geo = c->geo;
+  v.nflag = c->nflag;
+  v.F = c->F;
+  v.UT = c->UT;
+  v.tau = c->tau;
+  v.Z = c->Z;
+  v.fconn = c->fconn;
+  v.fgeo = c->fgeo;
+  v.fh = c->fh;
+  v.aneg = c->aneg;
+  v.rho = c->p.rho;
+  v.mu = c->p.mu;
+  v.omega = c->p.omega;
+  v.C_I = c->p.C_I;
+  v.beta = c->p.backflow_beta;
+  return v;
+}
+
+int64_t ndof(const tsgls_ctx* c) { return c->nn * 4 * c->S; }
+
+// Volume + face terms of the operator; out must be zeroed by the caller.
+int apply_operator(tsgls_ctx* c, const DevView& v, int mode, const double* Y, const double* VTp,
+                   double* Zout, double* out, double shift, const double* an, int resid) {
+  for (size_t k = 0; k + 1 < c->coff.size(); ++k)
+    HIPCHK(c, launch_elem(v, mode, Y, VTp, Zout, out, shift, c->coff[k], c->coff[k + 1], c->st));
+  for (size_t k = 0; k + 1 < c->fcoff.size(); ++k)
+    HIPCHK(c, launch_face_apply(v, Y, resid, an, out, c->fcoff[k], c->fcoff[k + 1], c->st));
+  return TSGLS_OK;
+}
+
+int linearize_impl(tsgls_ctx* c, const double* y, double* r) {
+  DevView v = view(c);
+  HIPCHK(c, launch_prep_time(c->K, y, c->nflag, 0, c->F, c->UT, c->nn, c->st));
+  HIPCHK(c, launch_tau(v, y, c->tau, c->st));
+  HIPCHK(c, launch_face_lin(v, c->UT, c->aneg, c->st));
+  double* rr = r ? r : c->rs;
+  HIPCHK(c, launch_zero(rr, ndof(c), c->st));
+  CHK(apply_operator(c, v, MODE_RESID | MODE_STOREZ, y, nullptr, c->Z, rr, 0.0, c->aneg, 1));
+  c->linearized = true;
+  return TSGLS_OK;
+}
+
+int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt) {
+  if (!c->linearized) return fail(c, TSGLS_ESTATE, "jv before linearize");
+  DevView v = view(c);
+  const int mode = jac == TSGLS_JAC_PICARD ? 0 : jac == TSGLS_JAC_PICARD_NOLS ? MODE_NOLS : MODE_NEWTON;
+  const double shift = dt > 0 ? 1.5 * c->p.rho / dt : 0.0;
+  HIPCHK(c, launch_prep_time(c->K, x, c->nflag, 1, c->F, c->VT, c->nn, c->st));
+  HIPCHK(c, launch_zero(out, ndof(c), c->st));
+  return apply_operator(c, v, mode, x, c->VT, nullptr, out, shift, c->aneg, 0);
+}
+
+int diag_impl(tsgls_ctx* c, double* d, double dt) {
+  if (!c->linearized) return fail(c, TSGLS_ESTATE, "jacobi_diag before linearize");
+  DevView v = view(c);
+  const double shift = dt > 0 ? 1.5 * c->p.rho / dt : 0.0;
+  HIPCHK(c, launch_zero(d, ndof(c), c->st));
+  for (size_t k = 0; k + 1 < c->coff.size(); ++k)
+    HIPCHK(c, launch_diag(v, d, shift, c->coff[k], c->coff[k + 1], c->st));
+  for (size_t k = 0; k + 1 < c->fcoff.size(); ++k)
+    HIPCHK(c, launch_face_diag(v, d, c->fcoff[k], c->fcoff[k + 1], c->st));
+  HIPCHK(c, launch_diag_finish(c->K, c->nflag, d, c->nn, c->st));
+  return TSGLS_OK;
+}
+
+// Deterministic dot products of J vectors (rows of V, leading dim ld) with w;
+// result to the device array out and, if host != null, to host memory.
+int multidot(tsgls_ctx* c, const double* V, int64_t ld, int J, const double* w, double* out,
+             double* host) {
+  const int64_t n = ndof(c);
+  const int nb = multidot_blocks(n);
+  HIPCHK(c, launch_multidot(V, ld, J, w, c->partial, nb, n, c->st));
+  HIPCHK(c, launch_reduce_partials(c->partial, nb, J, out, c->st));
+  if (host) {
+    HIPCHK(c, hipMemcpyAsync(host, out, J * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+  }
+  return TSGLS_OK;
+}
+
+int norm2(tsgls_ctx* c, const double* x, double* nrm) {
+  double h = 0.0;
+  CHK(multidot(c, x, 0, 1, x, c->dh + 2048, &h));
+  *nrm = std::sqrt(h);
+  return TSGLS_OK;
+}
+
+int ensure_krylov(tsgls_ctx* c, int m) {
+  if (c->m_alloc >= m) return TSGLS_OK;
+  dfree(c, c->V);
+  c->V = nullptr;
+  const int64_t n = ndof(c);
+  CHK(dalloc(c, &c->V, (size_t)(m + 1) * n));
+  if (!c->kx) {
+    CHK(dalloc(c, &c->kx, n));
+    CHK(dalloc(c, &c->kt, n));
+    CHK(dalloc(c, &c->kt2, n));
+    CHK(dalloc(c, &c->minv, n));
+    CHK(dalloc(c, &c->partial, (size_t)multidot_blocks(n) * 1024));
+    CHK(dalloc(c, &c->dh, 4096));
+  }
+  c->m_alloc = m;
+  return TSGLS_OK;
+}
+
+// Right-Jacobi-preconditioned restarted GMRES with classical Gram-Schmidt and
+// one reorthogonalization pass; x = J^{-1} b approximately, x zeroed first.
+int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv, int jac,
+          double dt, int* mv_out) {
+  const int64_t n = ndof(c);
+  HIPCHK(c, launch_zero(x, n, c->st));
+  double bnorm;
+  CHK(norm2(c, b, &bnorm));
+  if (!std::isfinite(bnorm)) return fail(c, TSGLS_ENONFINITE, "non-finite right-hand side");
+  int mv = 0;
+  if (bnorm == 0.0) {
+    *mv_out = 0;
+    return TSGLS_OK;
+  }
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), h2(m + 1), yv(m);
+  bool first = true;
+  while (mv < maxmv) {
+    double* V0 = c->V;
+    if (first) {
+      HIPCHK(c, launch_copy(b, V0, n, c->st));
+    } else {
+      CHK(jv_impl(c, x, c->kt, jac, dt));
+      ++mv;
+      HIPCHK(c, launch_copy(b, V0, n, c->st));
+      HIPCHK(c, launch_axpy(-1.0, c->kt, V0, n, c->st));
+    }
+    first = false;
+    double beta;
+    CHK(norm2(c, V0, &beta));
+    if (!std::isfinite(beta)) return fail(c, TSGLS_ENONFINITE, "non-finite GMRES residual");
+    if (beta <= tol * bnorm) break;
+    HIPCHK(c, launch_scal_copy(1.0 / beta, V0, V0, n, c->st));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    bool done = false;
+    for (int j = 0; j < m && mv < maxmv; ++j) {
+      double* Vj = c->V + (int64_t)j * n;
+      double* Vn = c->V + (int64_t)(j + 1) * n;
+      HIPCHK(c, launch_mul(c->minv, Vj, c->kt, n, c->st));
+      CHK(jv_impl(c, c->kt, Vn, jac, dt));
+      ++mv;
+      CHK(multidot(c, c->V, n, j + 1, Vn, c->dh, h.data()));
+      HIPCHK(c, launch_multiaxpy(c->V, n, j + 1, c->dh, Vn, n, c->st));
+      CHK(multidot(c, c->V, n, j + 1, Vn, c->dh, h2.data()));
+      HIPCHK(c, launch_multiaxpy(c->V, n, j + 1, c->dh, Vn, n, c->st));
+      for (int i = 0; i <= j; ++i) h[i] += h2[i];
+      double hn;
+      CHK(norm2(c, Vn, &hn));
+      if (!std::isfinite(hn)) return fail(c, TSGLS_ENONFINITE, "non-finite Krylov vector");
+      if (hn > 0) HIPCHK(c, launch_scal_copy(1.0 / hn, Vn, Vn, n, c->st));
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+        h[i] = t;
+      }
+      const double den = std::hypot(h[j], hn);
+      cs[j] = den > 0 ? h[j] / den : 1.0;
+      sn[j] = den > 0 ? hn / den : 0.0;
+      h[j] = den;
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      k = j + 1;
+      if (std::fabs(g[j + 1]) <= tol * bnorm || hn == 0.0) {
+        done = true;
+        break;
+      }
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int l = i + 1; l < k; ++l) s -= H[(size_t)i * m + l] * yv[l];
+      yv[i] = s / H[(size_t)i * m + i];
+    }
+    HIPCHK(c, hipMemcpyAsync(c->dh + 1024, yv.data(), k * sizeof(double), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, launch_zero(c->kt, n, c->st));
+    HIPCHK(c, launch_multiaxpy_add(c->V, n, k, c->dh + 1024, c->kt, n, c->st));
+    HIPCHK(c, launch_mul(c->minv, c->kt, c->kt2, n, c->st));
+    HIPCHK(c, launch_axpy(1.0, c->kt2, x, n, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (done) break;
+  }
+  *mv_out = mv;
+  return TSGLS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsgls_supported_K(int* out, int cap) { return supported_K_list(out, cap); }
+
+int tsgls_create(const double* xyz, int64_t n_nodes, const int32_t* tets, int64_t n_tets,
+                 const tsgls_params* params, void* hip_stream, tsgls_ctx** out) {
+  if (!out) return TSGLS_EINVAL;
+  *out = nullptr;
+  if (!xyz || !tets || !params || n_nodes <= 0 || n_tets <= 0) return TSGLS_EINVAL;
+  tsgls_ctx* c = new (std::nothrow) tsgls_ctx();
+  if (!c) return TSGLS_ENOMEM;
+  *out = c;
+  c->p = *params;
+  c->st = (hipStream_t)hip_stream;
+  const int K = params->K;
+  if (!(params->rho > 0) || !(params->mu > 0) || !(params->C_I >= 0) || !(params->backflow_beta >= 0) ||
+      !(params->backflow_beta <= 1) || !std::isfinite(params->omega))
+    return fail(c, TSGLS_EINVAL, "invalid physical parameters");
+  if (K < 0 || !supported_K(K)) return fail(c, TSGLS_EINVAL, "K=%d is not compiled into this library", K);
+  c->K = K;
+  c->n = 2 * K + 1;
+  c->S = 2 * K + 2;
+  c->M = 3 * K + 1;
+  c->P = c->n * (c->n + 1) / 2;
+  c->nn = n_nodes;
+  c->E = n_tets;
+  c->hxyz.assign(xyz, xyz + n_nodes * 3);
+  // mesh checks
+  for (int64_t e = 0; e < n_tets; ++e) {
+    const int32_t* t = tets + e * 4;
+    for (int b = 0; b < 4; ++b)
+      if (t[b] < 0 || t[b] >= n_nodes) return fail(c, TSGLS_EMESH, "tet %lld has node index %d out of range", (long long)e, t[b]);
+    double d[3][3];
+    for (int k = 0; k < 3; ++k)
+      for (int i = 0; i < 3; ++i) d[k][i] = xyz[(int64_t)t[k + 1] * 3 + i] - xyz[(int64_t)t[0] * 3 + i];
+    const double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
+                       d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
+                       d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
+    if (!(det > 0)) return fail(c, TSGLS_EMESH, "tet %lld has non-positive volume", (long long)e);
+  }
+  std::vector<int32_t> col;
+  int ncol = 0;
+  CHK(colour(c, tets, n_tets, 4, n_nodes, col, ncol));
+  c->perm.resize(n_tets);
+  for (int64_t e = 0; e < n_tets; ++e) c->perm[e] = (int32_t)e;
+  std::stable_sort(c->perm.begin(), c->perm.end(), [&](int32_t a, int32_t b) { return col[a] < col[b]; });
+  c->coff.assign(ncol + 1, 0);
+  for (int64_t e = 0; e < n_tets; ++e) c->coff[col[e] + 1]++;
+  for (int k = 0; k < ncol; ++k) c->coff[k + 1] += c->coff[k];
+  std::vector<int32_t> sconn(n_tets * 4);
+  for (int64_t e = 0; e < n_tets; ++e)
+    for (int b = 0; b < 4; ++b) sconn[e * 4 + b] = tets[(int64_t)c->perm[e] * 4 + b];
+  // device data
+  double* dxyz = nullptr;
+  CHK(dalloc(c, &dxyz, n_nodes * 3));
+  CHK(dalloc(c, &c->conn, n_tets * 4));
+  CHK(dalloc(c, &c->geo, n_tets * 16));
+  CHK(dalloc(c, &c->nflag, n_nodes));
+  CHK(dalloc(c, &c->F, (size_t)c->n * c->M));
+  CHK(dalloc(c, &c->UT, n_nodes * 3 * c->M));
+  CHK(dalloc(c, &c->VT, n_nodes * 3 * c->M));
+  CHK(dalloc(c, &c->tau, (size_t)n_tets * 4 * c->P));
+  CHK(dalloc(c, &c->Z, (size_t)n_tets * 12 * c->n));
+  CHK(dalloc(c, &c->rs, n_nodes * 4 * c->S));
+  HIPCHK(c, hipMemcpyAsync(dxyz, xyz, n_nodes * 3 * sizeof(double), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->conn, sconn.data(), n_tets * 4 * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemsetAsync(c->nflag, 0, n_nodes, c->st));
+  std::vector<double> F((size_t)c->n * c->M);
+  const double pi = 3.14159265358979323846;
+  for (int s = 0; s < c->M; ++s) {
+    F[s] = 1.0;
+    for (int k = 1; k <= K; ++k) {
+      const double th = 2.0 * pi * k * s / c->M;
+      F[(size_t)(2 * k - 1) * c->M + s] = std::sqrt(2.0) * std::cos(th);
+      F[(size_t)(2 * k) * c->M + s] = -std::sqrt(2.0) * std::sin(th);
+    }
+  }
+  HIPCHK(c, hipMemcpyAsync(c->F, F.data(), F.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, launch_geometry(dxyz, c->conn, c->geo, nullptr, n_tets, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  dfree(c, dxyz);
+  c->dev_bytes -= n_nodes * 3 * sizeof(double);
+  c->fcoff.assign(1, 0);
+  return TSGLS_OK;
+}
+
+int tsgls_set_dirichlet(tsgls_ctx* c, const int32_t* nodes, int64_t n) {
+  if (!c || (n > 0 && !nodes) || n < 0) return fail(c, TSGLS_EINVAL, "bad Dirichlet arguments");
+  std::vector<uint8_t> fl(c->nn, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (nodes[i] < 0 || nodes[i] >= c->nn) return fail(c, TSGLS_EINVAL, "Dirichlet node %d out of range", nodes[i]);
+    fl[nodes[i]] = 1;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->nflag, fl.data(), c->nn, hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->linearized = false;
+  return TSGLS_OK;
+}
+
+int tsgls_set_neumann(tsgls_ctx* c, const int32_t* tris, int64_t nf, const double* h) {
+  if (!c) return TSGLS_EINVAL;
+  if (nf < 0 || (nf > 0 && !tris)) return fail(c, TSGLS_EINVAL, "bad Neumann arguments");
+  dfree(c, c->fconn);
+  dfree(c, c->fgeo);
+  dfree(c, c->fh);
+  dfree(c, c->aneg);
+  dfree(c, c->anegr);
+  c->fconn = nullptr;
+  c->fgeo = c->fh = c->aneg = c->anegr = nullptr;
+  c->nf = 0;
+  c->fcoff.assign(1, 0);
+  c->linearized = false;
+  if (nf == 0) return TSGLS_OK;
+  std::vector<double> fg(nf * 4);
+  for (int64_t f = 0; f < nf; ++f) {
+    const int32_t* t = tris + f * 3;
+    for (int b = 0; b < 3; ++b)
+      if (t[b] < 0 || t[b] >= c->nn) return fail(c, TSGLS_EMESH, "face %lld has node index out of range", (long long)f);
+    const double* x0 = &c->hxyz[(size_t)t[0] * 3];
+    const double* x1 = &c->hxyz[(size_t)t[1] * 3];
+    const double* x2 = &c->hxyz[(size_t)t[2] * 3];
+    double a[3], b[3], nv[3];
+    for (int i = 0; i < 3; ++i) {
+      a[i] = x1[i] - x0[i];
+      b[i] = x2[i] - x0[i];
+    }
+    nv[0] = a[1] * b[2] - a[2] * b[1];
+    nv[1] = a[2] * b[0] - a[0] * b[2];
+    nv[2] = a[0] * b[1] - a[1] * b[0];
+    const double nn = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+    if (!(nn > 0)) return fail(c, TSGLS_EMESH, "face %lld is degenerate", (long long)f);
+    for (int i = 0; i < 3; ++i) fg[f * 4 + i] = nv[i] / nn;
+    fg[f * 4 + 3] = 0.5 * nn;
+  }
+  std::vector<int32_t> col;
+  int ncol = 0;
+  CHK(colour(c, tris, nf, 3, c->nn, col, ncol));
+  std::vector<int32_t> perm(nf);
+  for (int64_t f = 0; f < nf; ++f) perm[f] = (int32_t)f;
+  std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return col[a] < col[b]; });
+  c->fcoff.assign(ncol + 1, 0);
+  for (int64_t f = 0; f < nf; ++f) c->fcoff[col[f] + 1]++;
+  for (int k = 0; k < ncol; ++k) c->fcoff[k + 1] += c->fcoff[k];
+  std::vector<int32_t> sc(nf * 3);
+  std::vector<double> sg(nf * 4), sh;
+  for (int64_t f = 0; f < nf; ++f) {
+    for (int b = 0; b < 3; ++b) sc[f * 3 + b] = tris[(int64_t)perm[f] * 3 + b];
+    for (int i = 0; i < 4; ++i) sg[f * 4 + i] = fg[(int64_t)perm[f] * 4 + i];
+  }
+  CHK(dalloc(c, &c->fconn, nf * 3));
+  CHK(dalloc(c, &c->fgeo, nf * 4));
+  CHK(dalloc(c, &c->aneg, (size_t)nf * 3 * c->P));
+  HIPCHK(c, hipMemcpyAsync(c->fconn, sc.data(), sc.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->fgeo, sg.data(), sg.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+  if (h) {
+    // slots -> orthonormal coordinates (x_0 = slot 0, x_a = sqrt2 slot a+1)
+    sh.assign(nf * c->n, 0.0);
+    for (int64_t f = 0; f < nf; ++f) {
+      const double* hs = h + (int64_t)perm[f] * c->S;
+      sh[f * c->n] = hs[0];
+      for (int a = 1; a < c->n; ++a) sh[f * c->n + a] = std::sqrt(2.0) * hs[a + 1];
+    }
+    CHK(dalloc(c, &c->fh, sh.size()));
+    HIPCHK(c, hipMemcpyAsync(c->fh, sh.data(), sh.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->nf = nf;
+  return TSGLS_OK;
+}
+
+int tsgls_residual(tsgls_ctx* c, const double* y, double* r) {
+  if (!c) return TSGLS_EINVAL;
+  if (!y || !r) return fail(c, TSGLS_EINVAL, "null vector");
+  if (!c->UTr) {
+    CHK(dalloc(c, &c->UTr, c->nn * 3 * c->M));
+    CHK(dalloc(c, &c->taur, (size_t)c->E * 4 * c->P));
+  }
+  if (c->nf && !c->anegr) CHK(dalloc(c, &c->anegr, (size_t)c->nf * 3 * c->P));
+  DevView v = view(c);
+  v.UT = c->UTr;
+  v.tau = c->taur;
+  v.aneg = c->anegr;
+  HIPCHK(c, launch_prep_time(c->K, y, c->nflag, 0, c->F, c->UTr, c->nn, c->st));
+  HIPCHK(c, launch_tau(v, y, c->taur, c->st));
+  HIPCHK(c, launch_face_lin(v, c->UTr, c->anegr, c->st));
+  HIPCHK(c, launch_zero(r, ndof(c), c->st));
+  return apply_operator(c, v, MODE_RESID, y, nullptr, nullptr, r, 0.0, c->anegr, 1);
+}
+
+int tsgls_linearize(tsgls_ctx* c, const double* y, double* r) {
+  if (!c) return TSGLS_EINVAL;
+  if (!y) return fail(c, TSGLS_EINVAL, "null vector");
+  return linearize_impl(c, y, r);
+}
+
+int tsgls_jv(tsgls_ctx* c, const double* v, double* Jv, int jacobian, double dt_pseudo) {
+  if (!c) return TSGLS_EINVAL;
+  if (!v || !Jv || v == Jv) return fail(c, TSGLS_EINVAL, "bad vectors");
+  if (jacobian < 0 || jacobian > 2) return fail(c, TSGLS_EINVAL, "bad tangent variant %d", jacobian);
+  return jv_impl(c, v, Jv, jacobian, dt_pseudo);
+}
+
+int tsgls_jacobi_diag(tsgls_ctx* c, double* d, double dt_pseudo) {
+  if (!c) return TSGLS_EINVAL;
+  if (!d) return fail(c, TSGLS_EINVAL, "null vector");
+  return diag_impl(c, d, dt_pseudo);
+}
+
+int tsgls_get_tau(tsgls_ctx* c, double* tau_out) {
+  if (!c) return TSGLS_EINVAL;
+  if (!tau_out) return fail(c, TSGLS_EINVAL, "null pointer");
+  if (!c->linearized) return fail(c, TSGLS_ESTATE, "get_tau before linearize");
+  const size_t per = (size_t)4 * c->P;
+  std::vector<double> buf((size_t)c->E * per);
+  HIPCHK(c, hipMemcpyAsync(buf.data(), c->tau, buf.size() * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  for (int64_t e = 0; e < c->E; ++e)
+    std::memcpy(tau_out + (size_t)c->perm[e] * per, buf.data() + (size_t)e * per, per * sizeof(double));
+  return TSGLS_OK;
+}
+
+int tsgls_solve(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_stats* stats) {
+  if (!c) return TSGLS_EINVAL;
+  if (!y || !o) return fail(c, TSGLS_EINVAL, "null argument");
+  if (o->restart < 1 || o->restart > 1000 || o->max_newton < 0 || o->max_matvec < 1 || !(o->rtol > 0) ||
+      !(o->lin_rtol > 0) || o->jacobian < 0 || o->jacobian > 2)
+    return fail(c, TSGLS_EINVAL, "bad solve options");
+  const auto t0 = std::chrono::steady_clock::now();
+  tsgls_solve_stats st{};
+  CHK(ensure_krylov(c, o->restart));
+  const int64_t n = ndof(c);
+  double* r = c->rs;
+  CHK(linearize_impl(c, y, r));
+  double r0;
+  CHK(norm2(c, r, &r0));
+  if (!std::isfinite(r0)) return fail(c, TSGLS_ENONFINITE, "non-finite initial residual");
+  st.r0_norm = r0;
+  double rn = r0;
+  int it = 0;
+  int status = TSGLS_NOT_CONVERGED;
+  for (;;) {
+    const double rel = r0 > 0 ? rn / r0 : 0.0;
+    st.rel_residual = rel;
+    if (it > 0 && it <= 64) st.history[it - 1] = rel;
+    if (rel <= o->rtol || r0 == 0.0) {
+      status = TSGLS_OK;
+      break;
+    }
+    if (it >= o->max_newton) break;
+    CHK(diag_impl(c, c->minv, o->dt_pseudo));
+    HIPCHK(c, launch_recip(c->minv, n, c->st));
+    // b = -r in kt2 is overwritten inside gmres; keep it in the last Krylov slot-free buffer
+    HIPCHK(c, launch_scal_copy(-1.0, r, r, n, c->st));
+    int mv = 0;
+    CHK(gmres(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, o->dt_pseudo, &mv));
+    st.matvecs += mv;
+    HIPCHK(c, launch_axpy(1.0, c->kx, y, n, c->st));
+    CHK(linearize_impl(c, y, r));
+    CHK(norm2(c, r, &rn));
+    if (!std::isfinite(rn)) return fail(c, TSGLS_ENONFINITE, "non-finite residual at Newton step %d", it + 1);
+    ++it;
+    if (o->verbose) fprintf(stderr, "tsgls newton %d: |r|/|r0| = %.3e  gmres %d\n", it, rn / r0, mv);
+  }
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  st.newton_iters = it;
+  st.status = status;
+  st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = st;
+  return status;
+}
+
+int tsgls_info(const tsgls_ctx* c, int64_t* n_colors, int64_t* n_tets, int64_t* n_nodes,
+               int64_t* device_bytes) {
+  if (!c) return TSGLS_EINVAL;
+  if (n_colors) *n_colors = (int64_t)c->coff.size() - 1;
+  if (n_tets) *n_tets = c->E;
+  if (n_nodes) *n_nodes = c->nn;
+  if (device_bytes) *device_bytes = (int64_t)c->dev_bytes;
+  return TSGLS_OK;
+}
+
+const char* tsgls_last_error(const tsgls_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void tsgls_destroy(tsgls_ctx* c) {
+  if (!c) return;
+  if (c->st) (void)hipStreamSynchronize(c->st);
+  else (void)hipDeviceSynchronize();
+  for (void* p : c->allocs) (void)hipFree(p);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal interface between the host library (host.cpp) and the gfx950
+// kernels (elem.hip, face.hip, krylov.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tsgls {
+
+// Element-operator modes (compile-time flags of the element kernel).
+enum : int {
+  MODE_RESID = 1,    // input is the state: A built from it, no input mask
+  MODE_NEWTON = 2,   // keep the derivative of A (needs frozen tau L(u))
+  MODE_NOLS = 4,     // drop least-squares terms of G_i and D_i
+  MODE_STOREZ = 8,   // store z = tau L(u) (modal) during a residual pass
+};
+
+// Device view of one mesh + linearization.  All pointers are device memory.
+struct DevView {
+  int K;
+  int64_t n_nodes, n_tets, n_faces;
+  const int32_t* conn;       // [E][4] element nodes, colour-sorted order
+  const double* geo;         // [E][16]: grad N (a-major, 12), w = V/4, pad
+  const uint8_t* nflag;      // [n_nodes] bit0: velocity Dirichlet
+  const double* F;           // [n][M] phi_a(t_s), real orthonormal basis
+  const double* UT;          // [n_nodes][3][M] frozen velocity samples
+  const double* tau;         // [E][4][P] packed tau (colour-sorted order)
+  const double* Z;           // [E][4][3][n] tau L(u) modal (Newton tangent)
+  const int32_t* fconn;      // [nf][3] Neumann faces, colour-sorted
+  const double* fgeo;        // [nf][4] unit outward normal, area
+  const double* fh;          // [nf][n] traction modes (real basis) or null
+  const double* aneg;        // [nf][3][P] |A_n|_- packed per face point
+  double rho, mu, omega, C_I, beta;
+};
+
+// Launchers (return hipError_t of the launch).  Colour ranges are
+// [begin, end) in the colour-sorted element / face order.
+hipError_t launch_geometry(const double* xyz, const int32_t* conn, double* geo,
+                           int* bad, int64_t n_tets, hipStream_t st);
+hipError_t launch_prep_time(int K, const double* Y, const uint8_t* nflag,
+                            int masked, const double* F, double* XT,
+                            int64_t n_nodes, hipStream_t st);
+hipError_t launch_tau(const DevView& v, const double* Y, double* tau,
+                      hipStream_t st);
+hipError_t launch_elem(const DevView& v, int mode, const double* Y,
+                       const double* VT, double* Zout, double* out,
+                       double shift, int64_t begin, int64_t end,
+                       hipStream_t st);
+hipError_t launch_diag(const DevView& v, double* d, double shift,
+                       int64_t begin, int64_t end, hipStream_t st);
+hipError_t launch_face_lin(const DevView& v, const double* Y, double* aneg,
+                           hipStream_t st);
+hipError_t launch_face_apply(const DevView& v, const double* Y, int resid,
+                             const double* aneg, double* out, int64_t begin,
+                             int64_t end, hipStream_t st);
+hipError_t launch_face_diag(const DevView& v, double* d, int64_t begin,
+                            int64_t end, hipStream_t st);
+hipError_t launch_diag_finish(int K, const uint8_t* nflag, double* d,
+                              int64_t n_nodes, hipStream_t st);
+bool supported_K(int K);
+int supported_K_list(int* out, int cap);
+
+// BLAS-1 style kernels on float64 vectors of length n.
+hipError_t launch_zero(double* x, int64_t n, hipStream_t st);
+hipError_t launch_copy(const double* x, double* y, int64_t n, hipStream_t st);
+hipError_t launch_axpy(double a, const double* x, double* y, int64_t n, hipStream_t st);
+hipError_t launch_scal_copy(double a, const double* x, double* y, int64_t n, hipStream_t st);
+hipError_t launch_mul(const double* a, const double* x, double* y, int64_t n, hipStream_t st);
+hipError_t launch_recip(double* x, int64_t n, hipStream_t st);
+// partial[b*J + j] = sum over block b's chunk of V[j]*w; J <= 128.
+hipError_t launch_multidot(const double* V, int64_t ldv, int J, const double* w,
+                           double* partial, int nblocks, int64_t n, hipStream_t st);
+// out[j] = sum_b partial[b*J + j] (fixed order)
+hipError_t launch_reduce_partials(const double* partial, int nblocks, int J,
+                                  double* out, hipStream_t st);
+// w -= sum_j V[j] h[j]
+hipError_t launch_multiaxpy(const double* V, int64_t ldv, int J, const double* h,
+                            double* w, int64_t n, hipStream_t st);
+// y += sum_j V[j] c[j]  (c on device)
+hipError_t launch_multiaxpy_add(const double* V, int64_t ldv, int J, const double* c,
+                                double* y, int64_t n, hipStream_t st);
+int multidot_blocks(int64_t n);
+
+}  // namespace tsgls

@@ -1,0 +1,156 @@
+// gfx950 BLAS-1 kernels for the Krylov solver (FP64).  Dot products are
+// reduced in two deterministic stages: fixed per-block partial sums, then a
+// fixed-order sum over blocks, so results are bitwise reproducible.
+#include "internal.h"
+
+namespace tsgls {
+
+static inline unsigned grid_for(int64_t n, int bs) {
+  int64_t g = (n + bs - 1) / bs;
+  if (g > 65535LL * 32) g = 65535LL * 32;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+__global__ void k_zero(double* x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] = 0.0;
+}
+__global__ void k_copy(const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = x[i];
+}
+__global__ void k_axpy(double a, const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = fma(a, x[i], y[i]);
+}
+__global__ void k_scal_copy(double a, const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = a * x[i];
+}
+__global__ void k_mul(const double* __restrict__ a, const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = a[i] * x[i];
+}
+__global__ void k_recip(double* x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] = 1.0 / x[i];
+}
+
+hipError_t launch_zero(double* x, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_zero<<<grid_for(n, 256), 256, 0, st>>>(x, n);
+  return hipGetLastError();
+}
+hipError_t launch_copy(const double* x, double* y, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_copy<<<grid_for(n, 256), 256, 0, st>>>(x, y, n);
+  return hipGetLastError();
+}
+hipError_t launch_axpy(double a, const double* x, double* y, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_axpy<<<grid_for(n, 256), 256, 0, st>>>(a, x, y, n);
+  return hipGetLastError();
+}
+hipError_t launch_scal_copy(double a, const double* x, double* y, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_scal_copy<<<grid_for(n, 256), 256, 0, st>>>(a, x, y, n);
+  return hipGetLastError();
+}
+hipError_t launch_mul(const double* a, const double* x, double* y, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_mul<<<grid_for(n, 256), 256, 0, st>>>(a, x, y, n);
+  return hipGetLastError();
+}
+hipError_t launch_recip(double* x, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_recip<<<grid_for(n, 256), 256, 0, st>>>(x, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- multi-dot
+// Block b owns the contiguous chunk [b*chunk, min(n, (b+1)*chunk)); for a
+// tile of up to 8 vectors each thread accumulates strided products, then the
+// block reduces in LDS in a fixed tree order.
+constexpr int MD_BS = 256;
+constexpr int MD_TILE = 8;
+
+__global__ void __launch_bounds__(MD_BS)
+k_multidot(const double* __restrict__ V, int64_t ldv, int J, const double* __restrict__ w,
+           double* __restrict__ partial, int64_t n, int64_t chunk) {
+  __shared__ double red[MD_TILE][MD_BS];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int64_t lo = (int64_t)b * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  for (int j0 = 0; j0 < J; j0 += MD_TILE) {
+    double acc[MD_TILE];
+#pragma unroll
+    for (int k = 0; k < MD_TILE; ++k) acc[k] = 0.0;
+    for (int64_t i = lo + t; i < hi; i += MD_BS) {
+      const double wi = w[i];
+#pragma unroll
+      for (int k = 0; k < MD_TILE; ++k)
+        if (j0 + k < J) acc[k] = fma(V[(int64_t)(j0 + k) * ldv + i], wi, acc[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < MD_TILE; ++k) red[k][t] = acc[k];
+    __syncthreads();
+    for (int s = MD_BS / 2; s > 0; s >>= 1) {
+      if (t < s) {
+#pragma unroll
+        for (int k = 0; k < MD_TILE; ++k) red[k][t] += red[k][t + s];
+      }
+      __syncthreads();
+    }
+    if (t < MD_TILE && j0 + t < J) partial[(int64_t)b * J + j0 + t] = red[t][0];
+    __syncthreads();
+  }
+}
+
+int multidot_blocks(int64_t n) {
+  int64_t b = (n + 4095) / 4096;
+  if (b > 1024) b = 1024;
+  return (int)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_multidot(const double* V, int64_t ldv, int J, const double* w, double* partial,
+                           int nblocks, int64_t n, hipStream_t st) {
+  const int64_t chunk = (n + nblocks - 1) / nblocks;
+  k_multidot<<<nblocks, MD_BS, 0, st>>>(V, ldv, J, w, partial, n, chunk);
+  return hipGetLastError();
+}
+
+__global__ void k_reduce_partials(const double* __restrict__ partial, int nb, int J, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= J) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * J + j];
+  out[j] = s;
+}
+
+hipError_t launch_reduce_partials(const double* partial, int nblocks, int J, double* out, hipStream_t st) {
+  k_reduce_partials<<<(J + 127) / 128, 128, 0, st>>>(partial, nblocks, J, out);
+  return hipGetLastError();
+}
+
+// w -= sum_j V[j] h[j]   (h on device, J <= 1024)
+__global__ void k_multiaxpy(const double* __restrict__ V, int64_t ldv, int J, const double* __restrict__ h,
+                            double* __restrict__ w, int64_t n, double sign) {
+  __shared__ double sh[1024];
+  for (int j = threadIdx.x; j < J; j += blockDim.x) sh[j] = h[j];
+  __syncthreads();
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j < J; ++j) acc = fma(V[(int64_t)j * ldv + i], sh[j], acc);
+    w[i] = fma(sign, acc, w[i]);
+  }
+}
+
+hipError_t launch_multiaxpy(const double* V, int64_t ldv, int J, const double* h, double* w, int64_t n,
+                            hipStream_t st) {
+  if (n == 0 || J == 0) return hipSuccess;
+  k_multiaxpy<<<grid_for(n, 256), 256, 0, st>>>(V, ldv, J, h, w, n, -1.0);
+  return hipGetLastError();
+}
+
+hipError_t launch_multiaxpy_add(const double* V, int64_t ldv, int J, const double* c, double* y, int64_t n,
+                                hipStream_t st) {
+  if (n == 0 || J == 0) return hipSuccess;
+  k_multiaxpy<<<grid_for(n, 256), 256, 0, st>>>(V, ldv, J, c, y, n, 1.0);
+  return hipGetLastError();
+}
+
+}  // namespace tsgls
