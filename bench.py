@@ -1,0 +1,209 @@
+"""Benchmark of the time-spectral GLS hot path on one MI355X.
+
+Workload (default): synthetic Fontan-like cross junction, ~1M P1 tets,
+K = 6 harmonics (the paper's 7 modes), Re = 500, Wo = 10, seeded k^-2 inflow
+waveforms, zero-traction outlets with backflow stabilization, FP64.
+
+One step = one Newton iteration of the whole hot path through the C ABI:
+linearize (nodal time samples, tau eigen-solves at every quadrature point,
+residual), Jacobi diagonal, one GMRES cycle of a fixed number of tangent
+products with Gram-Schmidt, update.  `value` counts the tangent products'
+degree-of-freedom-modes processed per second of the whole step:
+steps * jv_per_step * n_nodes * 4 * (2K+1) / seconds / 1e9.
+
+Also reported: the element kernel's roofline position (FP64 ALU bound) from
+per-launch HIP events recorded inside the library over the timed region, the
+pure tangent-product rate, and the oracle timed on a bounded sample of the
+same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Jv GDOF-modes/s; time-to-1e-8 residual, plain FP64 vs mixed/learned/batched"
+FP64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def jv_flops_per_element(K: int, variant: str = "picard") -> float:
+    """Algorithmic FP64 flops of one tangent product per element: the DFT
+    rows of the sampled products (2nM each; 81 rows per element for the
+    Picard tangent, 114 for the Newton one), the packed tau apply (24 n^2)
+    and the modal element algebra (~300 n)."""
+    n, M = 2 * K + 1, 3 * K + 1
+    R = 81 if variant != "newton" else 114
+    return 2.0 * n * M * R + 24.0 * n * n + 300.0 * n
+
+
+def jv_bytes(K: int, E: int, nn: int, variant: str = "picard") -> float:
+    """Algorithmic HBM bytes of one tangent product: packed FP64 tau (4 points
+    x n(n+1)/2), element connectivity + geometry (4 i32 + 13 f64), and per node
+    the direction in, the frozen state and the product out."""
+    n = 2 * K + 1
+    P = n * (n + 1) // 2
+    b = E * (32.0 * P + 120.0) + nn * 8.0 * (4 * n + 3 * n + 4 * n)
+    if variant == "newton":
+        b += E * 96.0 * n
+    return b
+
+
+def _workload(name):
+    from workloads import junction_problem, womersley_problem
+    if name == "junction_1M_K6":
+        return junction_problem(h=0.048, K=6, Re=500.0, Wo=10.0, seed=0), dict(
+            workload="junction_1M_K6", geometry="cross junction: inlets r=0.8 (-z), 0.6 (+z); "
+            "outlets r=0.5 (+-x); arms 4", h=0.048, K=6, Re=500.0, Wo=10.0, seed=0)
+    if name == "womersley_6k_K3":
+        return womersley_problem(4, 16, K=3), dict(
+            workload="womersley_6k_K3", geometry="pipe R=1 L=4", K=3, Re=100.0, Wo=5.0)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(prob, jv_per_step, n_sample=3000):
+    """Oracle Newton-step work (linearize + Jacobi diagonal + jv_per_step
+    tangent products) on the first n_sample elements (Morton order, so a
+    contiguous patch), scaled to the full mesh."""
+    import numpy as np
+    import oracle as O
+    tets = prob.mesh.tets[:n_sample]
+    used = np.unique(tets)
+    remap = -np.ones(prob.mesh.n_nodes, dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    xyz = prob.mesh.xyz[used]
+    t = remap[tets].astype(np.int32)
+    dn = remap[prob.dirichlet_nodes]
+    par = O.Params(K=prob.K, rho=prob.rho, mu=prob.mu, omega=prob.omega, C_I=prob.C_I,
+                   backflow_beta=prob.backflow_beta, dirichlet_nodes=dn[dn >= 0],
+                   neumann_tris=np.zeros((0, 3), np.int32))
+    rng = np.random.default_rng(0)
+    y = rng.standard_normal((used.size, 4, 2 * prob.K + 2)) * 0.1
+    v = rng.standard_normal(y.shape)
+    c0 = time.process_time()
+    w0 = time.perf_counter()
+    lin = O.linearize(par, xyz, t, y)
+    O.jacobian_diagonal(par, xyz, t, lin)
+    for _ in range(jv_per_step):
+        O.jv(par, xyz, t, lin, v, "picard")
+    wall = time.perf_counter() - w0
+    cpu = time.process_time() - c0
+    scale = prob.mesh.n_tets / n_sample
+    step_s = wall * scale
+    dof = prob.mesh.n_nodes * 4 * (2 * prob.K + 1)
+    return dict(value=jv_per_step * dof / step_s / 1e9, unit="GDOF-modes/s",
+                cores=max(1, int(round(cpu / wall))), kind="oracle",
+                sample=f"oracle Newton-step work (linearize, Jacobi diagonal, {jv_per_step} Picard "
+                       f"tangent products) on {n_sample} of {prob.mesh.n_tets} elements, "
+                       f"{wall:.1f} s wall, scaled by {scale:.0f}x to the full mesh",
+                seconds=wall)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="junction_1M_K6")
+    ap.add_argument("--jv-per-step", type=int, default=30)
+    ap.add_argument("--jacobian", default="picard")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it "
+                          "(mesh-partition sharding is described in the design notes)",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2311_09465_amd as T
+    from workloads import initial_guess
+
+    torch.cuda.set_device(0)
+    prob, cfg = _workload(args.workload)
+    s = T.Solver.from_problem(prob)
+    info = s.info()
+    K, E, nn = prob.K, prob.mesh.n_tets, prob.mesh.n_nodes
+    dof = nn * 4 * (2 * K + 1)
+    y = torch.from_numpy(initial_guess(prob)).cuda()
+    m = args.jv_per_step
+    step_kw = dict(rtol=1e-300, lin_rtol=1e-300, restart=m, max_matvec=m, jacobian=args.jacobian)
+    if args.warmup > 0:
+        s.solve(y, max_newton=args.warmup, **step_kw)
+    torch.cuda.synchronize()
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = s.solve(y, max_newton=args.steps, **step_kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {k: s.profile_get(k) for k in s.PROF}
+    s.profile(False)
+    secs = t1 - t0
+    value = args.steps * m * dof / secs / 1e9
+
+    # dominant kernel: the element kernel of the tangent products
+    launches, tot_ms = prof["elem_tangent"]
+    avg_launch_s = tot_ms / max(launches, 1) / 1e3
+    elems_per_launch = E / info["n_colors"]
+    fl = jv_flops_per_element(K, args.jacobian) * elems_per_launch
+    achieved = fl / avg_launch_s / 1e12
+    roofline = dict(bound="alu", achieved=round(achieved, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=None,
+                    kernel="k_elem (tangent product, one launch per colour)",
+                    avg_launch_us=round(avg_launch_s * 1e6, 2), launches=launches,
+                    elements_per_launch=round(elems_per_launch, 1),
+                    flops_per_element=jv_flops_per_element(K, args.jacobian),
+                    hbm_gbs_equiv=round(jv_bytes(K, E, nn, args.jacobian) / info["n_colors"]
+                                        / avg_launch_s / 1e9, 1))
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "GDOF-modes/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(secs / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded junction mesh and inflow waveforms)",
+        "config": dict(cfg, n_tets=E, n_nodes=nn, jv_per_step=m, tangent=args.jacobian,
+                       n_colors=info["n_colors"]),
+        "roofline": roofline,
+        "breakdown_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in prof.items()},
+        "newton_rel_residual_after": st["rel_residual"],
+    }
+    if not args.no_extras:
+        # pure tangent-product rate, back to back at the current linearization
+        v = torch.randn_like(y)
+        o = torch.zeros_like(y)
+        s.jv(v, o, args.jacobian)
+        torch.cuda.synchronize()
+        reps = 20
+        a = time.perf_counter()
+        for _ in range(reps):
+            s.jv(v, o, args.jacobian)
+        torch.cuda.synchronize()
+        jv_ms = (time.perf_counter() - a) / reps * 1e3
+        out["jv_ms"] = round(jv_ms, 3)
+        out["jv_only_gdof_modes_s"] = round(dof / jv_ms / 1e6, 4)
+        # time to 1e-8 on the small Womersley case (full solve, FP64, Picard)
+        del s
+        torch.cuda.empty_cache()
+        pw, _ = _workload("womersley_6k_K3")
+        sw = T.Solver.from_problem(pw)
+        yw = torch.from_numpy(initial_guess(pw)).cuda()
+        stw = sw.solve(yw, rtol=1e-8, lin_rtol=0.05, restart=100, max_newton=60)
+        out["time_to_1e8_womersley_6k_K3_s"] = round(stw["seconds"], 4)
+        out["time_to_1e8_womersley_6k_K3_newton_iters"] = stw["newton_iters"]
+        out["time_to_1e8_womersley_6k_K3_matvecs"] = stw["matvecs"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, m)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -111,8 +111,9 @@ int tsgls_supported_K(int* out, int cap);
 
 /* Create a context for one mesh.  xyz: host [n_nodes][3]; tets: host
  * [n_tets][4] 0-based, positively oriented (TSGLS_EMESH otherwise).  The
- * library colours the elements (no two elements of a colour share a node)
- * and computes the element geometry on the device. */
+ * library orders the elements along a Morton curve, builds the node ->
+ * element incidence used to sum element contributions deterministically, and
+ * computes the element geometry on the device. */
 int tsgls_create(const double* xyz, int64_t n_nodes, const int32_t* tets,
                  int64_t n_tets, const tsgls_params* params, void* hip_stream,
                  tsgls_ctx** out);
@@ -156,9 +157,25 @@ int tsgls_get_tau(tsgls_ctx* ctx, double* tau_out);
 int tsgls_solve(tsgls_ctx* ctx, double* y, const tsgls_solve_opts* opts,
                 tsgls_solve_stats* stats);
 
-/* Introspection: n_colors, element and node counts, bytes held on device. */
+/* Introspection: element launches per operator application (1), element and
+ * node counts, bytes held on device. */
 int tsgls_info(const tsgls_ctx* ctx, int64_t* n_colors, int64_t* n_tets,
                int64_t* n_nodes, int64_t* device_bytes);
+
+/* Per-launch timing with HIP events on the context stream, for benchmarks.
+ * tsgls_profile(ctx, 1) clears the records and starts recording an event
+ * pair around every launch of the kernels below; tsgls_profile(ctx, 0)
+ * stops.  tsgls_profile_get synchronizes the stream and returns, for one
+ * kernel class, the number of recorded launches and their summed duration. */
+#define TSGLS_PROF_ELEM_TANGENT 0   /* element kernel in jv (one launch per product) */
+#define TSGLS_PROF_ELEM_RESIDUAL 1  /* element kernel in residual / linearize */
+#define TSGLS_PROF_TAU 2            /* tau kernel (one launch per linearize) */
+#define TSGLS_PROF_DIAG 3           /* Jacobi-diagonal element kernel */
+#define TSGLS_PROF_FACE 4           /* face-term kernel */
+#define TSGLS_PROF_ORTHO 5          /* Gram-Schmidt block of one GMRES iteration */
+#define TSGLS_PROF_GATHER 6         /* node-wise sum of element contributions */
+int tsgls_profile(tsgls_ctx* ctx, int enable);
+int tsgls_profile_get(tsgls_ctx* ctx, int which, int64_t* launches, double* total_ms);
 
 const char* tsgls_last_error(const tsgls_ctx* ctx);
 

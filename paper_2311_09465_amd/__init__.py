@@ -65,6 +65,8 @@ def lib():
         L.tsgls_get_tau.argtypes = [P, P]
         L.tsgls_solve.argtypes = [P, P, C.POINTER(SolveOpts), C.POINTER(SolveStats)]
         L.tsgls_info.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]
+        L.tsgls_profile.argtypes = [P, I32]
+        L.tsgls_profile_get.argtypes = [P, I32, C.POINTER(I64), C.POINTER(D)]
         L.tsgls_last_error.argtypes = [P]
         L.tsgls_last_error.restype = C.c_char_p
         L.tsgls_destroy.argtypes = [P]
@@ -175,6 +177,18 @@ class Solver:
         return dict(status=rc, newton_iters=st.newton_iters, matvecs=st.matvecs,
                     rel_residual=st.rel_residual, r0_norm=st.r0_norm, seconds=st.seconds,
                     history=list(st.history[:min(64, st.newton_iters)]))
+
+    PROF = {"elem_tangent": 0, "elem_residual": 1, "tau": 2, "diag": 3, "face": 4, "ortho": 5,
+            "gather": 6}
+
+    def profile(self, enable):
+        self._check(lib().tsgls_profile(self._h, int(bool(enable))), "profile")
+
+    def profile_get(self, which):
+        n, ms = C.c_int64(), C.c_double()
+        self._check(lib().tsgls_profile_get(self._h, self.PROF[which], C.byref(n), C.byref(ms)),
+                    "profile_get")
+        return n.value, ms.value
 
     def info(self):
         a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()

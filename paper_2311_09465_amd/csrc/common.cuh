@@ -32,6 +32,58 @@ __device__ __forceinline__ double slot_x(const double* ys, int a) {
   return a == 0 ? ys[0] : TS_SQ2 * ys[a + 1];
 }
 
+// Compile-time trigonometry for the sampling table (Taylor series after
+// reduction to [-pi, pi]; exact integer angle reduction r = k s mod M).
+constexpr double cx_pi = 3.14159265358979323846264338327950288;
+
+constexpr double cx_sin(double x) {
+  double x2 = x * x, term = x, sum = x;
+  for (int i = 1; i < 30; ++i) {
+    term *= -x2 / ((2.0 * i) * (2.0 * i + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+
+constexpr double cx_cos(double x) {
+  double x2 = x * x, term = 1.0, sum = 1.0;
+  for (int i = 1; i < 30; ++i) {
+    term *= -x2 / ((2.0 * i - 1.0) * (2.0 * i));
+    sum += term;
+  }
+  return sum;
+}
+
+// f[a][s] = phi_a(t_s): phi_0 = 1, phi_{2k-1} = sqrt2 cos(2 pi k s / M),
+// phi_{2k} = -sqrt2 sin(2 pi k s / M); b[a][s] = f[a][s] / M (projection).
+template <int K>
+struct SampleTable {
+  static constexpr int n = 2 * K + 1, M = 3 * K + 1;
+  double f[n][M];
+  double b[n][M];
+  constexpr SampleTable() : f(), b() {
+    for (int s = 0; s < M; ++s) {
+      f[0][s] = 1.0;
+      for (int k = 1; k <= K; ++k) {
+        const int r = (k * s) % M;
+        double th = 2.0 * cx_pi * r / M;          // in [0, 2 pi)
+        if (th > cx_pi) th -= 2.0 * cx_pi;        // in (-pi, pi]
+        double cs = 1.0, sg = 1.0;
+        if (th > 0.5 * cx_pi) {                   // sin(pi - x) = sin x, cos(pi - x) = -cos x
+          th = cx_pi - th;
+          cs = -1.0;
+        } else if (th < -0.5 * cx_pi) {
+          th = -cx_pi - th;
+          cs = -1.0;
+        }
+        f[2 * k - 1][s] = TS_SQ2 * cs * cx_cos(th);
+        f[2 * k][s] = -TS_SQ2 * sg * cx_sin(th);
+      }
+      for (int a = 0; a < n; ++a) b[a][s] = f[a][s] / M;
+    }
+  }
+};
+
 // (Omega x)_a in the orthonormal basis: time derivative, skew-symmetric.
 template <int n>
 __device__ __forceinline__ double omx(const double* x, int a, double omega) {

@@ -75,11 +75,12 @@ __global__ void k_prep_time(const double* __restrict__ Y, const uint8_t* __restr
 #pragma unroll
   for (int a = 0; a < n; ++a) x[a] = zero ? 0.0 : slot_x(ys, a);
   double* o = XT + idx * M;
+  constexpr SampleTable<K> TB{};
 #pragma unroll
   for (int s = 0; s < M; ++s) {
     double acc = 0.0;
 #pragma unroll
-    for (int a = 0; a < n; ++a) acc = fma(x[a], F[a * M + s], acc);
+    for (int a = 0; a < n; ++a) acc = fma(x[a], TB.f[a][s], acc);
     o[s] = acc;
   }
 }
@@ -108,6 +109,7 @@ k_tau(DevView v, const double* __restrict__ Y, double* __restrict__ tau) {
   constexpr int n = C::n, M = C::M, S = Dim<K>::S, NP = C::NP, P = Dim<K>::P, GB = C::GB;
   __shared__ double sU[GB][3][n], sVv[GB][3][n], sUt[GB][3][M], sVt[GB][3][M], sQ[GB][n * n];
   const double* __restrict__ F = v.F;
+  constexpr SampleTable<K> TB{};
   const int g = threadIdx.x / NP;
   const int c = threadIdx.x % NP;
   const int64_t gq = (int64_t)blockIdx.x * GB + g;
@@ -179,28 +181,27 @@ k_tau(DevView v, const double* __restrict__ Y, double* __restrict__ tau) {
 #pragma unroll
   for (int a = 0; a < n; ++a) w[a] = 0.0;
   if (valid && c < n) {
-    const double invM = 1.0 / M;
 #pragma unroll 1
     for (int i = 0; i < 3; ++i) {
       // b = A(v_i) e_c : project v_i(t) phi_c(t) on the K harmonics
       double bb[n];
 #pragma unroll
       for (int a = 0; a < n; ++a) bb[a] = 0.0;
-#pragma unroll 1
-      for (int s = 0; s < M; ++s) {
-        const double t = sVt[g][i][s] * F[c * M + s] * invM;
 #pragma unroll
-        for (int a = 0; a < n; ++a) bb[a] = fma(t, F[a * M + s], bb[a]);
+      for (int s = 0; s < M; ++s) {
+        const double t = sVt[g][i][s] * F[c * M + s];
+#pragma unroll
+        for (int a = 0; a < n; ++a) bb[a] = fma(t, TB.b[a][s], bb[a]);
       }
       // w += A(u_i) b
-#pragma unroll 1
+#pragma unroll
       for (int s = 0; s < M; ++s) {
         double yb = 0.0;
 #pragma unroll
-        for (int a = 0; a < n; ++a) yb = fma(bb[a], F[a * M + s], yb);
-        const double t = sUt[g][i][s] * yb * invM;
+        for (int a = 0; a < n; ++a) yb = fma(bb[a], TB.f[a][s], yb);
+        const double t = sUt[g][i][s] * yb;
 #pragma unroll
-        for (int a = 0; a < n; ++a) w[a] = fma(t, F[a * M + s], w[a]);
+        for (int a = 0; a < n; ++a) w[a] = fma(t, TB.b[a][s], w[a]);
       }
     }
 #pragma unroll
@@ -219,326 +220,387 @@ k_tau(DevView v, const double* __restrict__ Y, double* __restrict__ tau) {
   }
   __syncthreads();
   if (valid) {
-    double* out = tau + (e * 4 + q) * P;
+    const int64_t slot = v.tslot[e];
     for (int p = c; p < P; p += NP) {
       int r, cc;
       packed_rc<n>(p, r, cc);
       double acc = 0.0;
 #pragma unroll 4
       for (int k = 0; k < n; ++k) acc = fma(sQ[g][k * n + r], sQ[g][k * n + cc], acc);
-      out[p] = acc;
+      tau[tau_index(slot, q, p, P, v.TE)] = acc;
     }
   }
 }
 
 // ------------------------------------------------------- element operator
-// One tile of TE elements of the same colour per block; phases over index
-// spaces (element, time sample), (element, qp, field), (element, row),
-// (element, node, field).  The output is accumulated into `out` with plain
-// read-modify-write: elements of one colour share no node.
-template <int K, int MODE>
-struct ElemCfg {
-  static constexpr int n = Dim<K>::n, M = Dim<K>::M;
-  static constexpr bool NEWTON = (MODE & MODE_NEWTON) != 0;
-  static constexpr bool NOLS = (MODE & MODE_NOLS) != 0;
-  static constexpr int per = 13 + 16 * n + 12 * M + (NEWTON ? 12 * M : 0) + 24 * n +
-                             (NOLS ? 12 * n : 0) + 9 * M;
-  static constexpr int NT = 128;
-  static constexpr int TE0 = 40960 / (per * 8);
-  static constexpr int TE = TE0 < 1 ? 1 : (TE0 > 16 ? 16 : TE0);
+// One element per wave (block of 64 lanes).  The lanes are mapped over each
+// phase's own index space; the element's intermediates live in wave-private
+// LDS, so there is no cross-wave synchronisation and many independent waves
+// per CU hide each other's memory latency.
+//   gather      (node, field, mode)     modal input, orthonormal basis
+//   products    (sample, component)     conv_i(q,t) = u_j d_j du_i (+ du_j d_j u_i)
+//   to modes    MFMA                    [16 x M] x [M x n]
+//   operator    (row, mode)             gal = rho Omega du + rho conv, L = gal + dp
+//   tau apply   (row, mode)             z = tau L (packed tau staged in LDS)
+//   to samples  MFMA                    [16 x n] x [n x M]
+//   LS products (sample, direction j)   W_ji(t) = sum_q w u_j(q,t) z_i(q,t)
+//   to modes    MFMA
+//   assembly    (node, field, mode)     then a coalesced read-modify-write
+// Rows are (qp q, component i) -> q*3 + i.  Elements of one colour share no
+// node, so the read-modify-write needs no atomics.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <int K>
+struct TileCfg {
+  static constexpr int TE = 1;                    // tau / Z storage: one element per tile
 };
 
 template <int K, int MODE>
-__global__ void __launch_bounds__(128)
+struct ElemCfg {
+  static constexpr int n = Dim<K>::n, M = Dim<K>::M, S = Dim<K>::S, P = Dim<K>::P;
+  static constexpr bool NEWTON = (MODE & MODE_NEWTON) != 0;
+  static constexpr bool NOLS = (MODE & MODE_NOLS) != 0;
+  static constexpr int MS = (M + 3) / 4 * 4;      // padded samples (k of back transform)
+  static constexpr int NS = (n + 3) / 4 * 4;      // padded modes (k of forward transform)
+  static constexpr int NCT = (n + 15) / 16;       // column tiles over modes
+  static constexpr int MCT = (M + 15) / 16;       // column tiles over samples
+  static constexpr int MX1 = 16 * MS > 4 * P ? 16 * MS : 4 * P;
+  static constexpr int XR = MX1 > 16 * S ? MX1 : 16 * S;   // tau -> W(t) -> output slots
+};
+
+template <int K, int MODE>
+__global__ void __launch_bounds__(64)
 k_elem(DevView v, const double* __restrict__ Y, const double* __restrict__ VT,
        double* __restrict__ Zout, double* __restrict__ out, double shift, int64_t begin,
-       int64_t end) {
+       int64_t end, int64_t tile_off) {
   using C = ElemCfg<K, MODE>;
-  constexpr int n = Dim<K>::n, M = Dim<K>::M, S = Dim<K>::S, P = Dim<K>::P;
-  constexpr int TE = C::TE, NT = C::NT;
+  constexpr int n = C::n, M = C::M, S = C::S, P = C::P, MS = C::MS, NS = C::NS;
+  constexpr int NCT = C::NCT, MCT = C::MCT;
   constexpr bool RESID = (MODE & MODE_RESID) != 0;
   constexpr bool NEWTON = C::NEWTON, NOLS = C::NOLS;
   constexpr bool STOREZ = (MODE & MODE_STOREZ) != 0;
-  __shared__ double sGeo[TE][13];
-  __shared__ int sNode[TE][4];
-  __shared__ double sV[TE][4][4][n];
-  __shared__ double sT[TE][12][M];
-  __shared__ double sZT[NEWTON ? TE : 1][12][M];
-  __shared__ double sL[TE][12][n];
-  __shared__ double sZ[TE][12][n];
-  __shared__ double sZc[NOLS ? TE : 1][12][n];
-  __shared__ double sW[TE][9][M];
-  const double* __restrict__ F = v.F;
-  const double* __restrict__ UT = v.UT;
-  const int tid = threadIdx.x;
-  const int64_t e0 = begin + (int64_t)blockIdx.x * TE;
-  const int ne = (int)((end - e0) < TE ? (end - e0) : TE);
+  __shared__ double sV[4][4][n];          // modal input [node][field][mode]
+  __shared__ double sT[16][MS];           // conv(t) -> z(t) -> W modes [16][n]
+  __shared__ double sC[16][n];            // conv modes
+  __shared__ double sX[C::XR];            // packed tau [p][q] -> W(t) [16][MS] -> output
+  __shared__ double sZ[16][NS];           // z modes, zero beyond n
+  __shared__ double sL[12][n];            // momentum operator L (or gal for NOLS)
+  __shared__ double sG[12][n];            // gal, then gal - Omega z
+  __shared__ double sLc[NOLS ? 12 : 1][n];   // grad p alone (NOLS)
+  __shared__ double sZc[NOLS ? 12 : 1][n];
+  __shared__ double sZT[NEWTON ? 16 : 1][MS];
+  __shared__ double sZf[NEWTON ? 16 : 1][NS];
+  __shared__ double sD[4][3];             // grad N (lane-dependent lookups)
+  __shared__ int64_t sN[4];
+  // `out` receives this element's contributions [4 nodes][4 fields][S]
+  (void)end;
+  (void)tile_off;
+  const int lane = threadIdx.x;
+  const int64_t e = begin + blockIdx.x;
   const double rho = v.rho, omega = v.omega;
-  const double invM = 1.0 / M;
 
-  for (int i = tid; i < ne * 4; i += NT) sNode[i >> 2][i & 3] = v.conn[(e0 + (i >> 2)) * 4 + (i & 3)];
-  for (int i = tid; i < ne * 13; i += NT) sGeo[i / 13][i % 13] = v.geo[(e0 + i / 13) * 16 + i % 13];
-  __syncthreads();
+  // element data (uniform across the wave)
+  int64_t nd[4];
+  double dN[4][3];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    nd[b] = v.conn[e * 4 + b];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) dN[b][j] = v.geo[e * 16 + b * 3 + j];
+  }
+  const double wgt = v.geo[e * 16 + 12];
 
-  // gather the modal input in the orthonormal basis
-  for (int i = tid; i < ne * 16 * n; i += NT) {
-    const int e = i / (16 * n);
-    const int r = i % (16 * n);
-    const int b = r / (4 * n), f = (r / n) & 3, a = r % n;
-    const int node = sNode[e][b];
-    double val;
-    if (!RESID && f < 3 && (v.nflag[node] & 1))
-      val = 0.0;
-    else
-      val = slot_x(Y + ((int64_t)node * 4 + f) * S, a);
-    sV[e][b][f][a] = val;
+  // per-lane B fragments of the sampling matrices
+  double Bb[MS / 4][NCT];   // back: B[k=s][j=a] = phi_a(t_s) / M
+  double Bf[NS / 4][MCT];   // forward: B[k=a][j=s] = phi_a(t_s)
+  {
+    const double invM = 1.0 / M;
+#pragma unroll
+    for (int ks = 0; ks < MS / 4; ++ks)
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) {
+        const int s = ks * 4 + (lane >> 4), a = ct * 16 + (lane & 15);
+        Bb[ks][ct] = (s < M && a < n) ? v.F[a * M + s] * invM : 0.0;
+      }
+#pragma unroll
+    for (int ks = 0; ks < NS / 4; ++ks)
+#pragma unroll
+      for (int ct = 0; ct < MCT; ++ct) {
+        const int a = ks * 4 + (lane >> 4), s = ct * 16 + (lane & 15);
+        Bf[ks][ct] = (s < M && a < n) ? v.F[a * M + s] : 0.0;
+      }
   }
 
-  // convection products on the time samples: conv_i(q,t) = u_j d_j du_i (+ du_j d_j u_i)
-  for (int i = tid; i < ne * M; i += NT) {
-    const int e = i / M, s = i % M;
-    double U[4][3], W[4][3], dN[4][3];
+  // tau of the element: contiguous [p][q]; loads issued now, stored later
+  constexpr int NTAU = (4 * P + 63) / 64;
+  double taubuf[NTAU];
+  {
+    const double* src = v.tau + e * (int64_t)(4 * P);
+#pragma unroll
+    for (int k = 0; k < NTAU; ++k) {
+      const int i = lane + k * 64;
+      taubuf[k] = i < 4 * P ? src[i] : 0.0;
+    }
+  }
+  // gather the modal input (all loads issued before the stores)
+  {
+    constexpr int NIT = (16 * n + 63) / 64;
+    double buf[NIT];
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int i = lane + k * 64;
+      double val = 0.0;
+      if (i < 16 * n) {
+        const int b = i / (4 * n), f = (i / n) & 3, a = i % n;
+        const int64_t node = v.conn[e * 4 + b];
+        const double* ys = Y + (node * 4 + f) * S;
+        val = a == 0 ? ys[0] : TS_SQ2 * ys[a + 1];
+        if (!RESID && f < 3 && (v.nflag[node] & 1)) val = 0.0;
+      }
+      buf[k] = val;
+    }
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int i = lane + k * 64;
+      if (i < 16 * n) (&sV[0][0][0])[i] = buf[k];
+    }
+  }
+  if (lane < 4) sN[lane] = nd[lane];
+  if (lane < 12) sD[lane / 3][lane % 3] = v.geo[e * 16 + lane];
+  // zero padding entering the MFMA k dimension
+  for (int i = lane; i < 16 * MS; i += 64) (&sT[0][0])[i] = 0.0;
+  for (int i = lane; i < 16 * NS; i += 64) (&sZ[0][0])[i] = 0.0;
+  if (NEWTON)
+    for (int i = lane; i < 16 * NS; i += 64) (&sZf[0][0])[i] = 0.0;
+  __syncthreads();
+
+  // convection products on the samples: item (sample s, component i)
+  const double* __restrict__ UT = v.UT;
+  for (int it = lane; it < 3 * M; it += 64) {
+    const int s = it % M, ii = it / M;
+    double U[4][3], Wi[4], Ui[4], Wj[4][3];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const int64_t node = sNode[e][b];
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        U[b][j] = UT[(node * 3 + j) * M + s];
-        W[b][j] = RESID ? U[b][j] : VT[(node * 3 + j) * M + s];
-        dN[b][j] = sGeo[e][b * 3 + j];
+        U[b][j] = UT[(nd[b] * 3 + j) * M + s];
+        Wj[b][j] = RESID ? U[b][j] : (NEWTON ? VT[(nd[b] * 3 + j) * M + s] : 0.0);
       }
+      Ui[b] = UT[(nd[b] * 3 + ii) * M + s];
+      Wi[b] = RESID ? Ui[b] : VT[(nd[b] * 3 + ii) * M + s];
     }
-    double gW[3][3], gU[3][3], sUj[3], sWj[3];
+    double gW[3], gU[3], sU[3], sW[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      sUj[j] = U[0][j] + U[1][j] + U[2][j] + U[3][j];
-      sWj[j] = W[0][j] + W[1][j] + W[2][j] + W[3][j];
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii) {
-        gW[j][ii] = dN[0][j] * W[0][ii] + dN[1][j] * W[1][ii] + dN[2][j] * W[2][ii] + dN[3][j] * W[3][ii];
-        gU[j][ii] = dN[0][j] * U[0][ii] + dN[1][j] * U[1][ii] + dN[2][j] * U[2][ii] + dN[3][j] * U[3][ii];
-      }
+      gW[j] = dN[0][j] * Wi[0] + dN[1][j] * Wi[1] + dN[2][j] * Wi[2] + dN[3][j] * Wi[3];
+      gU[j] = dN[0][j] * Ui[0] + dN[1][j] * Ui[1] + dN[2][j] * Ui[2] + dN[3][j] * Ui[3];
+      sU[j] = U[0][j] + U[1][j] + U[2][j] + U[3][j];
+      sW[j] = Wj[0][j] + Wj[1][j] + Wj[2][j] + Wj[3][j];
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      double uq[3], wq[3];
+      double cv = 0.0;
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        uq[j] = TS_QB * sUj[j] + (TS_QA - TS_QB) * U[q][j];
-        wq[j] = TS_QB * sWj[j] + (TS_QA - TS_QB) * W[q][j];
+        const double uq = TS_QB * sU[j] + (TS_QA - TS_QB) * U[q][j];
+        cv = fma(uq, gW[j], cv);
+        if (NEWTON) {
+          const double wq = TS_QB * sW[j] + (TS_QA - TS_QB) * Wj[q][j];
+          cv = fma(wq, gU[j], cv);
+        }
       }
+      sT[q * 3 + ii][s] = cv;
+    }
+  }
 #pragma unroll
-      for (int ii = 0; ii < 3; ++ii) {
-        double cv = uq[0] * gW[0][ii] + uq[1] * gW[1][ii] + uq[2] * gW[2][ii];
-        if (NEWTON) cv += wq[0] * gU[0][ii] + wq[1] * gU[1][ii] + wq[2] * gU[2][ii];
-        sT[e][q * 3 + ii][s] = cv;
-      }
+  for (int k = 0; k < NTAU; ++k) {
+    const int i = lane + k * 64;
+    if (i < 4 * P) sX[i] = taubuf[k];
+  }
+  __syncthreads();
+
+  // conv(t) -> modes (MFMA)
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < MS / 4; ++ks)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sT[lane & 15][ks * 4 + (lane >> 4)], Bb[ks][ct], acc, 0, 0, 0);
+    const int a = ct * 16 + (lane & 15);
+    if (a < n) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sC[(lane >> 4) + 4 * r][a] = acc[r];
     }
   }
   __syncthreads();
 
-  // per (element, qp, field): back to modes, momentum operator L, z = tau L, z(t)
-  for (int i = tid; i < ne * 12; i += NT) {
-    const int e = i / 12, row = i % 12, q = row / 3, fi = row % 3;
-    double cm[n];
-#pragma unroll
-    for (int a = 0; a < n; ++a) cm[a] = 0.0;
-#pragma unroll 2
-    for (int s = 0; s < M; ++s) {
-      const double t = sT[e][row][s];
-#pragma unroll
-      for (int a = 0; a < n; ++a) cm[a] = fma(t, F[a * M + s], cm[a]);
+  // momentum operator per (row, mode)
+  for (int it = lane; it < 12 * n; it += 64) {
+    const int row = it / n, a = it % n, q = row / 3, fi = row % 3;
+    double om = 0.0;   // (Omega du)_a from du at the neighbouring mode
+    if (a > 0) {
+      const int a2 = (a & 1) ? a + 1 : a - 1;
+      const double du2 = TS_QB * (sV[0][fi][a2] + sV[1][fi][a2] + sV[2][fi][a2] + sV[3][fi][a2]) +
+                         (TS_QA - TS_QB) * sV[q][fi][a2];
+      om = (a & 1) ? -((a + 1) >> 1) * omega * du2 : (a >> 1) * omega * du2;
     }
-    double du[n], gp[n], gal[n];
-    const double g0 = sGeo[e][0 * 3 + fi], g1 = sGeo[e][1 * 3 + fi];
-    const double g2 = sGeo[e][2 * 3 + fi], g3 = sGeo[e][3 * 3 + fi];
+    const double gal = rho * (om + sC[row][a]);
+    const double gp = dN[0][fi] * sV[0][3][a] + dN[1][fi] * sV[1][3][a] + dN[2][fi] * sV[2][3][a] +
+                      dN[3][fi] * sV[3][3][a];
+    sG[row][a] = gal;
+    sL[row][a] = NOLS ? gal : gal + gp;
+    if (NOLS) sLc[NOLS ? row : 0][a] = gp;
+  }
+  __syncthreads();
+
+  // z = tau L per (row, mode); packed tau in sX as [p][q]
+  for (int it = lane; it < 12 * n; it += 64) {
+    const int row = it / n, a = it % n, q = row / 3, fi = row % 3;
+    double z = 0.0, zc = 0.0;
 #pragma unroll
-    for (int a = 0; a < n; ++a) {
-      du[a] = TS_QB * (sV[e][0][fi][a] + sV[e][1][fi][a] + sV[e][2][fi][a] + sV[e][3][fi][a]) +
-              (TS_QA - TS_QB) * sV[e][q][fi][a];
-      gp[a] = g0 * sV[e][0][3][a] + g1 * sV[e][1][3][a] + g2 * sV[e][2][3][a] + g3 * sV[e][3][3][a];
+    for (int b = 0; b < n; ++b) {
+      const int lo = a < b ? a : b, hi = a < b ? b : a;
+      const double t = sX[(lo * n - (lo * (lo - 1)) / 2 + (hi - lo)) * 4 + q];
+      z = fma(t, sL[row][b], z);
+      if (NOLS) zc = fma(t, sLc[NOLS ? row : 0][b], zc);
     }
-#pragma unroll
-    for (int a = 0; a < n; ++a) {
-      gal[a] = rho * (omx<n>(du, a, omega) + cm[a] * invM);
-      sL[e][row][a] = gal[a];
+    sZ[row][a] = z;
+    if (NOLS) sZc[NOLS ? row : 0][a] = zc;
+    if (STOREZ) Zout[z_index(e, row, a, n, 1)] = z;
+    if (NEWTON) sZf[NEWTON ? row : 0][a] = v.Z[z_index(e, row, a, n, 1)];
+    (void)fi;
+  }
+  __syncthreads();
+
+  // gal - Omega z (per (row, mode)) and z modes -> samples (MFMA)
+  for (int it = lane; it < 12 * n; it += 64) {
+    const int row = it / n, a = it % n;
+    if (a > 0) {
+      const int a2 = (a & 1) ? a + 1 : a - 1;
+      const double z2 = sZ[row][a2];
+      sG[row][a] -= (a & 1) ? -((a + 1) >> 1) * omega * z2 : (a >> 1) * omega * z2;
     }
-    const double* tp = v.tau + ((e0 + e) * 4 + q) * P;
-    double z[n], zc[n];
+  }
 #pragma unroll
-    for (int a = 0; a < n; ++a) {
-      z[a] = 0.0;
-      zc[a] = 0.0;
-    }
-    {
-      int p = 0;
+  for (int w = 0; w < (NEWTON ? 2 : 1); ++w) {
 #pragma unroll
-      for (int a = 0; a < n; ++a) {
+    for (int ct = 0; ct < MCT; ++ct) {
+      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int b = a; b < n; ++b) {
-          const double t = tp[p++];
-          const double La = NOLS ? gal[a] : gal[a] + gp[a];
-          const double Lb = NOLS ? gal[b] : gal[b] + gp[b];
-          z[a] = fma(t, Lb, z[a]);
-          if (b != a) z[b] = fma(t, La, z[b]);
-          if (NOLS) {
-            zc[a] = fma(t, gp[b], zc[a]);
-            if (b != a) zc[b] = fma(t, gp[a], zc[b]);
-          }
+      for (int ks = 0; ks < NS / 4; ++ks) {
+        const double av = (w == 0) ? sZ[lane & 15][ks * 4 + (lane >> 4)]
+                                   : sZf[NEWTON ? (lane & 15) : 0][ks * 4 + (lane >> 4)];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Bf[ks][ct], acc, 0, 0, 0);
+      }
+      const int s = ct * 16 + (lane & 15);
+      if (s < M) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (w == 0)
+            sT[(lane >> 4) + 4 * r][s] = acc[r];
+          else
+            sZT[NEWTON ? (lane >> 4) + 4 * r : 0][s] = acc[r];
         }
       }
     }
-#pragma unroll
-    for (int a = 0; a < n; ++a) {
-      sZ[e][row][a] = z[a];
-      if (NOLS) sZc[e][row][a] = zc[a];
-    }
-    if (STOREZ) {
-      double* zo = Zout + (((e0 + e) * 4 + q) * 3 + fi) * n;
-#pragma unroll
-      for (int a = 0; a < n; ++a) zo[a] = z[a];
-    }
-#pragma unroll 2
-    for (int s = 0; s < M; ++s) {
-      double acc = 0.0;
-#pragma unroll
-      for (int a = 0; a < n; ++a) acc = fma(z[a], F[a * M + s], acc);
-      sT[e][row][s] = acc;
-    }
-    if (NEWTON) {
-      const double* zf = v.Z + (((e0 + e) * 4 + q) * 3 + fi) * n;
-      double Zm[n];
-#pragma unroll
-      for (int a = 0; a < n; ++a) Zm[a] = zf[a];
-#pragma unroll 2
-      for (int s = 0; s < M; ++s) {
-        double acc = 0.0;
-#pragma unroll
-        for (int a = 0; a < n; ++a) acc = fma(Zm[a], F[a * M + s], acc);
-        sZT[NEWTON ? e : 0][row][s] = acc;
-      }
-    }
   }
   __syncthreads();
 
-  // least-squares test products: W_ji(t) = sum_q w u_j(q,t) z_i(q,t) (+ du_j Z_i)
-  for (int i = tid; i < ne * M; i += NT) {
-    const int e = i / M, s = i % M;
-    double U[4][3], W[4][3];
+  // least-squares test products per (sample, direction j); W(t) in sX as [16][MS]
+  for (int i = lane; i < 16 * MS; i += 64) sX[i] = 0.0;
+  __syncthreads();
+  for (int it = lane; it < 3 * M; it += 64) {
+    const int s = it % M, j = it / M;
+    double Uj[4], Wj[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const int64_t node = sNode[e][b];
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        U[b][j] = UT[(node * 3 + j) * M + s];
-        W[b][j] = NEWTON ? VT[(node * 3 + j) * M + s] : 0.0;
-      }
+      Uj[b] = UT[(nd[b] * 3 + j) * M + s];
+      Wj[b] = NEWTON ? VT[(nd[b] * 3 + j) * M + s] : 0.0;
     }
-    const double wgt = sGeo[e][12];
-    double acc[9];
-#pragma unroll
-    for (int r = 0; r < 9; ++r) acc[r] = 0.0;
+    const double su = Uj[0] + Uj[1] + Uj[2] + Uj[3];
+    const double sw = Wj[0] + Wj[1] + Wj[2] + Wj[3];
+    double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      double uq[3], wq[3];
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        uq[j] = TS_QB * (U[0][j] + U[1][j] + U[2][j] + U[3][j]) + (TS_QA - TS_QB) * U[q][j];
-        wq[j] = TS_QB * (W[0][j] + W[1][j] + W[2][j] + W[3][j]) + (TS_QA - TS_QB) * W[q][j];
-      }
+      const double uq = TS_QB * su + (TS_QA - TS_QB) * Uj[q];
+      const double wq = TS_QB * sw + (TS_QA - TS_QB) * Wj[q];
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii) {
-        const double zt = sT[e][q * 3 + ii][s];
-        const double Zt = NEWTON ? sZT[NEWTON ? e : 0][q * 3 + ii][s] : 0.0;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          acc[j * 3 + ii] = fma(uq[j], zt, acc[j * 3 + ii]);
-          if (NEWTON) acc[j * 3 + ii] = fma(wq[j], Zt, acc[j * 3 + ii]);
-        }
+        acc[ii] = fma(uq, sT[q * 3 + ii][s], acc[ii]);
+        if (NEWTON) acc[ii] = fma(wq, sZT[NEWTON ? q * 3 + ii : 0][s], acc[ii]);
       }
     }
 #pragma unroll
-    for (int r = 0; r < 9; ++r) sW[e][r][s] = wgt * acc[r];
+    for (int ii = 0; ii < 3; ++ii) sX[(j * 3 + ii) * MS + s] = wgt * acc[ii];
   }
   __syncthreads();
 
-  // back to modes; stored over the sT tile (9 n <= 12 M)
-  for (int i = tid; i < ne * 9; i += NT) {
-    const int e = i / 9, r = i % 9;
-    double acc[n];
+  // W(t) -> modes (MFMA), rows j*3 + i, stored over sT as [16][n]
+  double* wm = &sT[0][0];
 #pragma unroll
-    for (int a = 0; a < n; ++a) acc[a] = 0.0;
-#pragma unroll 2
-    for (int s = 0; s < M; ++s) {
-      const double t = sW[e][r][s];
+  for (int ct = 0; ct < NCT; ++ct) {
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int a = 0; a < n; ++a) acc[a] = fma(t, F[a * M + s], acc[a]);
+    for (int ks = 0; ks < MS / 4; ++ks)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sX[(lane & 15) * MS + ks * 4 + (lane >> 4)], Bb[ks][ct], acc, 0, 0, 0);
+    const int a = ct * 16 + (lane & 15);
+    __syncthreads();   // all A fragments of sT were read before sT is overwritten
+    if (a < n) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) wm[((lane >> 4) + 4 * r) * n + a] = acc[r];
     }
-    double* wm = &sT[e][0][0];
-#pragma unroll
-    for (int a = 0; a < n; ++a) wm[r * n + a] = acc[a] * invM;
   }
   __syncthreads();
 
-  // assemble per (element, node, field) and add to the global vector
+  // assembly per (node, field, mode) into output slots (sX as [16][S])
   const double mu = v.mu;
-  for (int i = tid; i < ne * 16; i += NT) {
-    const int e = i >> 4, b = (i >> 2) & 3, f = i & 3;
-    const int64_t node = sNode[e][b];
-    if (f < 3 && (v.nflag[node] & 1)) continue;
-    const double* dN = &sGeo[e][0];        // dN[c*3 + j]
-    const double wgt = sGeo[e][12];
-    const double* wm = &sT[e][0][0];
-    double o[n];
+  for (int it = lane; it < 16 * n; it += 64) {
+    const int b = it / (4 * n), f = (it / n) & 3, a = it % n;
+    double o;
     if (f < 3) {
       const int fi = f;
-      double lw[4], visc[4], mass[4];
+      double acc = 0.0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) lw[q] = wgt * lamq(q, b);
+      for (int q = 0; q < 4; ++q) acc += wgt * lamq(q, b) * sG[q * 3 + fi][a];
+      acc += sD[b][0] * wm[(0 * 3 + fi) * n + a] + sD[b][1] * wm[(1 * 3 + fi) * n + a] +
+             sD[b][2] * wm[(2 * 3 + fi) * n + a];
+      const double psum = sV[0][3][a] + sV[1][3][a] + sV[2][3][a] + sV[3][3][a];
+      acc -= sD[b][fi] * wgt * psum;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        visc[c] = 4.0 * wgt * mu * (dN[b * 3] * dN[c * 3] + dN[b * 3 + 1] * dN[c * 3 + 1] + dN[b * 3 + 2] * dN[c * 3 + 2]);
         const double mbc = (b == c) ? (TS_QA * TS_QA + 3.0 * TS_QB * TS_QB)
                                     : (2.0 * TS_QA * TS_QB + 2.0 * TS_QB * TS_QB);
-        mass[c] = shift * wgt * mbc;
+        const double kbc = 4.0 * wgt * mu * (sD[b][0] * dN[c][0] + sD[b][1] * dN[c][1] + sD[b][2] * dN[c][2]) +
+                           shift * wgt * mbc;
+        acc += kbc * sV[c][fi][a];
       }
-#pragma unroll
-      for (int a = 0; a < n; ++a) {
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          acc += lw[q] * (sL[e][q * 3 + fi][a] - omx<n>(&sZ[e][q * 3 + fi][0], a, omega));
-        acc += dN[b * 3] * wm[(0 * 3 + fi) * n + a] + dN[b * 3 + 1] * wm[(1 * 3 + fi) * n + a] +
-               dN[b * 3 + 2] * wm[(2 * 3 + fi) * n + a];
-        const double psum = sV[e][0][3][a] + sV[e][1][3][a] + sV[e][2][3][a] + sV[e][3][3][a];
-        acc -= dN[b * 3 + fi] * wgt * psum;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc += (visc[c] + mass[c]) * sV[e][c][fi][a];
-        o[a] = acc;
-      }
+      o = (v.nflag[sN[b]] & 1) ? 0.0 : acc;
     } else {
+      double div = 0.0;
 #pragma unroll
-      for (int a = 0; a < n; ++a) {
-        double div = 0.0;
+      for (int c = 0; c < 4; ++c) div += dN[c][0] * sV[c][0][a] + dN[c][1] * sV[c][1][a] + dN[c][2] * sV[c][2][a];
+      double ls = 0.0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-          div += dN[c * 3] * sV[e][c][0][a] + dN[c * 3 + 1] * sV[e][c][1][a] + dN[c * 3 + 2] * sV[e][c][2][a];
-        double ls = 0.0;
+      for (int ii = 0; ii < 3; ++ii) {
+        double zs = 0.0;
 #pragma unroll
-        for (int ii = 0; ii < 3; ++ii) {
-          double zs = 0.0;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) zs += NOLS ? sZc[NOLS ? e : 0][q * 3 + ii][a] : sZ[e][q * 3 + ii][a];
-          ls += dN[b * 3 + ii] * zs;
-        }
-        o[a] = wgt * div + (wgt / rho) * ls;
+        for (int q = 0; q < 4; ++q) zs += NOLS ? sZc[NOLS ? q * 3 + ii : 0][a] : sZ[q * 3 + ii][a];
+        ls += sD[b][ii] * zs;
       }
+      o = wgt * div + (wgt / rho) * ls;
     }
-    double* op = out + (node * 4 + f) * S;
-    op[0] += o[0];
-#pragma unroll
-    for (int a = 1; a < n; ++a) op[a + 1] += o[a] * TS_RS2;
+    double* so = &sX[(b * 4 + f) * S];
+    if (a == 0) {
+      so[0] = o;
+      so[1] = 0.0;
+    } else {
+      so[a + 1] = o * TS_RS2;
+    }
   }
+  __syncthreads();
+
+  // the element's 4 x 4 x S contributions, one contiguous coalesced store
+  for (int i = lane; i < 16 * S; i += 64) out[e * (16 * S) + i] = sX[i];
 }
 
 // ------------------------------------------------------- Jacobi diagonal
@@ -561,8 +623,7 @@ k_diag(DevView v, double* __restrict__ d, double shift, int64_t begin, int64_t e
   int nodes[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) nodes[c] = v.conn[e * 4 + c];
-  const double* __restrict__ F = v.F;
-  const double invM = 1.0 / M;
+  constexpr SampleTable<K> TB{};
   double dm[n], dc[n];
 #pragma unroll
   for (int a = 0; a < n; ++a) dm[a] = dc[a] = 0.0;
@@ -570,7 +631,7 @@ k_diag(DevView v, double* __restrict__ d, double shift, int64_t begin, int64_t e
   for (int q = 0; q < 4; ++q) {
     const double lam = lamq(q, b);
     double gs[M];
-#pragma unroll 1
+#pragma unroll
     for (int s = 0; s < M; ++s) {
       double gsum = 0.0;
 #pragma unroll
@@ -580,17 +641,17 @@ k_diag(DevView v, double* __restrict__ d, double shift, int64_t begin, int64_t e
       }
       gs[s] = gsum;
     }
-    const double* tp = v.tau + (e * 4 + q) * P;
+    const int64_t slot = v.tslot[e];
 #pragma unroll 1
     for (int a = 0; a < n; ++a) {
       double bcol[n];
 #pragma unroll
       for (int aa = 0; aa < n; ++aa) bcol[aa] = 0.0;
-#pragma unroll 1
-      for (int s = 0; s < M; ++s) {
-        const double t = gs[s] * F[a * M + s] * invM;
 #pragma unroll
-        for (int aa = 0; aa < n; ++aa) bcol[aa] = fma(t, F[aa * M + s], bcol[aa]);
+      for (int s = 0; s < M; ++s) {
+        const double t = gs[s] * v.F[a * M + s];
+#pragma unroll
+        for (int aa = 0; aa < n; ++aa) bcol[aa] = fma(t, TB.b[aa][s], bcol[aa]);
       }
       double Aaa = 0.0;
 #pragma unroll
@@ -612,7 +673,7 @@ k_diag(DevView v, double* __restrict__ d, double shift, int64_t begin, int64_t e
       for (int r = 0; r < n; ++r) {
 #pragma unroll
         for (int c = r; c < n; ++c) {
-          const double t = tp[p++];
+          const double t = v.tau[tau_index(slot, q, p++, P, v.TE)];
           quad += (r == c ? 1.0 : 2.0) * t * bcol[r] * bcol[c];
           if (r == c && r == a) taa = t;
         }
@@ -627,15 +688,33 @@ k_diag(DevView v, double* __restrict__ d, double shift, int64_t begin, int64_t e
         }
     }
   }
-  double* op = d + node * 4 * S;
+  (void)node;
+  double* op = d + (e * 4 + b) * 4 * S;      // this element's node-b contributions
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
     double* o = op + f * S;
     const double* src = f < 3 ? dm : dc;
-    o[0] += src[0];
+    o[0] = src[0];
+    o[1] = 0.0;
 #pragma unroll
-    for (int a = 1; a < n; ++a) o[a + 1] += src[a];
+    for (int a = 1; a < n; ++a) o[a + 1] = src[a];
   }
+}
+
+// Node-wise sum of element contributions (ascending element order): thread
+// per (node, slot of the node's 4 S values).
+template <int K>
+__global__ void k_gather(const int32_t* __restrict__ noff, const int32_t* __restrict__ ninc,
+                         const double* __restrict__ ebuf, double* __restrict__ out, int64_t nn) {
+  constexpr int S4 = 4 * Dim<K>::S;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= nn * S4) return;
+  const int64_t node = idx / S4;
+  const int j = (int)(idx % S4);
+  const int k0 = noff[node], k1 = noff[node + 1];
+  double acc = 0.0;
+  for (int k = k0; k < k1; ++k) acc += ebuf[(int64_t)ninc[k] * S4 + j];
+  out[idx] = acc;
 }
 
 template <int K>
@@ -650,6 +729,15 @@ __global__ void k_diag_finish(const uint8_t* __restrict__ nflag, double* __restr
 
 // --------------------------------------------------------------- dispatch
 #define TSGLS_FOR_EACH_K(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(11) X(15)
+
+int tile_elems(int K) {
+  switch (K) {
+#define CASE(k) case k: return TileCfg<k>::TE;
+    TSGLS_FOR_EACH_K(CASE)
+#undef CASE
+    default: return 1;
+  }
+}
 
 bool supported_K(int K) {
   switch (K) {
@@ -701,12 +789,11 @@ hipError_t launch_tau(const DevView& v, const double* Y, double* tau, hipStream_
 template <int K>
 static void elem_dispatch(const DevView& v, int mode, const double* Y, const double* VT,
                           double* Zout, double* out, double shift, int64_t begin, int64_t end,
-                          hipStream_t st) {
+                          int64_t tile_off, hipStream_t st) {
 #define LAUNCH(MD)                                                                       \
   {                                                                                      \
-    constexpr int TE = ElemCfg<K, MD>::TE;                                               \
-    const unsigned grid = (unsigned)((end - begin + TE - 1) / TE);                       \
-    k_elem<K, MD><<<grid, 128, 0, st>>>(v, Y, VT, Zout, out, shift, begin, end);         \
+    const unsigned grid = (unsigned)(end - begin);                                       \
+    k_elem<K, MD><<<grid, 64, 0, st>>>(v, Y, VT, Zout, out, shift, begin, end, tile_off); \
   }
   switch (mode) {
     case MODE_RESID: LAUNCH(MODE_RESID) break;
@@ -721,10 +808,10 @@ static void elem_dispatch(const DevView& v, int mode, const double* Y, const dou
 
 hipError_t launch_elem(const DevView& v, int mode, const double* Y, const double* VT,
                        double* Zout, double* out, double shift, int64_t begin, int64_t end,
-                       hipStream_t st) {
+                       int64_t tile_off, hipStream_t st) {
   if (end <= begin) return hipSuccess;
   switch (v.K) {
-#define CASE(k) case k: elem_dispatch<k>(v, mode, Y, VT, Zout, out, shift, begin, end, st); break;
+#define CASE(k) case k: elem_dispatch<k>(v, mode, Y, VT, Zout, out, shift, begin, end, tile_off, st); break;
     TSGLS_FOR_EACH_K(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -738,6 +825,20 @@ hipError_t launch_diag(const DevView& v, double* d, double shift, int64_t begin,
   const unsigned grid = (unsigned)(((end - begin) * 4 + 127) / 128);
   switch (v.K) {
 #define CASE(k) case k: k_diag<k><<<grid, 128, 0, st>>>(v, d, shift, begin, end); break;
+    TSGLS_FOR_EACH_K(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(int K, const int32_t* noff, const int32_t* ninc, const double* ebuf,
+                         double* out, int64_t nn, hipStream_t st) {
+  const int64_t tot = nn * 4 * (2 * K + 2);
+  if (tot == 0) return hipSuccess;
+  const unsigned grid = (unsigned)((tot + 255) / 256);
+  switch (K) {
+#define CASE(k) case k: k_gather<k><<<grid, 256, 0, st>>>(noff, ninc, ebuf, out, nn); break;
     TSGLS_FOR_EACH_K(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;

@@ -90,54 +90,58 @@ k_face_lin(DevView v, const double* __restrict__ UTs, double* __restrict__ aneg)
   }
 }
 
-// Thread per (face, face node, velocity component); faces of one colour share
-// no node.  resid != 0: input is the state (unmasked) and the traction term is
+// Thread per (Neumann node, velocity component): gathers the contributions of
+// the node's incident faces in a fixed order (deterministic, one launch).
+// resid != 0: input is the state (unmasked) and the traction term is
 // included; otherwise the input is a direction (Dirichlet entries masked).
 template <int K>
 __global__ void k_face_apply(DevView v, const double* __restrict__ Y, int resid,
-                             const double* __restrict__ an, double* __restrict__ out,
-                             int64_t begin, int64_t end) {
+                             const double* __restrict__ an, double* __restrict__ out) {
   constexpr int n = Dim<K>::n, S = Dim<K>::S, P = Dim<K>::P;
-  const int64_t idx = begin * 9 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= end * 9) return;
-  const int64_t f = idx / 9;
-  const int a = (int)((idx / 3) % 3), i = (int)(idx % 3);
-  const int64_t node = v.fconn[f * 3 + a];
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= v.n_fnodes * 3) return;
+  const int64_t u = idx / 3;
+  const int i = (int)(idx % 3);
+  const int64_t node = v.fnode[u];
   if (v.nflag[node] & 1) return;
-  const double area = v.fgeo[f * 4 + 3];
-  double xb[3][n];
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    const int64_t nb = v.fconn[f * 3 + b];
-    const bool z = !resid && (v.nflag[nb] & 1);
-#pragma unroll
-    for (int m = 0; m < n; ++m) xb[b][m] = z ? 0.0 : slot_x(Y + (nb * 4 + i) * S, m);
-  }
   double o[n];
 #pragma unroll
   for (int m = 0; m < n; ++m) o[m] = 0.0;
-  const double coef = -0.5 * v.rho * v.beta * area / 3.0;
+  for (int k = v.foff[u]; k < v.foff[u + 1]; ++k) {
+    const int64_t f = v.finc[k] / 3;
+    const int a = v.finc[k] % 3;
+    const double area = v.fgeo[f * 4 + 3];
+    double xb[3][n];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int64_t nb = v.fconn[f * 3 + b];
+      const bool z = !resid && (v.nflag[nb] & 1);
+#pragma unroll
+      for (int m = 0; m < n; ++m) xb[b][m] = z ? 0.0 : slot_x(Y + (nb * 4 + i) * S, m);
+    }
+    const double coef = -0.5 * v.rho * v.beta * area / 3.0;
 #pragma unroll 1
-  for (int q = 0; q < 3; ++q) {
-    double uq[n];
+    for (int q = 0; q < 3; ++q) {
+      double uq[n];
 #pragma unroll
-    for (int m = 0; m < n; ++m) uq[m] = flam(q, 0) * xb[0][m] + flam(q, 1) * xb[1][m] + flam(q, 2) * xb[2][m];
-    const double* tp = an + (f * 3 + q) * P;
-    const double lw = coef * flam(q, a);
-    int p = 0;
+      for (int m = 0; m < n; ++m) uq[m] = flam(q, 0) * xb[0][m] + flam(q, 1) * xb[1][m] + flam(q, 2) * xb[2][m];
+      const double* tp = an + (f * 3 + q) * P;
+      const double lw = coef * flam(q, a);
+      int p = 0;
 #pragma unroll
-    for (int r = 0; r < n; ++r)
+      for (int r = 0; r < n; ++r)
 #pragma unroll
-      for (int cc = r; cc < n; ++cc) {
-        const double t = lw * tp[p++];
-        o[r] = fma(t, uq[cc], o[r]);
-        if (cc != r) o[cc] = fma(t, uq[r], o[cc]);
-      }
-  }
-  if (resid && v.fh) {
-    const double ni = v.fgeo[f * 4 + i];
+        for (int cc = r; cc < n; ++cc) {
+          const double t = lw * tp[p++];
+          o[r] = fma(t, uq[cc], o[r]);
+          if (cc != r) o[cc] = fma(t, uq[r], o[cc]);
+        }
+    }
+    if (resid && v.fh) {
+      const double ni = v.fgeo[f * 4 + i];
 #pragma unroll
-    for (int m = 0; m < n; ++m) o[m] -= area / 3.0 * v.fh[f * n + m] * ni;
+      for (int m = 0; m < n; ++m) o[m] -= area / 3.0 * v.fh[f * n + m] * ni;
+    }
   }
   double* op = out + (node * 4 + i) * S;
   op[0] += o[0];
@@ -146,26 +150,27 @@ __global__ void k_face_apply(DevView v, const double* __restrict__ Y, int resid,
 }
 
 template <int K>
-__global__ void k_face_diag(DevView v, double* __restrict__ d, int64_t begin, int64_t end) {
+__global__ void k_face_diag(DevView v, double* __restrict__ d) {
   constexpr int n = Dim<K>::n, S = Dim<K>::S, P = Dim<K>::P;
-  const int64_t idx = begin * 3 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= end * 3) return;
-  const int64_t f = idx / 3;
-  const int a = (int)(idx % 3);
-  const int64_t node = v.fconn[f * 3 + a];
-  const double area = v.fgeo[f * 4 + 3];
-  const double coef = -0.5 * v.rho * v.beta * area / 3.0;
+  const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (u >= v.n_fnodes) return;
+  const int64_t node = v.fnode[u];
   double o[n];
 #pragma unroll
   for (int m = 0; m < n; ++m) o[m] = 0.0;
-  for (int q = 0; q < 3; ++q) {
-    const double* tp = v.aneg + (f * 3 + q) * P;
-    const double l = flam(q, a);
-    int p = 0;
+  for (int k = v.foff[u]; k < v.foff[u + 1]; ++k) {
+    const int64_t f = v.finc[k] / 3;
+    const int a = v.finc[k] % 3;
+    const double coef = -0.5 * v.rho * v.beta * v.fgeo[f * 4 + 3] / 3.0;
+    for (int q = 0; q < 3; ++q) {
+      const double* tp = v.aneg + (f * 3 + q) * P;
+      const double l = flam(q, a);
+      int p = 0;
 #pragma unroll
-    for (int r = 0; r < n; ++r) {
-      o[r] += coef * l * l * tp[p];
-      p += n - r;
+      for (int r = 0; r < n; ++r) {
+        o[r] += coef * l * l * tp[p];
+        p += n - r;
+      }
     }
   }
 #pragma unroll
@@ -197,11 +202,11 @@ hipError_t launch_face_lin(const DevView& v, const double* UTs, double* aneg, hi
 }
 
 hipError_t launch_face_apply(const DevView& v, const double* Y, int resid, const double* an,
-                             double* out, int64_t begin, int64_t end, hipStream_t st) {
-  if (end <= begin) return hipSuccess;
-  const unsigned grid = (unsigned)(((end - begin) * 9 + 127) / 128);
+                             double* out, hipStream_t st) {
+  if (v.n_fnodes == 0) return hipSuccess;
+  const unsigned grid = (unsigned)((v.n_fnodes * 3 + 127) / 128);
   switch (v.K) {
-#define CASE(k) case k: k_face_apply<k><<<grid, 128, 0, st>>>(v, Y, resid, an, out, begin, end); break;
+#define CASE(k) case k: k_face_apply<k><<<grid, 128, 0, st>>>(v, Y, resid, an, out); break;
     TSGLS_FOR_EACH_K(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -209,11 +214,11 @@ hipError_t launch_face_apply(const DevView& v, const double* Y, int resid, const
   return hipGetLastError();
 }
 
-hipError_t launch_face_diag(const DevView& v, double* d, int64_t begin, int64_t end, hipStream_t st) {
-  if (end <= begin) return hipSuccess;
-  const unsigned grid = (unsigned)(((end - begin) * 3 + 127) / 128);
+hipError_t launch_face_diag(const DevView& v, double* d, hipStream_t st) {
+  if (v.n_fnodes == 0) return hipSuccess;
+  const unsigned grid = (unsigned)((v.n_fnodes + 127) / 128);
   switch (v.K) {
-#define CASE(k) case k: k_face_diag<k><<<grid, 128, 0, st>>>(v, d, begin, end); break;
+#define CASE(k) case k: k_face_diag<k><<<grid, 128, 0, st>>>(v, d); break;
     TSGLS_FOR_EACH_K(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;

@@ -22,9 +22,13 @@ struct tsgls_ctx {
   hipStream_t st = nullptr;
   int K = 0, n = 1, S = 2, M = 1, P = 1;
   int64_t nn = 0, E = 0, nf = 0;
-  std::vector<int64_t> coff;    // colour offsets, elements
-  std::vector<int64_t> fcoff;   // colour offsets, faces
-  std::vector<int32_t> perm;    // sorted position -> input element index
+  std::vector<int32_t> perm;    // processing position -> input element index (Morton order)
+  int TE = 1;                   // elements per tile (tau / Z layout)
+  int64_t n_tiles = 0;
+  int32_t* tslot = nullptr;     // [E] storage slot per element
+  int32_t* noff = nullptr;      // [n_nodes+1] CSR offsets: node -> incident element slots
+  int32_t* ninc = nullptr;      // [4E] incident (element*4 + local node), ascending element
+  double* ebuf = nullptr;       // [E][4][4][2K+2] per-element contributions
   std::vector<double> hxyz;     // host copy of the coordinates (face geometry)
   int32_t* conn = nullptr;
   double* geo = nullptr;
@@ -36,6 +40,10 @@ struct tsgls_ctx {
   double* Z = nullptr;
   double* rs = nullptr;         // scratch residual for linearize
   int32_t* fconn = nullptr;
+  int64_t n_fnodes = 0;
+  int32_t* fnode = nullptr;
+  int32_t* foff = nullptr;
+  int32_t* finc = nullptr;
   double* fgeo = nullptr;
   double* fh = nullptr;
   double* aneg = nullptr;
@@ -53,6 +61,11 @@ struct tsgls_ctx {
   double* partial = nullptr;
   double* dh = nullptr;
   bool linearized = false;
+  // optional per-launch timing with HIP events (benchmark support)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_recs;
   size_t dev_bytes = 0;
   std::vector<void*> allocs;
   std::string err;
@@ -103,29 +116,19 @@ void dfree(tsgls_ctx* c, void* p) {
   (void)hipFree(p);
 }
 
-// Greedy colouring in the given order: an item gets the lowest colour not
-// used by an already coloured item that shares a node.
-int colour(tsgls_ctx* c, const int32_t* items, int64_t count, int per, int64_t nn,
-           std::vector<int32_t>& col, int& ncol) {
-  constexpr int W = 8;  // up to 512 colours
-  std::vector<uint64_t> used((size_t)nn * W, 0);
-  col.assign(count, 0);
-  ncol = 0;
-  for (int64_t e = 0; e < count; ++e) {
-    uint64_t m[W] = {0};
-    for (int b = 0; b < per; ++b) {
-      const uint64_t* u = &used[(size_t)items[e * per + b] * W];
-      for (int w = 0; w < W; ++w) m[w] |= u[w];
-    }
-    int cidx = -1;
-    for (int w = 0; w < W && cidx < 0; ++w)
-      if (~m[w]) cidx = w * 64 + __builtin_ctzll(~m[w]);
-    if (cidx < 0) return fail(c, TSGLS_EMESH, "more than %d colours needed", W * 64);
-    col[e] = cidx;
-    ncol = std::max(ncol, cidx + 1);
-    for (int b = 0; b < per; ++b) used[(size_t)items[e * per + b] * W + cidx / 64] |= 1ull << (cidx % 64);
-  }
-  return TSGLS_OK;
+// Morton (Z-order) key of a point in the unit cube, 21 bits per axis.
+uint64_t morton3(double x, double y, double z) {
+  auto spread = [](uint64_t v) {
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffull;
+    v = (v | v << 16) & 0x1f0000ff0000ffull;
+    v = (v | v << 8) & 0x100f00f00f00f00full;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+    v = (v | v << 2) & 0x1249249249249249ull;
+    return v;
+  };
+  auto q = [](double t) { return (uint64_t)std::min(2097151.0, std::max(0.0, t * 2097151.0)); };
+  return spread(q(x)) | spread(q(y)) << 1 | spread(q(z)) << 2;
 }
 
 DevView view(const tsgls_ctx* c) {
@@ -141,7 +144,15 @@ DevView view(const tsgls_ctx* c) {
   v.UT = c->UT;
   v.tau = c->tau;
   v.Z = c->Z;
+  v.tslot = c->tslot;
+  v.TE = c->TE;
+  v.noff = c->noff;
+  v.ninc = c->ninc;
   v.fconn = c->fconn;
+  v.n_fnodes = c->n_fnodes;
+  v.fnode = c->fnode;
+  v.foff = c->foff;
+  v.finc = c->finc;
   v.fgeo = c->fgeo;
   v.fh = c->fh;
   v.aneg = c->aneg;
@@ -155,23 +166,65 @@ DevView view(const tsgls_ctx* c) {
 
 int64_t ndof(const tsgls_ctx* c) { return c->nn * 4 * c->S; }
 
+hipEvent_t next_event(tsgls_ctx* c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
+// Records an event pair around one launch when profiling is on.
+struct ProfScope {
+  tsgls_ctx* c;
+  int which;
+  hipEvent_t b = nullptr;
+  ProfScope(tsgls_ctx* ctx, int w) : c(ctx), which(w) {
+    if (c->prof) {
+      b = next_event(c);
+      if (b) (void)hipEventRecord(b, c->st);
+    }
+  }
+  ~ProfScope() {
+    if (c->prof && b) {
+      hipEvent_t e = next_event(c);
+      if (e) {
+        (void)hipEventRecord(e, c->st);
+        c->prof_recs.push_back({which, {b, e}});
+      }
+    }
+  }
+};
+
 // Volume + face terms of the operator; out must be zeroed by the caller.
 int apply_operator(tsgls_ctx* c, const DevView& v, int mode, const double* Y, const double* VTp,
                    double* Zout, double* out, double shift, const double* an, int resid) {
-  for (size_t k = 0; k + 1 < c->coff.size(); ++k)
-    HIPCHK(c, launch_elem(v, mode, Y, VTp, Zout, out, shift, c->coff[k], c->coff[k + 1], c->st));
-  for (size_t k = 0; k + 1 < c->fcoff.size(); ++k)
-    HIPCHK(c, launch_face_apply(v, Y, resid, an, out, c->fcoff[k], c->fcoff[k + 1], c->st));
+  const int which = (mode & MODE_RESID) ? TSGLS_PROF_ELEM_RESIDUAL : TSGLS_PROF_ELEM_TANGENT;
+  {
+    ProfScope ps(c, which);
+    HIPCHK(c, launch_elem(v, mode, Y, VTp, Zout, c->ebuf, shift, 0, c->E, 0, c->st));
+  }
+  {
+    ProfScope ps(c, TSGLS_PROF_GATHER);
+    HIPCHK(c, launch_gather(c->K, c->noff, c->ninc, c->ebuf, out, c->nn, c->st));
+  }
+  if (c->nf) {
+    ProfScope ps(c, TSGLS_PROF_FACE);
+    HIPCHK(c, launch_face_apply(v, Y, resid, an, out, c->st));
+  }
   return TSGLS_OK;
 }
 
 int linearize_impl(tsgls_ctx* c, const double* y, double* r) {
   DevView v = view(c);
   HIPCHK(c, launch_prep_time(c->K, y, c->nflag, 0, c->F, c->UT, c->nn, c->st));
-  HIPCHK(c, launch_tau(v, y, c->tau, c->st));
+  {
+    ProfScope ps(c, TSGLS_PROF_TAU);
+    HIPCHK(c, launch_tau(v, y, c->tau, c->st));
+  }
   HIPCHK(c, launch_face_lin(v, c->UT, c->aneg, c->st));
   double* rr = r ? r : c->rs;
-  HIPCHK(c, launch_zero(rr, ndof(c), c->st));
   CHK(apply_operator(c, v, MODE_RESID | MODE_STOREZ, y, nullptr, c->Z, rr, 0.0, c->aneg, 1));
   c->linearized = true;
   return TSGLS_OK;
@@ -183,7 +236,6 @@ int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt) {
   const int mode = jac == TSGLS_JAC_PICARD ? 0 : jac == TSGLS_JAC_PICARD_NOLS ? MODE_NOLS : MODE_NEWTON;
   const double shift = dt > 0 ? 1.5 * c->p.rho / dt : 0.0;
   HIPCHK(c, launch_prep_time(c->K, x, c->nflag, 1, c->F, c->VT, c->nn, c->st));
-  HIPCHK(c, launch_zero(out, ndof(c), c->st));
   return apply_operator(c, v, mode, x, c->VT, nullptr, out, shift, c->aneg, 0);
 }
 
@@ -191,11 +243,12 @@ int diag_impl(tsgls_ctx* c, double* d, double dt) {
   if (!c->linearized) return fail(c, TSGLS_ESTATE, "jacobi_diag before linearize");
   DevView v = view(c);
   const double shift = dt > 0 ? 1.5 * c->p.rho / dt : 0.0;
-  HIPCHK(c, launch_zero(d, ndof(c), c->st));
-  for (size_t k = 0; k + 1 < c->coff.size(); ++k)
-    HIPCHK(c, launch_diag(v, d, shift, c->coff[k], c->coff[k + 1], c->st));
-  for (size_t k = 0; k + 1 < c->fcoff.size(); ++k)
-    HIPCHK(c, launch_face_diag(v, d, c->fcoff[k], c->fcoff[k + 1], c->st));
+  {
+    ProfScope ps(c, TSGLS_PROF_DIAG);
+    HIPCHK(c, launch_diag(v, c->ebuf, shift, 0, c->E, c->st));
+  }
+  HIPCHK(c, launch_gather(c->K, c->noff, c->ninc, c->ebuf, d, c->nn, c->st));
+  if (c->nf) HIPCHK(c, launch_face_diag(v, d, c->st));
   HIPCHK(c, launch_diag_finish(c->K, c->nflag, d, c->nn, c->st));
   return TSGLS_OK;
 }
@@ -282,10 +335,13 @@ int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv
       HIPCHK(c, launch_mul(c->minv, Vj, c->kt, n, c->st));
       CHK(jv_impl(c, c->kt, Vn, jac, dt));
       ++mv;
-      CHK(multidot(c, c->V, n, j + 1, Vn, c->dh, h.data()));
-      HIPCHK(c, launch_multiaxpy(c->V, n, j + 1, c->dh, Vn, n, c->st));
-      CHK(multidot(c, c->V, n, j + 1, Vn, c->dh, h2.data()));
-      HIPCHK(c, launch_multiaxpy(c->V, n, j + 1, c->dh, Vn, n, c->st));
+      {
+        ProfScope ps(c, TSGLS_PROF_ORTHO);
+        CHK(multidot(c, c->V, n, j + 1, Vn, c->dh, h.data()));
+        HIPCHK(c, launch_multiaxpy(c->V, n, j + 1, c->dh, Vn, n, c->st));
+        CHK(multidot(c, c->V, n, j + 1, Vn, c->dh, h2.data()));
+        HIPCHK(c, launch_multiaxpy(c->V, n, j + 1, c->dh, Vn, n, c->st));
+      }
       for (int i = 0; i <= j; ++i) h[i] += h2[i];
       double hn;
       CHK(norm2(c, Vn, &hn));
@@ -368,18 +424,42 @@ int tsgls_create(const double* xyz, int64_t n_nodes, const int32_t* tets, int64_
                        d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
     if (!(det > 0)) return fail(c, TSGLS_EMESH, "tet %lld has non-positive volume", (long long)e);
   }
-  std::vector<int32_t> col;
-  int ncol = 0;
-  CHK(colour(c, tets, n_tets, 4, n_nodes, col, ncol));
-  c->perm.resize(n_tets);
-  for (int64_t e = 0; e < n_tets; ++e) c->perm[e] = (int32_t)e;
-  std::stable_sort(c->perm.begin(), c->perm.end(), [&](int32_t a, int32_t b) { return col[a] < col[b]; });
-  c->coff.assign(ncol + 1, 0);
-  for (int64_t e = 0; e < n_tets; ++e) c->coff[col[e] + 1]++;
-  for (int k = 0; k < ncol; ++k) c->coff[k + 1] += c->coff[k];
+  // processing order: Morton order of the element centroids (locality of the
+  // node gathers); contributions are summed per node afterwards in a fixed order
+  {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < n_nodes; ++i)
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = std::min(lo[d], xyz[i * 3 + d]);
+        hi[d] = std::max(hi[d], xyz[i * 3 + d]);
+      }
+    std::vector<uint64_t> key(n_tets);
+    for (int64_t e = 0; e < n_tets; ++e) {
+      double cc[3] = {0, 0, 0};
+      for (int b = 0; b < 4; ++b)
+        for (int d = 0; d < 3; ++d) cc[d] += 0.25 * xyz[(int64_t)tets[e * 4 + b] * 3 + d];
+      for (int d = 0; d < 3; ++d) cc[d] = (cc[d] - lo[d]) / std::max(hi[d] - lo[d], 1e-300);
+      key[e] = morton3(cc[0], cc[1], cc[2]);
+    }
+    c->perm.resize(n_tets);
+    for (int64_t e = 0; e < n_tets; ++e) c->perm[e] = (int32_t)e;
+    std::stable_sort(c->perm.begin(), c->perm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+  }
+  c->TE = tile_elems(K);
+  c->n_tiles = (n_tets + c->TE - 1) / c->TE;
+  std::vector<int32_t> slot(n_tets);
+  for (int64_t e = 0; e < n_tets; ++e) slot[e] = (int32_t)e;
   std::vector<int32_t> sconn(n_tets * 4);
   for (int64_t e = 0; e < n_tets; ++e)
     for (int b = 0; b < 4; ++b) sconn[e * 4 + b] = tets[(int64_t)c->perm[e] * 4 + b];
+  // node -> incident (element, local node) in ascending element order
+  std::vector<int32_t> noff(n_nodes + 1, 0), ninc(n_tets * 4);
+  for (int64_t k = 0; k < n_tets * 4; ++k) noff[sconn[k] + 1]++;
+  for (int64_t i = 0; i < n_nodes; ++i) noff[i + 1] += noff[i];
+  {
+    std::vector<int32_t> fill(noff.begin(), noff.end() - 1);
+    for (int64_t k = 0; k < n_tets * 4; ++k) ninc[fill[sconn[k]]++] = (int32_t)k;
+  }
   // device data
   double* dxyz = nullptr;
   CHK(dalloc(c, &dxyz, n_nodes * 3));
@@ -389,11 +469,18 @@ int tsgls_create(const double* xyz, int64_t n_nodes, const int32_t* tets, int64_
   CHK(dalloc(c, &c->F, (size_t)c->n * c->M));
   CHK(dalloc(c, &c->UT, n_nodes * 3 * c->M));
   CHK(dalloc(c, &c->VT, n_nodes * 3 * c->M));
-  CHK(dalloc(c, &c->tau, (size_t)n_tets * 4 * c->P));
-  CHK(dalloc(c, &c->Z, (size_t)n_tets * 12 * c->n));
+  CHK(dalloc(c, &c->tau, (size_t)c->n_tiles * c->TE * 4 * c->P));
+  CHK(dalloc(c, &c->Z, (size_t)c->n_tiles * c->TE * 12 * c->n));
+  CHK(dalloc(c, &c->tslot, n_tets));
+  CHK(dalloc(c, &c->noff, n_nodes + 1));
+  CHK(dalloc(c, &c->ninc, n_tets * 4));
+  CHK(dalloc(c, &c->ebuf, (size_t)n_tets * 16 * c->S));
   CHK(dalloc(c, &c->rs, n_nodes * 4 * c->S));
   HIPCHK(c, hipMemcpyAsync(dxyz, xyz, n_nodes * 3 * sizeof(double), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->conn, sconn.data(), n_tets * 4 * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->tslot, slot.data(), n_tets * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->noff, noff.data(), noff.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->ninc, ninc.data(), ninc.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemsetAsync(c->nflag, 0, n_nodes, c->st));
   std::vector<double> F((size_t)c->n * c->M);
   const double pi = 3.14159265358979323846;
@@ -410,7 +497,6 @@ int tsgls_create(const double* xyz, int64_t n_nodes, const int32_t* tets, int64_
   HIPCHK(c, hipStreamSynchronize(c->st));
   dfree(c, dxyz);
   c->dev_bytes -= n_nodes * 3 * sizeof(double);
-  c->fcoff.assign(1, 0);
   return TSGLS_OK;
 }
 
@@ -435,10 +521,13 @@ int tsgls_set_neumann(tsgls_ctx* c, const int32_t* tris, int64_t nf, const doubl
   dfree(c, c->fh);
   dfree(c, c->aneg);
   dfree(c, c->anegr);
-  c->fconn = nullptr;
+  dfree(c, c->fnode);
+  dfree(c, c->foff);
+  dfree(c, c->finc);
+  c->fconn = c->fnode = c->foff = c->finc = nullptr;
   c->fgeo = c->fh = c->aneg = c->anegr = nullptr;
   c->nf = 0;
-  c->fcoff.assign(1, 0);
+  c->n_fnodes = 0;
   c->linearized = false;
   if (nf == 0) return TSGLS_OK;
   std::vector<double> fg(nf * 4);
@@ -462,21 +551,34 @@ int tsgls_set_neumann(tsgls_ctx* c, const int32_t* tris, int64_t nf, const doubl
     for (int i = 0; i < 3; ++i) fg[f * 4 + i] = nv[i] / nn;
     fg[f * 4 + 3] = 0.5 * nn;
   }
-  std::vector<int32_t> col;
-  int ncol = 0;
-  CHK(colour(c, tris, nf, 3, c->nn, col, ncol));
+  // node -> incident (face, local vertex) lists, ascending face order
+  std::vector<int32_t> fnode(tris, tris + nf * 3);
+  std::sort(fnode.begin(), fnode.end());
+  fnode.erase(std::unique(fnode.begin(), fnode.end()), fnode.end());
+  std::vector<int32_t> foff(fnode.size() + 1, 0), finc(nf * 3);
+  for (int64_t k = 0; k < nf * 3; ++k) {
+    const int64_t u = std::lower_bound(fnode.begin(), fnode.end(), tris[k]) - fnode.begin();
+    foff[u + 1]++;
+  }
+  for (size_t u = 0; u < fnode.size(); ++u) foff[u + 1] += foff[u];
+  {
+    std::vector<int32_t> fill(foff.begin(), foff.end() - 1);
+    for (int64_t k = 0; k < nf * 3; ++k) {
+      const int64_t u = std::lower_bound(fnode.begin(), fnode.end(), tris[k]) - fnode.begin();
+      finc[fill[u]++] = (int32_t)k;
+    }
+  }
+  std::vector<int32_t> sc(tris, tris + nf * 3);
+  std::vector<double> sg = fg, sh;
   std::vector<int32_t> perm(nf);
   for (int64_t f = 0; f < nf; ++f) perm[f] = (int32_t)f;
-  std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return col[a] < col[b]; });
-  c->fcoff.assign(ncol + 1, 0);
-  for (int64_t f = 0; f < nf; ++f) c->fcoff[col[f] + 1]++;
-  for (int k = 0; k < ncol; ++k) c->fcoff[k + 1] += c->fcoff[k];
-  std::vector<int32_t> sc(nf * 3);
-  std::vector<double> sg(nf * 4), sh;
-  for (int64_t f = 0; f < nf; ++f) {
-    for (int b = 0; b < 3; ++b) sc[f * 3 + b] = tris[(int64_t)perm[f] * 3 + b];
-    for (int i = 0; i < 4; ++i) sg[f * 4 + i] = fg[(int64_t)perm[f] * 4 + i];
-  }
+  c->n_fnodes = (int64_t)fnode.size();
+  CHK(dalloc(c, &c->fnode, fnode.size()));
+  CHK(dalloc(c, &c->foff, foff.size()));
+  CHK(dalloc(c, &c->finc, finc.size()));
+  HIPCHK(c, hipMemcpyAsync(c->fnode, fnode.data(), fnode.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->foff, foff.data(), foff.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->finc, finc.data(), finc.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
   CHK(dalloc(c, &c->fconn, nf * 3));
   CHK(dalloc(c, &c->fgeo, nf * 4));
   CHK(dalloc(c, &c->aneg, (size_t)nf * 3 * c->P));
@@ -503,7 +605,7 @@ int tsgls_residual(tsgls_ctx* c, const double* y, double* r) {
   if (!y || !r) return fail(c, TSGLS_EINVAL, "null vector");
   if (!c->UTr) {
     CHK(dalloc(c, &c->UTr, c->nn * 3 * c->M));
-    CHK(dalloc(c, &c->taur, (size_t)c->E * 4 * c->P));
+    CHK(dalloc(c, &c->taur, (size_t)c->n_tiles * c->TE * 4 * c->P));
   }
   if (c->nf && !c->anegr) CHK(dalloc(c, &c->anegr, (size_t)c->nf * 3 * c->P));
   DevView v = view(c);
@@ -540,12 +642,15 @@ int tsgls_get_tau(tsgls_ctx* c, double* tau_out) {
   if (!c) return TSGLS_EINVAL;
   if (!tau_out) return fail(c, TSGLS_EINVAL, "null pointer");
   if (!c->linearized) return fail(c, TSGLS_ESTATE, "get_tau before linearize");
-  const size_t per = (size_t)4 * c->P;
-  std::vector<double> buf((size_t)c->E * per);
+  std::vector<double> buf((size_t)c->n_tiles * c->TE * 4 * c->P);
+  std::vector<int32_t> slot(c->E);
   HIPCHK(c, hipMemcpyAsync(buf.data(), c->tau, buf.size() * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(slot.data(), c->tslot, slot.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
   for (int64_t e = 0; e < c->E; ++e)
-    std::memcpy(tau_out + (size_t)c->perm[e] * per, buf.data() + (size_t)e * per, per * sizeof(double));
+    for (int q = 0; q < 4; ++q)
+      for (int p = 0; p < c->P; ++p)
+        tau_out[((size_t)c->perm[e] * 4 + q) * c->P + p] = buf[tau_index(slot[e], q, p, c->P, c->TE)];
   return TSGLS_OK;
 }
 
@@ -602,10 +707,36 @@ int tsgls_solve(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_
 int tsgls_info(const tsgls_ctx* c, int64_t* n_colors, int64_t* n_tets, int64_t* n_nodes,
                int64_t* device_bytes) {
   if (!c) return TSGLS_EINVAL;
-  if (n_colors) *n_colors = (int64_t)c->coff.size() - 1;
+  if (n_colors) *n_colors = 1;   // one element launch per operator application
   if (n_tets) *n_tets = c->E;
   if (n_nodes) *n_nodes = c->nn;
   if (device_bytes) *device_bytes = (int64_t)c->dev_bytes;
+  return TSGLS_OK;
+}
+
+int tsgls_profile(tsgls_ctx* c, int enable) {
+  if (!c) return TSGLS_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->prof = enable != 0;
+  c->prof_recs.clear();
+  c->ev_used = 0;
+  return TSGLS_OK;
+}
+
+int tsgls_profile_get(tsgls_ctx* c, int which, int64_t* launches, double* total_ms) {
+  if (!c || !launches || !total_ms) return TSGLS_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  int64_t cnt = 0;
+  double tot = 0.0;
+  for (auto& r : c->prof_recs) {
+    if (r.first != which) continue;
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, r.second.first, r.second.second));
+    tot += ms;
+    ++cnt;
+  }
+  *launches = cnt;
+  *total_ms = tot;
   return TSGLS_OK;
 }
 
@@ -616,6 +747,7 @@ void tsgls_destroy(tsgls_ctx* c) {
   if (c->st) (void)hipStreamSynchronize(c->st);
   else (void)hipDeviceSynchronize();
   for (void* p : c->allocs) (void)hipFree(p);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
 }
 

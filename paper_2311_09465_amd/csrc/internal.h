@@ -6,6 +6,17 @@
 
 namespace tsgls {
 
+// Storage layout of the per-quadrature-point tau (packed, P entries) and of
+// tau L(u) (n modes per (qp, component) row): tiles of TE elements with the
+// tile's points interleaved innermost, so that the threads of one tile read
+// consecutive addresses.  slot = tile * TE + element-in-tile.
+__host__ __device__ __forceinline__ int64_t tau_index(int64_t slot, int q, int p, int P, int TE) {
+  return ((slot / TE) * P + p) * (int64_t)(TE * 4) + (slot % TE) * 4 + q;
+}
+__host__ __device__ __forceinline__ int64_t z_index(int64_t slot, int row, int a, int n, int TE) {
+  return ((slot / TE) * n + a) * (int64_t)(TE * 12) + (slot % TE) * 12 + row;
+}
+
 // Element-operator modes (compile-time flags of the element kernel).
 enum : int {
   MODE_RESID = 1,    // input is the state: A built from it, no input mask
@@ -23,17 +34,26 @@ struct DevView {
   const uint8_t* nflag;      // [n_nodes] bit0: velocity Dirichlet
   const double* F;           // [n][M] phi_a(t_s), real orthonormal basis
   const double* UT;          // [n_nodes][3][M] frozen velocity samples
-  const double* tau;         // [E][4][P] packed tau (colour-sorted order)
-  const double* Z;           // [E][4][3][n] tau L(u) modal (Newton tangent)
-  const int32_t* fconn;      // [nf][3] Neumann faces, colour-sorted
+  const double* tau;         // packed tau, tile-interleaved (tau_index)
+  const double* Z;           // tau L(u) modal, tile-interleaved (z_index)
+  const int32_t* tslot;      // [E] storage slot of each (colour-sorted) element
+  int TE;                    // elements per tile of the element kernel
+  const int32_t* noff;       // [n_nodes+1] node -> incident element slots
+  const int32_t* ninc;       // element*4 + local node, ascending element
+  const int32_t* fconn;      // [nf][3] Neumann faces
+  int64_t n_fnodes;          // distinct nodes of the Neumann faces
+  const int32_t* fnode;      // [n_fnodes] node ids
+  const int32_t* foff;       // [n_fnodes+1] CSR offsets into finc
+  const int32_t* finc;       // incident (face*3 + local vertex), ascending
   const double* fgeo;        // [nf][4] unit outward normal, area
   const double* fh;          // [nf][n] traction modes (real basis) or null
   const double* aneg;        // [nf][3][P] |A_n|_- packed per face point
   double rho, mu, omega, C_I, beta;
 };
 
-// Launchers (return hipError_t of the launch).  Colour ranges are
-// [begin, end) in the colour-sorted element / face order.
+// Launchers (return hipError_t of the launch).  Element ranges [begin, end)
+// are in processing (Morton) order; element kernels write per-element
+// contributions [E][4 nodes][4 fields][S] that launch_gather sums per node.
 hipError_t launch_geometry(const double* xyz, const int32_t* conn, double* geo,
                            int* bad, int64_t n_tets, hipStream_t st);
 hipError_t launch_prep_time(int K, const double* Y, const uint8_t* nflag,
@@ -44,16 +64,21 @@ hipError_t launch_tau(const DevView& v, const double* Y, double* tau,
 hipError_t launch_elem(const DevView& v, int mode, const double* Y,
                        const double* VT, double* Zout, double* out,
                        double shift, int64_t begin, int64_t end,
-                       hipStream_t st);
+                       int64_t tile_off, hipStream_t st);
+// Elements per tile for K harmonics (fixes the tau / Z storage layout).
+int tile_elems(int K);
 hipError_t launch_diag(const DevView& v, double* d, double shift,
                        int64_t begin, int64_t end, hipStream_t st);
+// out[node][4][S] = sum over incident (element, local node) of ebuf, in
+// ascending element order (deterministic).
+hipError_t launch_gather(int K, const int32_t* noff, const int32_t* ninc,
+                         const double* ebuf, double* out, int64_t n_nodes,
+                         hipStream_t st);
 hipError_t launch_face_lin(const DevView& v, const double* Y, double* aneg,
                            hipStream_t st);
 hipError_t launch_face_apply(const DevView& v, const double* Y, int resid,
-                             const double* aneg, double* out, int64_t begin,
-                             int64_t end, hipStream_t st);
-hipError_t launch_face_diag(const DevView& v, double* d, int64_t begin,
-                            int64_t end, hipStream_t st);
+                             const double* aneg, double* out, hipStream_t st);
+hipError_t launch_face_diag(const DevView& v, double* d, hipStream_t st);
 hipError_t launch_diag_finish(int K, const uint8_t* nflag, double* d,
                               int64_t n_nodes, hipStream_t st);
 bool supported_K(int K);

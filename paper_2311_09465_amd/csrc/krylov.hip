@@ -113,16 +113,25 @@ hipError_t launch_multidot(const double* V, int64_t ldv, int J, const double* w,
   return hipGetLastError();
 }
 
-__global__ void k_reduce_partials(const double* __restrict__ partial, int nb, int J, double* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= J) return;
+// One block per output j: strided partial sums over the blocks' partials in
+// a fixed assignment, then a fixed-order tree in LDS.
+__global__ void __launch_bounds__(256)
+k_reduce_partials(const double* __restrict__ partial, int nb, int J, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int j = blockIdx.x, t = threadIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * J + j];
-  out[j] = s;
+  for (int b = t; b < nb; b += 256) s += partial[(int64_t)b * J + j];
+  red[t] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (t < k) red[t] += red[t + k];
+    __syncthreads();
+  }
+  if (t == 0) out[j] = red[0];
 }
 
 hipError_t launch_reduce_partials(const double* partial, int nblocks, int J, double* out, hipStream_t st) {
-  k_reduce_partials<<<(J + 127) / 128, 128, 0, st>>>(partial, nblocks, J, out);
+  k_reduce_partials<<<J, 256, 0, st>>>(partial, nblocks, J, out);
   return hipGetLastError();
 }
 
