@@ -150,6 +150,17 @@ __device__ __forceinline__ double group_sum(double x) {
   return x;
 }
 
+// Workgroups are handed to the 8 XCDs of the chip round-robin by block id.
+// xcd_block maps block id b of a grid of nb blocks to a logical block so that
+// each XCD works on one contiguous range of logical blocks: elements that
+// share nodes then share that XCD's L2.  A bijection on [0, nb).
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  constexpr int NX = 8;
+  const int64_t x = b % NX, j = b / NX;
+  const int64_t q = nb / NX, r = nb % NX;
+  return x < r ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
+}
+
 constexpr int np_of(int n) {
   return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : n <= 8 ? 8 : n <= 16 ? 16 : n <= 32 ? 32 : 64;
 }

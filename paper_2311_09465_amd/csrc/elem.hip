@@ -112,7 +112,7 @@ k_tau(DevView v, const double* __restrict__ Y, double* __restrict__ tau) {
   constexpr SampleTable<K> TB{};
   const int g = threadIdx.x / NP;
   const int c = threadIdx.x % NP;
-  const int64_t gq = (int64_t)blockIdx.x * GB + g;
+  const int64_t gq = xcd_block(blockIdx.x, gridDim.x) * GB + g;
   const int64_t e = gq >> 2;
   const int q = (int)(gq & 3);
   const bool valid = e < v.n_tets;
@@ -296,7 +296,7 @@ k_elem(DevView v, const double* __restrict__ Y, const double* __restrict__ VT,
   (void)end;
   (void)tile_off;
   const int lane = threadIdx.x;
-  const int64_t e = begin + blockIdx.x;
+  const int64_t e = begin + xcd_block(blockIdx.x, gridDim.x);
   const double rho = v.rho, omega = v.omega;
 
   // element data (uniform across the wave)
@@ -612,7 +612,7 @@ template <int K>
 __global__ void __launch_bounds__(128)
 k_diag(DevView v, double* __restrict__ d, double shift, int64_t begin, int64_t end) {
   constexpr int n = Dim<K>::n, M = Dim<K>::M, S = Dim<K>::S, P = Dim<K>::P;
-  const int64_t idx = begin * 4 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t idx = begin * 4 + xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= end * 4) return;
   const int64_t e = idx >> 2;
   const int b = (int)(idx & 3);
