@@ -1,0 +1,542 @@
+// gfx950 element operator of the GLS method: residual of eq. Rmc and the
+// tangent products of eq. tangent / eq. K_mat, element by element on linear
+// tetrahedra with the 4-point rule (weights V/4).
+//
+// One element at a time per 64-lane wave; each wave loops over a contiguous
+// Morton range of elements (the ranges are split per XCD so that elements
+// sharing nodes share an L2).  Every phase uses a lane layout fixed for the
+// whole kernel, so all index arithmetic is done once per wave and LDS
+// addresses are a per-lane base plus compile-time offsets.  Lane l has
+// g = l / 16 and c = l % 16; "positions" p = c + 16 pt index the modes
+// (pos_mode), so the two modes of one harmonic are on lanes c and c ^ 1.
+//
+//   products   lane (s, i), s < M sample, i < 3 component:
+//              conv_{q,i}(t_s) = u_q(t_s) . grad du_i(t_s) for the 4 points
+//              (+ du_q . grad u_i for the Newton tangent)
+//   to modes   MFMA 16x16x4: rows i*4+q, k = samples  ->  lane (q=g, p), reg i
+//   modal      lane (q, p): L_i = rho (Omega du_i + conv_i) + d_i p;
+//              z_i = tau_q L_i with tau_q's row p from LDS, L broadcast
+//   to samples MFMA: rows q*4+i, k = positions  ->  lane (i=g, s), reg q
+//   LS         lane (s, i): W_ji(t_s) = w sum_q u_{q,j} z_{q,i}
+//   to modes   MFMA: rows j*4+i  ->  lane (i=g, p), reg j
+//   assembly   lane (f=g, p), reg b: Galerkin, viscous, pressure, LS and
+//              PSPG terms; one store per node row to the element buffer.
+#include "common.cuh"
+#include "internal.h"
+
+namespace tsgls {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <int K>
+struct OpCfg {
+  static constexpr int n = 2 * K + 1, M = 3 * K + 1, S = 2 * K + 2, P = n * (n + 1) / 2;
+  static constexpr int PW = (n + 15) / 16 * 16;   // positions per field row
+  static constexpr int NPT = PW / 16;             // position tiles
+  static constexpr int MS = (M + 3) / 4 * 4;      // samples padded to the MFMA k step
+  static constexpr int NKB = MS / 4;              // k steps, samples -> modes
+  static constexpr int MT = (M + 15) / 16;        // sample tiles, modes -> samples
+  static constexpr int NKF = (n + 3) / 4;         // k steps, modes -> samples
+  static constexpr int NPR = (3 * M + 63) / 64;   // passes over (sample, component)
+  static constexpr int NTL = (P + 63) / 64;       // loads per packed tau block
+  static constexpr bool KEEPU = NPR == 1;         // keep u_q(t_s) in registers
+};
+
+// Value of lane l ^ 1 (quad permutation 1,0,3,2).
+__device__ __forceinline__ double swap_pair(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+template <int K, int MODE>
+__global__ void __launch_bounds__(64)
+k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
+     double* __restrict__ Zout, double* __restrict__ out, double shift, int64_t begin,
+     int64_t end) {
+  using C = OpCfg<K>;
+  constexpr int n = C::n, M = C::M, S = C::S, P = C::P, PW = C::PW, NPT = C::NPT;
+  constexpr int MS = C::MS, NKB = C::NKB, MT = C::MT, NKF = C::NKF, NPR = C::NPR, NTL = C::NTL;
+  constexpr bool RESID = (MODE & MODE_RESID) != 0;
+  constexpr bool NEWTON = (MODE & MODE_NEWTON) != 0;
+  constexpr bool NOLS = (MODE & MODE_NOLS) != 0;
+  constexpr bool STOREZ = (MODE & MODE_STOREZ) != 0;
+  constexpr bool KEEPU = C::KEEPU;
+  constexpr int NL = NOLS ? 2 : 1;
+
+  __shared__ double sV[16 * PW];               // modes [node][field][position]
+  __shared__ double sT[4 * n * n];             // tau_q rows [q][position][position]
+  __shared__ double sL[NL * 12 * PW];          // L [q][i][position] (+ grad p part), then G
+  __shared__ double sC[16 * MS];               // conv(t) / z(t) staging [16][M] / W(t)
+  __shared__ double sZ[NL * 16 * PW];          // z [q*4+i][position] (+ tau grad p)
+  __shared__ double sZf[NEWTON ? 16 * PW : 1];    // stored tau L(u) [q*4+i][position]
+  __shared__ double sZft[NEWTON ? 16 * M : 1];    // its samples [i*4+q][s]
+  __shared__ double sWq[NEWTON ? 12 * M : 1];     // direction at the points [q][j][s]
+
+  const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
+  const double rho = v.rho, mu = v.mu, omega = v.omega;
+  const double* __restrict__ F = v.F;
+  const double* __restrict__ UT = v.UT;
+
+  // ---- per-lane constants (once per wave)
+  double Bb[NKB][NPT];   // B[k = s][col = position] = phi(t_s) / M
+  double Bf[NKF][MT];    // B[k = position][col = s] = phi(t_s)
+#pragma unroll
+  for (int ks = 0; ks < NKB; ++ks)
+#pragma unroll
+    for (int pt = 0; pt < NPT; ++pt) {
+      const int s = ks * 4 + g, a = pos_mode(c + 16 * pt, K);
+      Bb[ks][pt] = (s < M && a >= 0) ? F[a * M + s] * (1.0 / M) : 0.0;
+    }
+#pragma unroll
+  for (int ks = 0; ks < NKF; ++ks)
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int s = c + 16 * mt, a = pos_mode(ks * 4 + g, K);
+      Bf[ks][mt] = (s < M && a >= 0) ? F[a * M + s] : 0.0;
+    }
+  int sP[NPR], iP[NPR];
+  bool okP[NPR];
+#pragma unroll
+  for (int r = 0; r < NPR; ++r) {
+    const int it = lane + 64 * r;
+    okP[r] = it < 3 * M;
+    sP[r] = okP[r] ? it % M : 0;
+    iP[r] = okP[r] ? it / M : 0;
+  }
+  double om[NPT];        // (Omega x)_p = om_p x_{p^1}
+  int trow[NPT];         // row of tau_q read by this lane (padding lanes read row 0)
+#pragma unroll
+  for (int pt = 0; pt < NPT; ++pt) {
+    const int p = c + 16 * pt;
+    om[pt] = p < 2 * K ? ((p & 1) ? ((p + 1) >> 1) * omega : -((p >> 1) + 1) * omega) : 0.0;
+    trow[pt] = (g * n + (p < n ? p : 0)) * n;
+  }
+  int tdst[NTL];         // unpacking of packed tau: (r*n + c) | (c*n + r) << 16
+  bool tok[NTL];
+#pragma unroll
+  for (int j = 0; j < NTL; ++j) {
+    const int pi = lane + 64 * j;
+    tok[j] = pi < P;
+    int r = 0, cc = 0;
+    if (tok[j]) packed_rc<n>(pi, r, cc);
+    tdst[j] = (r * n + cc) | ((cc * n + r) << 16);
+  }
+  int oslot[NPT];        // output slot of position p (-1: none); slot 1 (Im c_0) gets 0
+  double oscale[NPT];
+#pragma unroll
+  for (int pt = 0; pt < NPT; ++pt) {
+    const int p = c + 16 * pt;
+    oslot[pt] = p < 2 * K ? p + 2 : (p == 2 * K ? 0 : (p == 2 * K + 1 ? 1 : -1));
+    oscale[pt] = p < 2 * K ? TS_RS2 : (p == 2 * K ? 1.0 : 0.0);
+  }
+  constexpr double MD = TS_QA * TS_QA + 3.0 * TS_QB * TS_QB;      // sum_q lam_qb^2
+  constexpr double MO = 2.0 * TS_QA * TS_QB + 2.0 * TS_QB * TS_QB;  // sum_q lam_qb lam_qc
+
+  // padding that enters the MFMA k dimension must be finite
+  for (int i = lane; i < 16 * MS; i += 64) sC[i] = 0.0;
+  for (int i = lane; i < NL * 16 * PW; i += 64) sZ[i] = 0.0;
+  if (NEWTON)
+    for (int i = lane; i < 16 * PW; i += 64) sZf[i] = 0.0;
+  __syncthreads();
+
+  // ---- contiguous element range of this block's XCD
+  const int64_t nbx = gridDim.x >> 3, xcd = blockIdx.x & 7, jx = blockIdx.x >> 3;
+  const int64_t cnt = end - begin;
+  const int64_t lo = begin + cnt * xcd / 8, hi = begin + cnt * (xcd + 1) / 8;
+
+  for (int64_t e = lo + jx; e < hi; e += nbx) {
+    int nd[4];
+    double dN[4][3];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      nd[b] = v.conn[e * 4 + b];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) dN[b][j] = v.geo[e * 16 + b * 3 + j];
+    }
+    const double wgt = v.geo[e * 16 + 12];
+
+    // global loads of tau and the modal input first (consumed after products)
+    double tv[4][NTL];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int j = 0; j < NTL; ++j)
+        tv[q][j] = tok[j] ? v.tau[(e * 4 + q) * P + lane + 64 * j] : 0.0;
+    double xv[4][NPT];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int pt = 0; pt < NPT; ++pt) xv[b][pt] = XP[(int64_t)nd[b] * (4 * PW) + pt * 64 + lane];
+
+    // ---- products at the samples
+    double uq[KEEPU ? NPR : 1][4][3];
+#pragma unroll
+    for (int r = 0; r < NPR; ++r) {
+      if (!okP[r]) continue;
+      const int s = sP[r], i = iP[r];
+      double U[4][3], Wi[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const double* ut = UT + (int64_t)nd[b] * (3 * M) + s;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) U[b][j] = ut[j * M];
+        Wi[b] = RESID ? ut[i * M] : VT[(int64_t)nd[b] * (3 * M) + i * M + s];
+      }
+      double gW[3], su[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        gW[j] = dN[0][j] * Wi[0] + dN[1][j] * Wi[1] + dN[2][j] * Wi[2] + dN[3][j] * Wi[3];
+        su[j] = U[0][j] + U[1][j] + U[2][j] + U[3][j];
+      }
+      double u[4][3];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) u[q][j] = TS_QB * su[j] + (TS_QA - TS_QB) * U[q][j];
+      double conv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) conv[q] = u[q][0] * gW[0] + u[q][1] * gW[1] + u[q][2] * gW[2];
+      if (NEWTON) {
+        double Wd[4][3], Ui[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const double* vt = VT + (int64_t)nd[b] * (3 * M) + s;
+#pragma unroll
+          for (int j = 0; j < 3; ++j) Wd[b][j] = vt[j * M];
+          Ui[b] = UT[(int64_t)nd[b] * (3 * M) + i * M + s];
+        }
+        double gU[3], sw[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          gU[j] = dN[0][j] * Ui[0] + dN[1][j] * Ui[1] + dN[2][j] * Ui[2] + dN[3][j] * Ui[3];
+          sw[j] = Wd[0][j] + Wd[1][j] + Wd[2][j] + Wd[3][j];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double wq[3];
+#pragma unroll
+          for (int j = 0; j < 3; ++j) wq[j] = TS_QB * sw[j] + (TS_QA - TS_QB) * Wd[q][j];
+          conv[q] += wq[0] * gU[0] + wq[1] * gU[1] + wq[2] * gU[2];
+          // this lane's component i of the direction at point q
+          sWq[(q * 3 + i) * M + s] = i == 0 ? wq[0] : (i == 1 ? wq[1] : wq[2]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sC[(i * 4 + q) * MS + s] = conv[q];
+      if (KEEPU)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) uq[KEEPU ? r : 0][q][j] = u[q][j];
+    }
+    // stage tau rows and the modal input
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int j = 0; j < NTL; ++j)
+        if (tok[j]) {
+          sT[q * n * n + (tdst[j] & 0xffff)] = tv[q][j];
+          sT[q * n * n + (tdst[j] >> 16)] = tv[q][j];
+        }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int pt = 0; pt < NPT; ++pt) sV[b * 4 * PW + pt * 64 + lane] = xv[b][pt];
+    __syncthreads();
+
+    // ---- conv(t) -> modes: lane (q = g, p), reg i
+    double cm[NPT][3];
+    {
+      double a[NKB];
+#pragma unroll
+      for (int ks = 0; ks < NKB; ++ks) a[ks] = sC[c * MS + ks * 4 + g];
+#pragma unroll
+      for (int pt = 0; pt < NPT; ++pt) {
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < NKB; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], Bb[ks][pt], acc, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) cm[pt][i] = acc[i];
+      }
+    }
+
+    // ---- momentum operator L per (q, position)
+    double gal[NPT][3];
+#pragma unroll
+    for (int pt = 0; pt < NPT; ++pt) {
+      const int p = c + 16 * pt;
+      double Vb[4][4], Vq[3];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int f = 0; f < 4; ++f) Vb[b][f] = sV[(b * 4 + f) * PW + p];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) Vq[i] = sV[(g * 4 + i) * PW + p];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double du = TS_QB * (Vb[0][i] + Vb[1][i] + Vb[2][i] + Vb[3][i]) + (TS_QA - TS_QB) * Vq[i];
+        const double dp = dN[0][i] * Vb[0][3] + dN[1][i] * Vb[1][3] + dN[2][i] * Vb[2][3] + dN[3][i] * Vb[3][3];
+        gal[pt][i] = rho * fma(om[pt], swap_pair(du), cm[pt][i]);
+        sL[(g * 3 + i) * PW + p] = NOLS ? gal[pt][i] : gal[pt][i] + dp;
+        if (NOLS) sL[12 * PW + (g * 3 + i) * PW + p] = dp;
+      }
+    }
+    __syncthreads();
+
+    // ---- z = tau_q L (and tau_q grad p for the variant without LS coupling)
+    double z[NPT][3], zc[NPT][3];
+#pragma unroll
+    for (int pt = 0; pt < NPT; ++pt) {
+      double tr[n];
+#pragma unroll
+      for (int k = 0; k < n; ++k) tr[k] = sT[trow[pt] + k];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double* lr = sL + (g * 3 + i) * PW;
+        double acc = 0.0, accc = 0.0;
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+          acc = fma(tr[k], lr[k], acc);
+          if (NOLS) accc = fma(tr[k], lr[12 * PW + k], accc);
+        }
+        z[pt][i] = acc;
+        zc[pt][i] = accc;
+      }
+    }
+    __syncthreads();
+    // G = gal - Omega z (into sL), z rows q*4+i, stored / frozen z
+#pragma unroll
+    for (int pt = 0; pt < NPT; ++pt) {
+      const int p = c + 16 * pt;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        sL[(g * 3 + i) * PW + p] = gal[pt][i] - om[pt] * swap_pair(z[pt][i]);
+        sZ[(g * 4 + i) * PW + p] = z[pt][i];
+        if (NOLS) sZ[16 * PW + (g * 4 + i) * PW + p] = zc[pt][i];
+        if (p < n) {
+          const int64_t zi = ((e * 4 + g) * 3 + i) * n + p;
+          if (STOREZ) Zout[zi] = z[pt][i];
+          if (NEWTON) sZf[(g * 4 + i) * PW + p] = v.Z[zi];
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- z modes -> samples: lane (i = g, s = c + 16 mt), reg q; staged [i*4+q][s]
+    {
+      double a[NKF], af[NEWTON ? NKF : 1];
+#pragma unroll
+      for (int ks = 0; ks < NKF; ++ks) {
+        a[ks] = sZ[c * PW + ks * 4 + g];
+        if (NEWTON) af[NEWTON ? ks : 0] = sZf[c * PW + ks * 4 + g];
+      }
+      dbl4 zt[MT], zft[NEWTON ? MT : 1];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < NKF; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], Bf[ks][mt], acc, 0, 0, 0);
+        zt[mt] = acc;
+        if (NEWTON) {
+          dbl4 accf = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int ks = 0; ks < NKF; ++ks)
+            accf = __builtin_amdgcn_mfma_f64_16x16x4f64(af[NEWTON ? ks : 0], Bf[ks][mt], accf, 0, 0, 0);
+          zft[NEWTON ? mt : 0] = accf;
+        }
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int s = c + 16 * mt;
+        if (s < M) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            sC[(g * 4 + q) * M + s] = zt[mt][q];
+            if (NEWTON) sZft[(g * 4 + q) * M + s] = zft[NEWTON ? mt : 0][q];
+          }
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- least-squares test products W_ji(t_s), lane (s, i)
+    {
+      double W[NPR][3];
+#pragma unroll
+      for (int r = 0; r < NPR; ++r) {
+        W[r][0] = W[r][1] = W[r][2] = 0.0;
+        if (!okP[r]) continue;
+        const int s = sP[r], i = iP[r];
+        double u[4][3];
+        if (KEEPU) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) u[q][j] = uq[KEEPU ? r : 0][q][j];
+        } else {
+          double U[4][3], su[3];
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) U[b][j] = UT[(int64_t)nd[b] * (3 * M) + j * M + s];
+#pragma unroll
+          for (int j = 0; j < 3; ++j) su[j] = U[0][j] + U[1][j] + U[2][j] + U[3][j];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) u[q][j] = TS_QB * su[j] + (TS_QA - TS_QB) * U[q][j];
+        }
+        double zq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) zq[q] = sC[(i * 4 + q) * M + s];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          double acc = 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc = fma(u[q][j], zq[q], acc);
+          W[r][j] = acc;
+        }
+        if (NEWTON) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const double zf = sZft[(i * 4 + q) * M + s];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) W[r][j] = fma(sWq[(q * 3 + j) * M + s], zf, W[r][j]);
+          }
+        }
+      }
+      __syncthreads();   // every lane has read the staged z(t) before W(t) overwrites it
+#pragma unroll
+      for (int r = 0; r < NPR; ++r) {
+        if (!okP[r]) continue;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) sC[(j * 4 + iP[r]) * MS + sP[r]] = wgt * W[r][j];
+      }
+    }
+    __syncthreads();
+
+    // ---- W(t) -> modes: lane (i = g, p), reg j
+    double wm[NPT][3];
+    {
+      double a[NKB];
+#pragma unroll
+      for (int ks = 0; ks < NKB; ++ks) a[ks] = sC[c * MS + ks * 4 + g];
+#pragma unroll
+      for (int pt = 0; pt < NPT; ++pt) {
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < NKB; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], Bb[ks][pt], acc, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) wm[pt][j] = acc[j];
+      }
+    }
+
+    // ---- assembly: lane (field f = g, position p), node rows b
+    double* oe = out + e * (16 * S);
+#pragma unroll
+    for (int pt = 0; pt < NPT; ++pt) {
+      const int p = c + 16 * pt;
+      double o[4];
+      if (g < 3) {
+        const int i = g;
+        double Gq[4], Vf[4], Vp[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Gq[q] = sL[(q * 3 + i) * PW + p];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          Vf[b] = sV[(b * 4 + i) * PW + p];
+          Vp[b] = sV[(b * 4 + 3) * PW + p];
+        }
+        const double Gs = Gq[0] + Gq[1] + Gq[2] + Gq[3];
+        const double ps = Vp[0] + Vp[1] + Vp[2] + Vp[3];
+        const double Vs = Vf[0] + Vf[1] + Vf[2] + Vf[3];
+        double gV[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gV[j] = dN[0][j] * Vf[0] + dN[1][j] * Vf[1] + dN[2][j] * Vf[2] + dN[3][j] * Vf[3];
+        const double kv = 4.0 * wgt * mu, ks = shift * wgt;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const double dNi = i == 0 ? dN[b][0] : (i == 1 ? dN[b][1] : dN[b][2]);
+          double acc = wgt * (TS_QB * Gs + (TS_QA - TS_QB) * Gq[b]);
+          acc += dN[b][0] * wm[pt][0] + dN[b][1] * wm[pt][1] + dN[b][2] * wm[pt][2];
+          acc -= dNi * wgt * ps;
+          acc += kv * (dN[b][0] * gV[0] + dN[b][1] * gV[1] + dN[b][2] * gV[2]);
+          acc += ks * (MO * Vs + (MD - MO) * Vf[b]);
+          o[b] = acc;
+        }
+      } else {
+        double div = 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) div = fma(dN[b][j], sV[(b * 4 + j) * PW + p], div);
+        double zs[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const double* zr = sZ + (NOLS ? 16 * PW : 0) + i * PW + p;
+          zs[i] = zr[0] + zr[4 * PW] + zr[8 * PW] + zr[12 * PW];
+        }
+        const double wr = wgt / rho;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          o[b] = wgt * div + wr * (dN[b][0] * zs[0] + dN[b][1] * zs[1] + dN[b][2] * zs[2]);
+      }
+      if (oslot[pt] >= 0) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) oe[(b * 4 + g) * S + oslot[pt]] = o[b] * oscale[pt];
+      }
+    }
+    __syncthreads();   // LDS of this element fully consumed before the next one
+  }
+}
+
+// ------------------------------------------------------------- dispatch
+template <int K, int MD>
+static hipError_t op_launch(const DevView& v, const double* XP, const double* VT, double* Zout,
+                            double* out, double shift, int64_t begin, int64_t end, hipStream_t st) {
+  static int max_blocks = 0;   // resident blocks on the whole device, multiple of 8
+  if (max_blocks == 0) {
+    int dev = 0, ncu = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_op<K, MD>, 64, 0);
+    if (e != hipSuccess) return e;
+    const int mb = ncu * (per_cu > 0 ? per_cu : 1);
+    max_blocks = mb < 8 ? 8 : mb / 8 * 8;
+  }
+  const int64_t cnt = end - begin;
+  int64_t nb = (cnt + 7) / 8 * 8;
+  if (nb > max_blocks) nb = max_blocks;
+  k_op<K, MD><<<(unsigned)nb, 64, 0, st>>>(v, XP, VT, Zout, out, shift, begin, end);
+  return hipGetLastError();
+}
+
+template <int K>
+static hipError_t op_dispatch(const DevView& v, int mode, const double* XP, const double* VT,
+                              double* Zout, double* out, double shift, int64_t begin, int64_t end,
+                              hipStream_t st) {
+  switch (mode) {
+    case MODE_RESID: return op_launch<K, MODE_RESID>(v, XP, VT, Zout, out, shift, begin, end, st);
+    case MODE_RESID | MODE_STOREZ:
+      return op_launch<K, MODE_RESID | MODE_STOREZ>(v, XP, VT, Zout, out, shift, begin, end, st);
+    case 0: return op_launch<K, 0>(v, XP, VT, Zout, out, shift, begin, end, st);
+    case MODE_NOLS: return op_launch<K, MODE_NOLS>(v, XP, VT, Zout, out, shift, begin, end, st);
+    case MODE_NEWTON: return op_launch<K, MODE_NEWTON>(v, XP, VT, Zout, out, shift, begin, end, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_elem(const DevView& v, int mode, const double* XP, const double* VT,
+                       double* Zout, double* out, double shift, int64_t begin, int64_t end,
+                       hipStream_t st) {
+  if (end <= begin) return hipSuccess;
+  switch (v.K) {
+#define CASE(k) case k: return op_dispatch<k>(v, mode, XP, VT, Zout, out, shift, begin, end, st);
+    TSGLS_FOR_EACH_K(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace tsgls

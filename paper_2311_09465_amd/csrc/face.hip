@@ -182,7 +182,6 @@ __global__ void k_face_diag(DevView v, double* __restrict__ d) {
   }
 }
 
-#define TSGLS_FOR_EACH_K(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(11) X(15)
 
 hipError_t launch_face_lin(const DevView& v, const double* UTs, double* aneg, hipStream_t st) {
   if (v.n_faces == 0) return hipSuccess;

@@ -23,9 +23,6 @@ struct tsgls_ctx {
   int K = 0, n = 1, S = 2, M = 1, P = 1;
   int64_t nn = 0, E = 0, nf = 0;
   std::vector<int32_t> perm;    // processing position -> input element index (Morton order)
-  int TE = 1;                   // elements per tile (tau / Z layout)
-  int64_t n_tiles = 0;
-  int32_t* tslot = nullptr;     // [E] storage slot per element
   int32_t* noff = nullptr;      // [n_nodes+1] CSR offsets: node -> incident element slots
   int32_t* ninc = nullptr;      // [4E] incident (element*4 + local node), ascending element
   double* ebuf = nullptr;       // [E][4][4][2K+2] per-element contributions
@@ -36,6 +33,7 @@ struct tsgls_ctx {
   double* F = nullptr;
   double* UT = nullptr;
   double* VT = nullptr;
+  double* XP = nullptr;         // [n_nodes][4][PW] modes at their positions (operator input)
   double* tau = nullptr;
   double* Z = nullptr;
   double* rs = nullptr;         // scratch residual for linearize
@@ -144,8 +142,6 @@ DevView view(const tsgls_ctx* c) {
   v.UT = c->UT;
   v.tau = c->tau;
   v.Z = c->Z;
-  v.tslot = c->tslot;
-  v.TE = c->TE;
   v.noff = c->noff;
   v.ninc = c->ninc;
   v.fconn = c->fconn;
@@ -197,17 +193,19 @@ struct ProfScope {
   }
 };
 
-// Volume + face terms of the operator; out must be zeroed by the caller.
+// Volume + face terms of the operator into out (overwritten).  The input's
+// modes must already be in c->XP (launch_prep_time); Y is the input vector
+// itself (face terms).
 int apply_operator(tsgls_ctx* c, const DevView& v, int mode, const double* Y, const double* VTp,
                    double* Zout, double* out, double shift, const double* an, int resid) {
   const int which = (mode & MODE_RESID) ? TSGLS_PROF_ELEM_RESIDUAL : TSGLS_PROF_ELEM_TANGENT;
   {
     ProfScope ps(c, which);
-    HIPCHK(c, launch_elem(v, mode, Y, VTp, Zout, c->ebuf, shift, 0, c->E, 0, c->st));
+    HIPCHK(c, launch_elem(v, mode, c->XP, VTp, Zout, c->ebuf, shift, 0, c->E, c->st));
   }
   {
     ProfScope ps(c, TSGLS_PROF_GATHER);
-    HIPCHK(c, launch_gather(c->K, c->noff, c->ninc, c->ebuf, out, c->nn, c->st));
+    HIPCHK(c, launch_gather(c->K, c->noff, c->ninc, c->nflag, c->ebuf, out, c->nn, c->st));
   }
   if (c->nf) {
     ProfScope ps(c, TSGLS_PROF_FACE);
@@ -218,7 +216,7 @@ int apply_operator(tsgls_ctx* c, const DevView& v, int mode, const double* Y, co
 
 int linearize_impl(tsgls_ctx* c, const double* y, double* r) {
   DevView v = view(c);
-  HIPCHK(c, launch_prep_time(c->K, y, c->nflag, 0, c->F, c->UT, c->nn, c->st));
+  HIPCHK(c, launch_prep_time(c->K, y, c->nflag, 0, c->F, c->UT, c->XP, c->nn, c->st));
   {
     ProfScope ps(c, TSGLS_PROF_TAU);
     HIPCHK(c, launch_tau(v, y, c->tau, c->st));
@@ -235,7 +233,7 @@ int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt) {
   DevView v = view(c);
   const int mode = jac == TSGLS_JAC_PICARD ? 0 : jac == TSGLS_JAC_PICARD_NOLS ? MODE_NOLS : MODE_NEWTON;
   const double shift = dt > 0 ? 1.5 * c->p.rho / dt : 0.0;
-  HIPCHK(c, launch_prep_time(c->K, x, c->nflag, 1, c->F, c->VT, c->nn, c->st));
+  HIPCHK(c, launch_prep_time(c->K, x, c->nflag, 1, c->F, c->VT, c->XP, c->nn, c->st));
   return apply_operator(c, v, mode, x, c->VT, nullptr, out, shift, c->aneg, 0);
 }
 
@@ -247,7 +245,7 @@ int diag_impl(tsgls_ctx* c, double* d, double dt) {
     ProfScope ps(c, TSGLS_PROF_DIAG);
     HIPCHK(c, launch_diag(v, c->ebuf, shift, 0, c->E, c->st));
   }
-  HIPCHK(c, launch_gather(c->K, c->noff, c->ninc, c->ebuf, d, c->nn, c->st));
+  HIPCHK(c, launch_gather(c->K, c->noff, c->ninc, c->nflag, c->ebuf, d, c->nn, c->st));
   if (c->nf) HIPCHK(c, launch_face_diag(v, d, c->st));
   HIPCHK(c, launch_diag_finish(c->K, c->nflag, d, c->nn, c->st));
   return TSGLS_OK;
@@ -445,10 +443,6 @@ int tsgls_create(const double* xyz, int64_t n_nodes, const int32_t* tets, int64_
     for (int64_t e = 0; e < n_tets; ++e) c->perm[e] = (int32_t)e;
     std::stable_sort(c->perm.begin(), c->perm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
   }
-  c->TE = tile_elems(K);
-  c->n_tiles = (n_tets + c->TE - 1) / c->TE;
-  std::vector<int32_t> slot(n_tets);
-  for (int64_t e = 0; e < n_tets; ++e) slot[e] = (int32_t)e;
   std::vector<int32_t> sconn(n_tets * 4);
   for (int64_t e = 0; e < n_tets; ++e)
     for (int b = 0; b < 4; ++b) sconn[e * 4 + b] = tets[(int64_t)c->perm[e] * 4 + b];
@@ -469,16 +463,15 @@ int tsgls_create(const double* xyz, int64_t n_nodes, const int32_t* tets, int64_
   CHK(dalloc(c, &c->F, (size_t)c->n * c->M));
   CHK(dalloc(c, &c->UT, n_nodes * 3 * c->M));
   CHK(dalloc(c, &c->VT, n_nodes * 3 * c->M));
-  CHK(dalloc(c, &c->tau, (size_t)c->n_tiles * c->TE * 4 * c->P));
-  CHK(dalloc(c, &c->Z, (size_t)c->n_tiles * c->TE * 12 * c->n));
-  CHK(dalloc(c, &c->tslot, n_tets));
+  CHK(dalloc(c, &c->XP, n_nodes * 4 * pos_width(K)));
+  CHK(dalloc(c, &c->tau, (size_t)n_tets * 4 * c->P));
+  CHK(dalloc(c, &c->Z, (size_t)n_tets * 12 * c->n));
   CHK(dalloc(c, &c->noff, n_nodes + 1));
   CHK(dalloc(c, &c->ninc, n_tets * 4));
   CHK(dalloc(c, &c->ebuf, (size_t)n_tets * 16 * c->S));
   CHK(dalloc(c, &c->rs, n_nodes * 4 * c->S));
   HIPCHK(c, hipMemcpyAsync(dxyz, xyz, n_nodes * 3 * sizeof(double), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->conn, sconn.data(), n_tets * 4 * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
-  HIPCHK(c, hipMemcpyAsync(c->tslot, slot.data(), n_tets * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->noff, noff.data(), noff.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->ninc, ninc.data(), ninc.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemsetAsync(c->nflag, 0, n_nodes, c->st));
@@ -605,17 +598,16 @@ int tsgls_residual(tsgls_ctx* c, const double* y, double* r) {
   if (!y || !r) return fail(c, TSGLS_EINVAL, "null vector");
   if (!c->UTr) {
     CHK(dalloc(c, &c->UTr, c->nn * 3 * c->M));
-    CHK(dalloc(c, &c->taur, (size_t)c->n_tiles * c->TE * 4 * c->P));
+    CHK(dalloc(c, &c->taur, (size_t)c->E * 4 * c->P));
   }
   if (c->nf && !c->anegr) CHK(dalloc(c, &c->anegr, (size_t)c->nf * 3 * c->P));
   DevView v = view(c);
   v.UT = c->UTr;
   v.tau = c->taur;
   v.aneg = c->anegr;
-  HIPCHK(c, launch_prep_time(c->K, y, c->nflag, 0, c->F, c->UTr, c->nn, c->st));
+  HIPCHK(c, launch_prep_time(c->K, y, c->nflag, 0, c->F, c->UTr, c->XP, c->nn, c->st));
   HIPCHK(c, launch_tau(v, y, c->taur, c->st));
   HIPCHK(c, launch_face_lin(v, c->UTr, c->anegr, c->st));
-  HIPCHK(c, launch_zero(r, ndof(c), c->st));
   return apply_operator(c, v, MODE_RESID, y, nullptr, nullptr, r, 0.0, c->anegr, 1);
 }
 
@@ -642,15 +634,20 @@ int tsgls_get_tau(tsgls_ctx* c, double* tau_out) {
   if (!c) return TSGLS_EINVAL;
   if (!tau_out) return fail(c, TSGLS_EINVAL, "null pointer");
   if (!c->linearized) return fail(c, TSGLS_ESTATE, "get_tau before linearize");
-  std::vector<double> buf((size_t)c->n_tiles * c->TE * 4 * c->P);
-  std::vector<int32_t> slot(c->E);
+  std::vector<double> buf((size_t)c->E * 4 * c->P);
   HIPCHK(c, hipMemcpyAsync(buf.data(), c->tau, buf.size() * sizeof(double), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(c, hipMemcpyAsync(slot.data(), c->tslot, slot.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
+  // device storage is packed over positions; the output is packed over modes
+  std::vector<int> map(c->P);
+  for (int r = 0, p = 0; r < c->n; ++r)
+    for (int cc = r; cc < c->n; ++cc, ++p) {
+      const int pr = mode_pos(r, c->K), pc = mode_pos(cc, c->K);
+      map[p] = pr < pc ? pk_index(pr, pc, c->n) : pk_index(pc, pr, c->n);
+    }
   for (int64_t e = 0; e < c->E; ++e)
     for (int q = 0; q < 4; ++q)
       for (int p = 0; p < c->P; ++p)
-        tau_out[((size_t)c->perm[e] * 4 + q) * c->P + p] = buf[tau_index(slot[e], q, p, c->P, c->TE)];
+        tau_out[((size_t)c->perm[e] * 4 + q) * c->P + p] = buf[((size_t)e * 4 + q) * c->P + map[p]];
   return TSGLS_OK;
 }
 

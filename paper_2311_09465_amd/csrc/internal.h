@@ -6,16 +6,27 @@
 
 namespace tsgls {
 
-// Storage layout of the per-quadrature-point tau (packed, P entries) and of
-// tau L(u) (n modes per (qp, component) row): tiles of TE elements with the
-// tile's points interleaved innermost, so that the threads of one tile read
-// consecutive addresses.  slot = tile * TE + element-in-tile.
-__host__ __device__ __forceinline__ int64_t tau_index(int64_t slot, int q, int p, int P, int TE) {
-  return ((slot / TE) * P + p) * (int64_t)(TE * 4) + (slot % TE) * 4 + q;
+// Harmonic counts K the kernels are instantiated for.
+#define TSGLS_FOR_EACH_K(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(11) X(15)
+
+// Mode positions.  Inside the element operator the n = 2K+1 real modes of a
+// field sit at "positions" p: mode 2k-1 (cos k wt) at p = 2k-2, mode 2k
+// (sin k wt) at p = 2k-1, mode 0 at p = 2K; positions 2K+1 .. are padding.
+// The two modes of one harmonic then sit at p and p^1, so the time
+// derivative Omega pairs neighbouring lanes.
+__host__ __device__ constexpr int pos_mode(int p, int K) {
+  return p < 2 * K ? p + 1 : (p == 2 * K ? 0 : -1);
 }
-__host__ __device__ __forceinline__ int64_t z_index(int64_t slot, int row, int a, int n, int TE) {
-  return ((slot / TE) * n + a) * (int64_t)(TE * 12) + (slot % TE) * 12 + row;
+__host__ __device__ constexpr int mode_pos(int a, int K) { return a == 0 ? 2 * K : a - 1; }
+// Packed upper triangle (row-major) of a symmetric n x n matrix, r <= c.
+__host__ __device__ constexpr int pk_index(int r, int c, int n) {
+  return r * n - (r * (r - 1)) / 2 + (c - r);
 }
+
+// tau is stored per element and quadrature point as the packed upper
+// triangle over positions: tau[(e*4 + q)*P + pk_index(pr, pc, n)], e in
+// processing order.  z = tau L(u) (Newton tangent) is stored as
+// Z[((e*4 + q)*3 + i)*n + p].
 
 // Element-operator modes (compile-time flags of the element kernel).
 enum : int {
@@ -29,15 +40,13 @@ enum : int {
 struct DevView {
   int K;
   int64_t n_nodes, n_tets, n_faces;
-  const int32_t* conn;       // [E][4] element nodes, colour-sorted order
+  const int32_t* conn;       // [E][4] element nodes, processing (Morton) order
   const double* geo;         // [E][16]: grad N (a-major, 12), w = V/4, pad
   const uint8_t* nflag;      // [n_nodes] bit0: velocity Dirichlet
   const double* F;           // [n][M] phi_a(t_s), real orthonormal basis
   const double* UT;          // [n_nodes][3][M] frozen velocity samples
-  const double* tau;         // packed tau, tile-interleaved (tau_index)
-  const double* Z;           // tau L(u) modal, tile-interleaved (z_index)
-  const int32_t* tslot;      // [E] storage slot of each (colour-sorted) element
-  int TE;                    // elements per tile of the element kernel
+  const double* tau;         // [E][4][P] packed tau over positions
+  const double* Z;           // [E][4][3][n] tau L(u) over positions
   const int32_t* noff;       // [n_nodes+1] node -> incident element slots
   const int32_t* ninc;       // element*4 + local node, ascending element
   const int32_t* fconn;      // [nf][3] Neumann faces
@@ -56,24 +65,30 @@ struct DevView {
 // contributions [E][4 nodes][4 fields][S] that launch_gather sums per node.
 hipError_t launch_geometry(const double* xyz, const int32_t* conn, double* geo,
                            int* bad, int64_t n_tets, hipStream_t st);
+// XT[node][3][M]: time samples of the three velocity components;
+// XP[node][4][PW]: the four fields' modes in the orthonormal basis at their
+// positions (zero padding).  masked != 0 zeroes Dirichlet velocity rows.
 hipError_t launch_prep_time(int K, const double* Y, const uint8_t* nflag,
                             int masked, const double* F, double* XT,
-                            int64_t n_nodes, hipStream_t st);
+                            double* XP, int64_t n_nodes, hipStream_t st);
+// Positions per field row of XP (16 or 32).
+int pos_width(int K);
 hipError_t launch_tau(const DevView& v, const double* Y, double* tau,
                       hipStream_t st);
-hipError_t launch_elem(const DevView& v, int mode, const double* Y,
+// Element operator over elements [begin, end) (processing order); input
+// modes from XP, direction samples VT (tangent modes), writes the per-element
+// contributions out[E][4][4][S].  Zout (mode & MODE_STOREZ) receives tau L(u).
+hipError_t launch_elem(const DevView& v, int mode, const double* XP,
                        const double* VT, double* Zout, double* out,
-                       double shift, int64_t begin, int64_t end,
-                       int64_t tile_off, hipStream_t st);
-// Elements per tile for K harmonics (fixes the tau / Z storage layout).
-int tile_elems(int K);
+                       double shift, int64_t begin, int64_t end, hipStream_t st);
 hipError_t launch_diag(const DevView& v, double* d, double shift,
                        int64_t begin, int64_t end, hipStream_t st);
 // out[node][4][S] = sum over incident (element, local node) of ebuf, in
 // ascending element order (deterministic).
+// Velocity rows of Dirichlet nodes (nflag bit 0) are written as zero.
 hipError_t launch_gather(int K, const int32_t* noff, const int32_t* ninc,
-                         const double* ebuf, double* out, int64_t n_nodes,
-                         hipStream_t st);
+                         const uint8_t* nflag, const double* ebuf, double* out,
+                         int64_t n_nodes, hipStream_t st);
 hipError_t launch_face_lin(const DevView& v, const double* Y, double* aneg,
                            hipStream_t st);
 hipError_t launch_face_apply(const DevView& v, const double* Y, int resid,
