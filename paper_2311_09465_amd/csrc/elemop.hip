@@ -40,6 +40,11 @@ struct OpCfg {
   static constexpr int NPR = (3 * M + 63) / 64;   // passes over (sample, component)
   static constexpr int NTL = (P + 63) / 64;       // loads per packed tau block
   static constexpr bool KEEPU = NPR == 1;         // keep u_q(t_s) in registers
+  // LDS row strides, odd so that rows touched by different lane rows fall
+  // in different banks
+  static constexpr int RP = PW + 1;               // rows over positions
+  static constexpr int RS = MS | 1;               // rows over samples (>= M)
+  static constexpr int RM = M | 1;                // staged z(t) rows
 };
 
 // Value of lane l ^ 1 (quad permutation 1,0,3,2).
@@ -57,6 +62,7 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
   using C = OpCfg<K>;
   constexpr int n = C::n, M = C::M, S = C::S, P = C::P, PW = C::PW, NPT = C::NPT;
   constexpr int MS = C::MS, NKB = C::NKB, MT = C::MT, NKF = C::NKF, NPR = C::NPR, NTL = C::NTL;
+  constexpr int RP = C::RP, RS = C::RS, RM = C::RM;
   constexpr bool RESID = (MODE & MODE_RESID) != 0;
   constexpr bool NEWTON = (MODE & MODE_NEWTON) != 0;
   constexpr bool NOLS = (MODE & MODE_NOLS) != 0;
@@ -64,14 +70,15 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
   constexpr bool KEEPU = C::KEEPU;
   constexpr int NL = NOLS ? 2 : 1;
 
-  __shared__ double sV[16 * PW];               // modes [node][field][position]
+  constexpr int NC = 16 * (RS > RM ? RS : RM);
+  __shared__ double sV[16 * RP];               // modes [node][field][position]
   __shared__ double sT[4 * n * n];             // tau_q rows [q][position][position]
-  __shared__ double sL[NL * 12 * PW];          // L [q][i][position] (+ grad p part), then G
-  __shared__ double sC[16 * MS];               // conv(t) / z(t) staging [16][M] / W(t)
-  __shared__ double sZ[NL * 16 * PW];          // z [q*4+i][position] (+ tau grad p)
-  __shared__ double sZf[NEWTON ? 16 * PW : 1];    // stored tau L(u) [q*4+i][position]
-  __shared__ double sZft[NEWTON ? 16 * M : 1];    // its samples [i*4+q][s]
-  __shared__ double sWq[NEWTON ? 12 * M : 1];     // direction at the points [q][j][s]
+  __shared__ double sL[NL * 12 * RP];          // L [q][i][position] (+ grad p part), then G
+  __shared__ double sC[NC];                    // conv(t) [16][RS] / z(t) [16][RM] / W(t) [16][RS]
+  __shared__ double sZ[NL * 16 * RP];          // z [q*4+i][position] (+ tau grad p)
+  __shared__ double sZf[NEWTON ? 16 * RP : 1];    // stored tau L(u) [q*4+i][position]
+  __shared__ double sZft[NEWTON ? 16 * RM : 1];   // its samples [i*4+q][s]
+  __shared__ double sWq[NEWTON ? 12 * RM : 1];    // direction at the points [q][j][s]
 
   const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
   const double rho = v.rho, mu = v.mu, omega = v.omega;
@@ -134,10 +141,10 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
   constexpr double MO = 2.0 * TS_QA * TS_QB + 2.0 * TS_QB * TS_QB;  // sum_q lam_qb lam_qc
 
   // padding that enters the MFMA k dimension must be finite
-  for (int i = lane; i < 16 * MS; i += 64) sC[i] = 0.0;
-  for (int i = lane; i < NL * 16 * PW; i += 64) sZ[i] = 0.0;
+  for (int i = lane; i < NC; i += 64) sC[i] = 0.0;
+  for (int i = lane; i < NL * 16 * RP; i += 64) sZ[i] = 0.0;
   if (NEWTON)
-    for (int i = lane; i < 16 * PW; i += 64) sZf[i] = 0.0;
+    for (int i = lane; i < 16 * RP; i += 64) sZf[i] = 0.0;
   __syncthreads();
 
   // ---- contiguous element range of this block's XCD
@@ -219,11 +226,11 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
           for (int j = 0; j < 3; ++j) wq[j] = TS_QB * sw[j] + (TS_QA - TS_QB) * Wd[q][j];
           conv[q] += wq[0] * gU[0] + wq[1] * gU[1] + wq[2] * gU[2];
           // this lane's component i of the direction at point q
-          sWq[(q * 3 + i) * M + s] = i == 0 ? wq[0] : (i == 1 ? wq[1] : wq[2]);
+          sWq[(q * 3 + i) * RM + s] = i == 0 ? wq[0] : (i == 1 ? wq[1] : wq[2]);
         }
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) sC[(i * 4 + q) * MS + s] = conv[q];
+      for (int q = 0; q < 4; ++q) sC[(i * 4 + q) * RS + s] = conv[q];
       if (KEEPU)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
@@ -242,7 +249,10 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int pt = 0; pt < NPT; ++pt) sV[b * 4 * PW + pt * 64 + lane] = xv[b][pt];
+      for (int pt = 0; pt < NPT; ++pt) {
+        const int fp = pt * 64 + lane;   // field * PW + position within the node's block
+        sV[(b * 4 + fp / PW) * RP + fp % PW] = xv[b][pt];
+      }
     __syncthreads();
 
     // ---- conv(t) -> modes: lane (q = g, p), reg i
@@ -250,7 +260,7 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
     {
       double a[NKB];
 #pragma unroll
-      for (int ks = 0; ks < NKB; ++ks) a[ks] = sC[c * MS + ks * 4 + g];
+      for (int ks = 0; ks < NKB; ++ks) a[ks] = sC[c * RS + ks * 4 + g];
 #pragma unroll
       for (int pt = 0; pt < NPT; ++pt) {
         dbl4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -270,16 +280,16 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
 #pragma unroll
       for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int f = 0; f < 4; ++f) Vb[b][f] = sV[(b * 4 + f) * PW + p];
+        for (int f = 0; f < 4; ++f) Vb[b][f] = sV[(b * 4 + f) * RP + p];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) Vq[i] = sV[(g * 4 + i) * PW + p];
+      for (int i = 0; i < 3; ++i) Vq[i] = sV[(g * 4 + i) * RP + p];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         const double du = TS_QB * (Vb[0][i] + Vb[1][i] + Vb[2][i] + Vb[3][i]) + (TS_QA - TS_QB) * Vq[i];
         const double dp = dN[0][i] * Vb[0][3] + dN[1][i] * Vb[1][3] + dN[2][i] * Vb[2][3] + dN[3][i] * Vb[3][3];
         gal[pt][i] = rho * fma(om[pt], swap_pair(du), cm[pt][i]);
-        sL[(g * 3 + i) * PW + p] = NOLS ? gal[pt][i] : gal[pt][i] + dp;
-        if (NOLS) sL[12 * PW + (g * 3 + i) * PW + p] = dp;
+        sL[(g * 3 + i) * RP + p] = NOLS ? gal[pt][i] : gal[pt][i] + dp;
+        if (NOLS) sL[12 * RP + (g * 3 + i) * RP + p] = dp;
       }
     }
     __syncthreads();
@@ -293,12 +303,12 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
       for (int k = 0; k < n; ++k) tr[k] = sT[trow[pt] + k];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const double* lr = sL + (g * 3 + i) * PW;
+        const double* lr = sL + (g * 3 + i) * RP;
         double acc = 0.0, accc = 0.0;
 #pragma unroll
         for (int k = 0; k < n; ++k) {
           acc = fma(tr[k], lr[k], acc);
-          if (NOLS) accc = fma(tr[k], lr[12 * PW + k], accc);
+          if (NOLS) accc = fma(tr[k], lr[12 * RP + k], accc);
         }
         z[pt][i] = acc;
         zc[pt][i] = accc;
@@ -311,13 +321,13 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
       const int p = c + 16 * pt;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        sL[(g * 3 + i) * PW + p] = gal[pt][i] - om[pt] * swap_pair(z[pt][i]);
-        sZ[(g * 4 + i) * PW + p] = z[pt][i];
-        if (NOLS) sZ[16 * PW + (g * 4 + i) * PW + p] = zc[pt][i];
+        sL[(g * 3 + i) * RP + p] = gal[pt][i] - om[pt] * swap_pair(z[pt][i]);
+        sZ[(g * 4 + i) * RP + p] = z[pt][i];
+        if (NOLS) sZ[16 * RP + (g * 4 + i) * RP + p] = zc[pt][i];
         if (p < n) {
           const int64_t zi = ((e * 4 + g) * 3 + i) * n + p;
           if (STOREZ) Zout[zi] = z[pt][i];
-          if (NEWTON) sZf[(g * 4 + i) * PW + p] = v.Z[zi];
+          if (NEWTON) sZf[(g * 4 + i) * RP + p] = v.Z[zi];
         }
       }
     }
@@ -328,8 +338,8 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
       double a[NKF], af[NEWTON ? NKF : 1];
 #pragma unroll
       for (int ks = 0; ks < NKF; ++ks) {
-        a[ks] = sZ[c * PW + ks * 4 + g];
-        if (NEWTON) af[NEWTON ? ks : 0] = sZf[c * PW + ks * 4 + g];
+        a[ks] = sZ[c * RP + ks * 4 + g];
+        if (NEWTON) af[NEWTON ? ks : 0] = sZf[c * RP + ks * 4 + g];
       }
       dbl4 zt[MT], zft[NEWTON ? MT : 1];
 #pragma unroll
@@ -352,8 +362,8 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
         if (s < M) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            sC[(g * 4 + q) * M + s] = zt[mt][q];
-            if (NEWTON) sZft[(g * 4 + q) * M + s] = zft[NEWTON ? mt : 0][q];
+            sC[(g * 4 + q) * RM + s] = zt[mt][q];
+            if (NEWTON) sZft[(g * 4 + q) * RM + s] = zft[NEWTON ? mt : 0][q];
           }
         }
       }
@@ -389,7 +399,7 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
         }
         double zq[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) zq[q] = sC[(i * 4 + q) * M + s];
+        for (int q = 0; q < 4; ++q) zq[q] = sC[(i * 4 + q) * RM + s];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
           double acc = 0.0;
@@ -400,9 +410,9 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
         if (NEWTON) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const double zf = sZft[(i * 4 + q) * M + s];
+            const double zf = sZft[(i * 4 + q) * RM + s];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) W[r][j] = fma(sWq[(q * 3 + j) * M + s], zf, W[r][j]);
+            for (int j = 0; j < 3; ++j) W[r][j] = fma(sWq[(q * 3 + j) * RM + s], zf, W[r][j]);
           }
         }
       }
@@ -411,7 +421,7 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
       for (int r = 0; r < NPR; ++r) {
         if (!okP[r]) continue;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) sC[(j * 4 + iP[r]) * MS + sP[r]] = wgt * W[r][j];
+        for (int j = 0; j < 3; ++j) sC[(j * 4 + iP[r]) * RS + sP[r]] = wgt * W[r][j];
       }
     }
     __syncthreads();
@@ -421,7 +431,7 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
     {
       double a[NKB];
 #pragma unroll
-      for (int ks = 0; ks < NKB; ++ks) a[ks] = sC[c * MS + ks * 4 + g];
+      for (int ks = 0; ks < NKB; ++ks) a[ks] = sC[c * RS + ks * 4 + g];
 #pragma unroll
       for (int pt = 0; pt < NPT; ++pt) {
         dbl4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -442,11 +452,11 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
         const int i = g;
         double Gq[4], Vf[4], Vp[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Gq[q] = sL[(q * 3 + i) * PW + p];
+        for (int q = 0; q < 4; ++q) Gq[q] = sL[(q * 3 + i) * RP + p];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          Vf[b] = sV[(b * 4 + i) * PW + p];
-          Vp[b] = sV[(b * 4 + 3) * PW + p];
+          Vf[b] = sV[(b * 4 + i) * RP + p];
+          Vp[b] = sV[(b * 4 + 3) * RP + p];
         }
         const double Gs = Gq[0] + Gq[1] + Gq[2] + Gq[3];
         const double ps = Vp[0] + Vp[1] + Vp[2] + Vp[3];
@@ -470,12 +480,12 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
 #pragma unroll
         for (int b = 0; b < 4; ++b)
 #pragma unroll
-          for (int j = 0; j < 3; ++j) div = fma(dN[b][j], sV[(b * 4 + j) * PW + p], div);
+          for (int j = 0; j < 3; ++j) div = fma(dN[b][j], sV[(b * 4 + j) * RP + p], div);
         double zs[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-          const double* zr = sZ + (NOLS ? 16 * PW : 0) + i * PW + p;
-          zs[i] = zr[0] + zr[4 * PW] + zr[8 * PW] + zr[12 * PW];
+          const double* zr = sZ + (NOLS ? 16 * RP : 0) + i * RP + p;
+          zs[i] = zr[0] + zr[4 * RP] + zr[8 * RP] + zr[12 * RP];
         }
         const double wr = wgt / rho;
 #pragma unroll
