@@ -84,6 +84,40 @@ struct SampleTable {
   }
 };
 
+// The harmonics above K that M = 3K+1 samples still resolve: K real sampled
+// vectors v_r (cos and sin of k = K+1 .. M/2; a lone cos at the Nyquist
+// frequency when M is even), with v_r . v_r = 1 / coef_r.  The band-limiting
+// projection on the samples is x - sum_r coef_r v_r (v_r . x).
+template <int K>
+struct AliasTable {
+  static constexpr int M = 3 * K + 1, R = K > 0 ? K : 1;
+  double v[R][M];
+  double coef[R];
+  constexpr AliasTable() : v(), coef() {
+    int r = 0;
+    for (int k = K + 1; 2 * k <= M && r < K; ++k) {
+      const bool nyq = 2 * k == M;
+      for (int s = 0; s < M; ++s) {
+        double th = 2.0 * cx_pi * ((k * s) % M) / M;
+        if (th > cx_pi) th -= 2.0 * cx_pi;
+        double cs = 1.0, ts = th;
+        if (th > 0.5 * cx_pi) {
+          ts = cx_pi - th;
+          cs = -1.0;
+        } else if (th < -0.5 * cx_pi) {
+          ts = -cx_pi - th;
+          cs = -1.0;
+        }
+        v[r][s] = cs * cx_cos(ts);
+        if (!nyq) v[r + 1][s] = cx_sin(ts);
+      }
+      coef[r] = nyq ? 1.0 / M : 2.0 / M;
+      if (!nyq) coef[r + 1] = 2.0 / M;
+      r += nyq ? 1 : 2;
+    }
+  }
+};
+
 // (Omega x)_a in the orthonormal basis: time derivative, skew-symmetric.
 template <int n>
 __device__ __forceinline__ double omx(const double* x, int a, double omega) {
@@ -100,46 +134,107 @@ __device__ __forceinline__ void packed_rc(int p, int& r, int& c) {
   c = a + (p - off);
 }
 
+// Value held by lane (lane ^ k), 0 < k < 64.  XOR 1..3 within a quad, 7
+// within an 8-lane half row, 8 and 15 within a 16-lane row are single DPP
+// moves; other distances go through the LDS crossbar (ds_bpermute).
+template <int k>
+__device__ __forceinline__ int xor_lane(int x) {
+  if constexpr (k >= 1 && k <= 3) {
+    constexpr int sel = k;   // quad_perm: lane i takes lane i ^ k
+    constexpr int ctrl = (0 ^ sel) | ((1 ^ sel) << 2) | ((2 ^ sel) << 4) | ((3 ^ sel) << 6);
+    return __builtin_amdgcn_mov_dpp(x, ctrl, 0xF, 0xF, false);
+  } else if constexpr (k == 7) {
+    return __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false);   // row_half_mirror
+  } else if constexpr (k == 8) {
+    return __builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, false);   // row_ror:8
+  } else if constexpr (k == 15) {
+    return __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, false);   // row_mirror
+  } else {
+    return __shfl_xor(x, k);
+  }
+}
+template <int k>
+__device__ __forceinline__ double xor_lane(double x) {
+  return __hiloint2double(xor_lane<k>(__double2hiint(x)), xor_lane<k>(__double2loint(x)));
+}
+
+// 1/x and 1/sqrt(x) for x > 0 from the hardware estimates refined by two
+// Newton steps (quadratic convergence: full double precision).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(fma(-x, y, 1.0), y, y);
+  y = fma(fma(-x, y, 1.0), y, y);
+  return y;
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
+// One round of the one-sided Jacobi: the columns of lanes c and c ^ k are
+// rotated to be orthogonal.  Both lanes of a pair evaluate the same rotation
+// bit for bit (same operands in the same order).  nrm is this lane's |w|^2,
+// kept up to date; big is set when (w_c . w_d)^2 > 1e-20 |w_c|^2 |w_d|^2.
+template <int n, int k>
+__device__ __forceinline__ void jacobi_round(double (&w)[n], double& nrm, int c, int& big,
+                                             int& rot) {
+  double o[n];
+#pragma unroll
+  for (int a = 0; a < n; ++a) o[a] = xor_lane<k>(w[a]);
+  const double onrm = xor_lane<k>(nrm);
+  const bool low = c < (c ^ k);
+  // same summation order on both lanes: lo . hi
+  double ga = 0.0;
+#pragma unroll
+  for (int a = 0; a < n; ++a) ga = low ? fma(w[a], o[a], ga) : fma(o[a], w[a], ga);
+  const double al = low ? nrm : onrm, be = low ? onrm : nrm;
+  const double ab = al * be;
+  const double g2 = ga * ga;
+  if (g2 > 1e-20 * ab) big = 1;
+  if (g2 > 1e-30 * ab) {
+    // tan(theta) = 2 g sgn(d) / (|d| + sqrt(d^2 + 4 g^2)), d = be - al
+    const double d = be - al;
+    const double r2 = fma(d, d, 4.0 * g2);
+    const double r = r2 * rsq_nr(r2);
+    const double t = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) * rcp_nr(fabs(d) + r);
+    const double cs = rsq_nr(fma(t, t, 1.0));
+    const double sn = cs * t;
+#pragma unroll
+    for (int a = 0; a < n; ++a) w[a] = low ? fma(cs, w[a], -sn * o[a]) : fma(sn, o[a], cs * w[a]);
+    const double c2 = cs * cs, s2 = sn * sn, cs2 = 2.0 * cs * sn * ga;
+    nrm = low ? fma(c2, al, fma(s2, be, -cs2)) : fma(s2, al, fma(c2, be, cs2));
+    rot = 1;
+  }
+}
+
+template <int n, int k, int NP>
+__device__ __forceinline__ void jacobi_rounds(double (&w)[n], double& nrm, int c, int& big,
+                                              int& rot) {
+  if constexpr (k < NP) {
+    jacobi_round<n, k>(w, nrm, c, big, rot);
+    jacobi_rounds<n, k + 1, NP>(w, nrm, c, big, rot);
+  }
+}
+
 // One-sided (Hestenes) cyclic Jacobi on the columns held by a group of NP
 // lanes: lane c holds column c (n entries, zero for c >= n).  Pairs per
 // round are (c, c xor k), k = 1..NP-1, which covers every pair once per
-// sweep.  Both lanes of a pair compute the same rotation bit for bit.  On
-// return the columns are mutually orthogonal to working precision.
+// sweep.  Sweeps stop after the first one whose largest rotation was below
+// 1e-10 in relative terms (convergence is quadratic, so the columns are then
+// orthogonal to working precision), or that rotated nothing.  The whole wave
+// sweeps until all its groups are done.
 template <int n, int NP>
 __device__ __forceinline__ void jacobi_columns(double (&w)[n], int c) {
-  const double tol = 1e-15;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    int rot = 0;
-#pragma unroll 1
-    for (int k = 1; k < NP; ++k) {
-      double o[n];
+    double nrm = 0.0;
 #pragma unroll
-      for (int a = 0; a < n; ++a) o[a] = __shfl_xor(w[a], k);
-      const bool low = c < (c ^ k);
-      double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-      for (int a = 0; a < n; ++a) {
-        const double lo = low ? w[a] : o[a];
-        const double hi = low ? o[a] : w[a];
-        al = fma(lo, lo, al);
-        be = fma(hi, hi, be);
-        ga = fma(lo, hi, ga);
-      }
-      if (fabs(ga) > tol * sqrt(al * be)) {
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t);
-        const double sn = cs * t;
-#pragma unroll
-        for (int a = 0; a < n; ++a) {
-          const double lo = low ? w[a] : o[a];
-          const double hi = low ? o[a] : w[a];
-          w[a] = low ? (cs * lo - sn * hi) : (sn * lo + cs * hi);
-        }
-        rot = 1;
-      }
-    }
-    if (!__any(rot)) break;
+    for (int a = 0; a < n; ++a) nrm = fma(w[a], w[a], nrm);
+    int big = 0, rot = 0;
+    jacobi_rounds<n, 1, NP>(w, nrm, c, big, rot);
+    if (!__any(rot) || !__any(big)) break;
   }
 }
 

@@ -16,6 +16,8 @@
 
 namespace tsgls {
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 // ---------------------------------------------------------------- geometry
 // grad N_a (node 0 at the parent origin, xi_k = N_k), w = V/4 per point.
 __global__ void k_geometry(const double* __restrict__ xyz, const int32_t* __restrict__ conn,
@@ -103,16 +105,24 @@ __global__ void k_prep_time(const double* __restrict__ Y, const uint8_t* __restr
 // column c of S = sum_i A(u_i) A(v_i) + C_I nu^2 (G:G) I, v_i = G_ij u_j
 // (eq. 3D-tau), the group runs one-sided Jacobi on the columns, and
 // tau = S^(-1/2) = sum_c lambda_c^(-1/2) v_c v_c^T with v_c = w_c / lambda_c.
+//
+// Column c on the samples: A(v_i) e_c is the band-limited part of
+// v_i(t) phi_c(t), i.e. the sampled product minus its K alias harmonics
+// (AliasTable); A(u_i) of that is formed the same way, and only the final
+// sum over i is projected on the modes.
 template <int K>
 struct TauCfg {
   static constexpr int n = Dim<K>::n, M = Dim<K>::M;
-  static constexpr int NP = np_of(n);
-  static constexpr int per_group = 6 * n + 6 * M + n * n;   // doubles of LDS
-  static constexpr int G0 = 256 / NP;
-  static constexpr int Gmem = 49152 / (per_group * 8);
-  static constexpr int G = G0 < Gmem ? G0 : (Gmem < 1 ? 1 : Gmem);
-  static constexpr int BLOCK = G * NP < 64 ? 64 : G * NP;
-  static constexpr int GB = BLOCK / NP;   // groups per block after rounding up
+  static constexpr int NP = np_of(n);              // lanes per point
+  static constexpr int PW = (n + 15) / 16 * 16;    // positions, padded to the MFMA tile
+  static constexpr int QW = 64 / NP;               // points per wave
+  static constexpr int BLOCK = 256;
+  static constexpr int GB = BLOCK / NP;            // points per block
+  static constexpr bool MFMA_OUT = NP >= 16;       // tau = Q^T Q on MFMA
+  static constexpr int QS = PW + 1;                // row stride of Q
+  static constexpr int PH1 = 6 * n + 6 * M;        // LDS per point, first phase
+  static constexpr int PH2 = MFMA_OUT ? PW * QS : n * n;   // ... output phase
+  static constexpr int PG = PH1 > PH2 ? PH1 : PH2;
 };
 
 template <int K>
@@ -120,33 +130,30 @@ __global__ void __launch_bounds__(TauCfg<K>::BLOCK)
 k_tau(DevView v, const double* __restrict__ Y, double* __restrict__ tau) {
   using C = TauCfg<K>;
   constexpr int n = C::n, M = C::M, S = Dim<K>::S, NP = C::NP, P = Dim<K>::P, GB = C::GB;
-  __shared__ double sU[GB][3][n], sVv[GB][3][n], sUt[GB][3][M], sVt[GB][3][M], sQ[GB][n * n];
+  constexpr int PW = C::PW, QS = C::QS, QW = C::QW;
+  __shared__ double lds[GB * C::PG];
   const double* __restrict__ F = v.F;
   constexpr SampleTable<K> TB{};
+  constexpr AliasTable<K> AT{};
   const int g = threadIdx.x / NP;
   const int c = threadIdx.x % NP;
-  const int64_t gq = xcd_block(blockIdx.x, gridDim.x) * GB + g;
+  double* sU = lds + g * C::PG;          // [3][n]  u_j modes at the point
+  double* sVv = sU + 3 * n;              // [3][n]  v_i = G_ij u_j
+  double* sUt = sVv + 3 * n;             // [3][M]  samples
+  double* sVt = sUt + 3 * M;             // [3][M]
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t gq = blk * GB + g;
   const int64_t e = gq >> 2;
   const int q = (int)(gq & 3);
   const bool valid = e < v.n_tets;
   double dN[4][3];
-  double wq = 0.0;
   int nodes[4] = {0, 0, 0, 0};
-  if (valid) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      nodes[b] = v.conn[e * 4 + b];
+  for (int b = 0; b < 4; ++b) {
+    if (valid) nodes[b] = v.conn[e * 4 + b];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) dN[b][i] = v.geo[e * 16 + b * 3 + i];
-    }
-    wq = v.geo[e * 16 + 12];
-  } else {
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int i = 0; i < 3; ++i) dN[b][i] = 0.0;
+    for (int i = 0; i < 3; ++i) dN[b][i] = valid ? v.geo[e * 16 + b * 3 + i] : 0.0;
   }
-  (void)wq;
   double Gm[3][3];
   double GG = 0.0;
 #pragma unroll
@@ -164,14 +171,14 @@ k_tau(DevView v, const double* __restrict__ Y, double* __restrict__ tau) {
       double acc = 0.0;
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc += lamq(q, b) * slot_x(Y + ((int64_t)nodes[b] * 4 + j) * S, c);
-      sU[g][j][c] = acc;
+      sU[j * n + c] = acc;
     }
   }
   __syncthreads();
   if (valid && c < n) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
-      sVv[g][i][c] = Gm[i][0] * sU[g][0][c] + Gm[i][1] * sU[g][1][c] + Gm[i][2] * sU[g][2][c];
+      sVv[i * n + c] = Gm[i][0] * sU[c] + Gm[i][1] * sU[n + c] + Gm[i][2] * sU[2 * n + c];
   }
   __syncthreads();
   if (valid) {
@@ -181,11 +188,11 @@ k_tau(DevView v, const double* __restrict__ Y, double* __restrict__ tau) {
         double au = 0.0, av = 0.0;
 #pragma unroll
         for (int a = 0; a < n; ++a) {
-          au = fma(sU[g][j][a], F[a * M + s], au);
-          av = fma(sVv[g][j][a], F[a * M + s], av);
+          au = fma(sU[j * n + a], F[a * M + s], au);
+          av = fma(sVv[j * n + a], F[a * M + s], av);
         }
-        sUt[g][j][s] = au;
-        sVt[g][j][s] = av;
+        sUt[j * M + s] = au;
+        sVt[j * M + s] = av;
       }
     }
   }
@@ -194,55 +201,98 @@ k_tau(DevView v, const double* __restrict__ Y, double* __restrict__ tau) {
 #pragma unroll
   for (int a = 0; a < n; ++a) w[a] = 0.0;
   if (valid && c < n) {
+    double Fc[M], Z[M];
+#pragma unroll
+    for (int s = 0; s < M; ++s) {
+      Fc[s] = F[c * M + s];
+      Z[s] = 0.0;
+    }
 #pragma unroll 1
     for (int i = 0; i < 3; ++i) {
-      // b = A(v_i) e_c : project v_i(t) phi_c(t) on the K harmonics
-      double bb[n];
+      double x[M];
 #pragma unroll
-      for (int a = 0; a < n; ++a) bb[a] = 0.0;
+      for (int s = 0; s < M; ++s) x[s] = sVt[i * M + s] * Fc[s];
 #pragma unroll
-      for (int s = 0; s < M; ++s) {
-        const double t = sVt[g][i][s] * F[c * M + s];
+      for (int r = 0; r < K; ++r) {
+        double d = 0.0;
 #pragma unroll
-        for (int a = 0; a < n; ++a) bb[a] = fma(t, TB.b[a][s], bb[a]);
+        for (int s = 0; s < M; ++s) d = fma(x[s], AT.v[r][s], d);
+        d *= AT.coef[r];
+#pragma unroll
+        for (int s = 0; s < M; ++s) x[s] = fma(-d, AT.v[r][s], x[s]);
       }
-      // w += A(u_i) b
 #pragma unroll
-      for (int s = 0; s < M; ++s) {
-        double yb = 0.0;
-#pragma unroll
-        for (int a = 0; a < n; ++a) yb = fma(bb[a], TB.f[a][s], yb);
-        const double t = sUt[g][i][s] * yb;
-#pragma unroll
-        for (int a = 0; a < n; ++a) w[a] = fma(t, TB.b[a][s], w[a]);
-      }
+      for (int s = 0; s < M; ++s) Z[s] = fma(sUt[i * M + s], x[s], Z[s]);
     }
 #pragma unroll
-    for (int a = 0; a < n; ++a)
-      if (a == c) w[a] += kap;
+    for (int a = 0; a < n; ++a) {
+      double acc = 0.0;
+#pragma unroll
+      for (int s = 0; s < M; ++s) acc = fma(TB.b[a][s], Z[s], acc);
+      w[a] = a == c ? acc + kap : acc;
+    }
   }
   jacobi_columns<n, NP>(w, c);
   double l2 = 0.0;
 #pragma unroll
   for (int a = 0; a < n; ++a) l2 = fma(w[a], w[a], l2);
-  const double lam = sqrt(l2);
-  if (valid && c < n) {
-    const double sc = lam > 0.0 ? pow(lam, -1.25) : 0.0;
+  const double sc = l2 > 0.0 ? pow(l2, -0.625) : 0.0;   // lambda^(-5/4), lambda = |w|
+  __syncthreads();   // the first-phase arrays are reused below
+  if constexpr (C::MFMA_OUT) {
+    // Q[k][p] = w_k[pos_mode(p)] lambda_k^(-5/4); tau over positions = Q^T Q
+    double* sQ = lds + g * C::PG;
+    for (int i = c; i < PW * QS; i += NP) sQ[i] = 0.0;
+    __syncthreads();
+    if (valid && c < n) {
 #pragma unroll
-    for (int a = 0; a < n; ++a) sQ[g][c * n + a] = w[a] * sc;
-  }
-  __syncthreads();
-  if (valid) {
-    // packed over positions: entry (pr, pc) is tau between modes
-    // pos_mode(pr) and pos_mode(pc)
-    for (int p = c; p < P; p += NP) {
-      int pr, pc;
-      packed_rc<n>(p, pr, pc);
-      const int r = pos_mode(pr, K), cc = pos_mode(pc, K);
-      double acc = 0.0;
+      for (int a = 0; a < n; ++a) sQ[c * QS + mode_pos(a, K)] = w[a] * sc;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, gl = lane >> 4, cl = lane & 15;
+#pragma unroll 1
+    for (int j = 0; j < QW; ++j) {
+      const int gg = wv * QW + j;            // point of this wave
+      const int64_t gqj = blk * GB + gg;
+      const int64_t ej = gqj >> 2;
+      if (ej >= v.n_tets) break;             // uniform across the wave
+      const double* Qj = lds + gg * C::PG;
+      double* tj = tau + gqj * P;
+#pragma unroll
+      for (int tr = 0; tr < PW / 16; ++tr)
+#pragma unroll
+        for (int tc = tr; tc < PW / 16; ++tc) {
+          dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int ks = 0; ks < PW / 4; ++ks) {
+            const double* qr = Qj + (ks * 4 + gl) * QS;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(qr[cl + 16 * tr], qr[cl + 16 * tc], acc, 0, 0, 0);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = gl + 4 * r + 16 * tr, col = cl + 16 * tc;
+            if (row <= col && col < n) tj[pk_index(row, col, n)] = acc[r];
+          }
+        }
+    }
+  } else {
+    double* sQ = lds + g * C::PG;
+    if (valid && c < n) {
+#pragma unroll
+      for (int a = 0; a < n; ++a) sQ[c * n + a] = w[a] * sc;
+    }
+    __syncthreads();
+    if (valid) {
+      // packed over positions: entry (pr, pc) is tau between modes
+      // pos_mode(pr) and pos_mode(pc)
+      for (int p = c; p < P; p += NP) {
+        int pr, pc;
+        packed_rc<n>(p, pr, pc);
+        const int r = pos_mode(pr, K), cc = pos_mode(pc, K);
+        double acc = 0.0;
 #pragma unroll 4
-      for (int k = 0; k < n; ++k) acc = fma(sQ[g][k * n + r], sQ[g][k * n + cc], acc);
-      tau[(e * 4 + q) * P + p] = acc;
+        for (int k = 0; k < n; ++k) acc = fma(sQ[k * n + r], sQ[k * n + cc], acc);
+        tau[(e * 4 + q) * P + p] = acc;
+      }
     }
   }
 }
