@@ -305,7 +305,7 @@ int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv
     *mv_out = 0;
     return TSGLS_OK;
   }
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), h2(m + 1), yv(m);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), h2(2 * m + 3), yv(m);
   bool first = true;
   while (mv < maxmv) {
     double* V0 = c->V;
@@ -333,16 +333,37 @@ int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv
       HIPCHK(c, launch_mul(c->minv, Vj, c->kt, n, c->st));
       CHK(jv_impl(c, c->kt, Vn, jac, dt));
       ++mv;
-      {
-        ProfScope ps(c, TSGLS_PROF_ORTHO);
-        CHK(multidot(c, c->V, n, j + 1, Vn, c->dh, h.data()));
-        HIPCHK(c, launch_multiaxpy(c->V, n, j + 1, c->dh, Vn, n, c->st));
-        CHK(multidot(c, c->V, n, j + 1, Vn, c->dh, h2.data()));
-        HIPCHK(c, launch_multiaxpy(c->V, n, j + 1, c->dh, Vn, n, c->st));
-      }
-      for (int i = 0; i <= j; ++i) h[i] += h2[i];
       double hn;
-      CHK(norm2(c, Vn, &hn));
+      if (j + 1 <= 32) {
+        // CGS2 with the first pass's update fused with the second pass's dots
+        // and the second update fused with the norm: three reads of the basis
+        // and one host synchronisation per step.
+        ProfScope ps(c, TSGLS_PROF_ORTHO);
+        const int J = j + 1, nb = multidot_blocks(n);
+        double* dh1 = c->dh;            // h  [J]
+        double* dh2 = c->dh + J;        // h2 [J]
+        double* dnn = c->dh + 2 * J;    // |Vn|^2
+        HIPCHK(c, launch_multidot(c->V, n, J, Vn, c->partial, nb, n, c->st));
+        HIPCHK(c, launch_reduce_partials(c->partial, nb, J, dh1, c->st));
+        HIPCHK(c, launch_axpy_dot(c->V, n, J, dh1, -1.0, Vn, J, 0, c->partial, nb, n, c->st));
+        HIPCHK(c, launch_reduce_partials(c->partial, nb, J, dh2, c->st));
+        HIPCHK(c, launch_axpy_dot(c->V, n, J, dh2, -1.0, Vn, 0, 1, c->partial, nb, n, c->st));
+        HIPCHK(c, launch_reduce_partials(c->partial, nb, 1, dnn, c->st));
+        HIPCHK(c, hipMemcpyAsync(h2.data(), c->dh, (2 * J + 1) * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(c, hipStreamSynchronize(c->st));
+        for (int i = 0; i < J; ++i) h[i] = h2[i] + h2[J + i];
+        hn = std::sqrt(std::max(h2[2 * J], 0.0));
+      } else {
+        {
+          ProfScope ps(c, TSGLS_PROF_ORTHO);
+          CHK(multidot(c, c->V, n, j + 1, Vn, c->dh, h.data()));
+          HIPCHK(c, launch_multiaxpy(c->V, n, j + 1, c->dh, Vn, n, c->st));
+          CHK(multidot(c, c->V, n, j + 1, Vn, c->dh, h2.data()));
+          HIPCHK(c, launch_multiaxpy(c->V, n, j + 1, c->dh, Vn, n, c->st));
+        }
+        for (int i = 0; i <= j; ++i) h[i] += h2[i];
+        CHK(norm2(c, Vn, &hn));
+      }
       if (!std::isfinite(hn)) return fail(c, TSGLS_ENONFINITE, "non-finite Krylov vector");
       if (hn > 0) HIPCHK(c, launch_scal_copy(1.0 / hn, Vn, Vn, n, c->st));
       for (int i = 0; i < j; ++i) {

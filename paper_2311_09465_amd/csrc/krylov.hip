@@ -135,6 +135,81 @@ hipError_t launch_reduce_partials(const double* partial, int nblocks, int J, dou
   return hipGetLastError();
 }
 
+// Fused Gram-Schmidt update and dots (J <= JT): w += sign * sum_j V[j] h[j],
+// then block partials of V[j] . w_new for j < Jd, and of w_new . w_new in
+// slot Jd when self != 0.  Same chunking and fixed-order block reduction as
+// k_multidot, so the result is reproducible.
+template <int JT>
+__global__ void __launch_bounds__(MD_BS)
+k_axpy_dot(const double* __restrict__ V, int64_t ldv, int J, const double* __restrict__ h,
+           double sign, double* __restrict__ w, int Jd, int self, double* __restrict__ partial,
+           int64_t n, int64_t chunk) {
+  __shared__ double red[MD_TILE][MD_BS];
+  __shared__ double sh[JT];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int Jo = Jd + (self ? 1 : 0);
+  if (t < JT) sh[t] = t < J ? sign * h[t] : 0.0;
+  __syncthreads();
+  const int64_t lo = (int64_t)b * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  double d[JT + 1];
+#pragma unroll
+  for (int j = 0; j <= JT; ++j) d[j] = 0.0;
+  for (int64_t i = lo + t; i < hi; i += MD_BS) {
+    double vj[JT];
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < JT; ++j) {
+      vj[j] = j < J ? V[(int64_t)j * ldv + i] : 0.0;
+      acc = fma(vj[j], sh[j], acc);
+    }
+    const double wn = w[i] + acc;
+    w[i] = wn;
+#pragma unroll
+    for (int j = 0; j < JT; ++j) d[j] = fma(vj[j], wn, d[j]);
+    d[JT] = fma(wn, wn, d[JT]);
+  }
+  for (int j0 = 0; j0 < Jo; j0 += MD_TILE) {
+#pragma unroll
+    for (int k = 0; k < MD_TILE; ++k) {
+      const int o = j0 + k;
+      double x = 0.0;
+      if (self && o == Jd) {
+        x = d[JT];
+      } else {
+#pragma unroll
+        for (int j = 0; j < JT; ++j)
+          if (j == o) x = d[j];
+      }
+      red[k][t] = x;
+    }
+    __syncthreads();
+    for (int s = MD_BS / 2; s > 0; s >>= 1) {
+      if (t < s) {
+#pragma unroll
+        for (int k = 0; k < MD_TILE; ++k) red[k][t] += red[k][t + s];
+      }
+      __syncthreads();
+    }
+    if (t < MD_TILE && j0 + t < Jo) partial[(int64_t)b * Jo + j0 + t] = red[t][0];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_axpy_dot(const double* V, int64_t ldv, int J, const double* h, double sign,
+                           double* w, int Jd, int self, double* partial, int nblocks, int64_t n,
+                           hipStream_t st) {
+  if (J < 0 || Jd < 0 || Jd > J) return hipErrorInvalidValue;
+  const int64_t chunk = (n + nblocks - 1) / nblocks;
+#define L(JT) k_axpy_dot<JT><<<nblocks, MD_BS, 0, st>>>(V, ldv, J, h, sign, w, Jd, self, partial, n, chunk)
+  if (J <= 8) L(8);
+  else if (J <= 16) L(16);
+  else if (J <= 32) L(32);
+  else return hipErrorInvalidValue;
+#undef L
+  return hipGetLastError();
+}
+
 // w -= sum_j V[j] h[j]   (h on device, J <= 1024)
 __global__ void k_multiaxpy(const double* __restrict__ V, int64_t ldv, int J, const double* __restrict__ h,
                             double* __restrict__ w, int64_t n, double sign) {
