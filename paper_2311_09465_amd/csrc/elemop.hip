@@ -54,8 +54,13 @@ __device__ __forceinline__ double swap_pair(double x) {
   return __hiloint2double(hi, lo);
 }
 
+// Waves per SIMD the register allocation must allow: the Picard tangent
+// (the launch repeated inside GMRES) fits three without spilling.
+template <int MODE>
+constexpr int op_waves() { return MODE == 0 ? 3 : 1; }
+
 template <int K, int MODE>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(op_waves<MODE>())))
 k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
      double* __restrict__ Zout, double* __restrict__ out, double shift, int64_t begin,
      int64_t end) {
@@ -152,6 +157,17 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
   const int64_t cnt = end - begin;
   const int64_t lo = begin + cnt * xcd / 8, hi = begin + cnt * (xcd + 1) / 8;
 
+  // packed tau of the next element is loaded one element ahead (it streams
+  // from HBM with no reuse, so its latency is hidden behind the current one)
+  double tv[4][NTL];
+  if (lo + jx < hi) {
+    const int64_t e0 = lo + jx;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int j = 0; j < NTL; ++j) tv[q][j] = tok[j] ? v.tau[(e0 * 4 + q) * P + lane + 64 * j] : 0.0;
+  }
+
   for (int64_t e = lo + jx; e < hi; e += nbx) {
     int nd[4];
     double dN[4][3];
@@ -163,13 +179,7 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
     }
     const double wgt = v.geo[e * 16 + 12];
 
-    // global loads of tau and the modal input first (consumed after products)
-    double tv[4][NTL];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int j = 0; j < NTL; ++j)
-        tv[q][j] = tok[j] ? v.tau[(e * 4 + q) * P + lane + 64 * j] : 0.0;
+    // modal input first (consumed after the products)
     double xv[4][NPT];
 #pragma unroll
     for (int b = 0; b < 4; ++b)
@@ -253,6 +263,13 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
         const int fp = pt * 64 + lane;   // field * PW + position within the node's block
         sV[(b * 4 + fp / PW) * RP + fp % PW] = xv[b][pt];
       }
+    if (e + nbx < hi) {
+      const int64_t en = e + nbx;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int j = 0; j < NTL; ++j) tv[q][j] = tok[j] ? v.tau[(en * 4 + q) * P + lane + 64 * j] : 0.0;
+    }
     __syncthreads();
 
     // ---- conv(t) -> modes: lane (q = g, p), reg i
