@@ -395,23 +395,50 @@ k_diag(DevView v, double* __restrict__ d, double shift, int64_t begin, int64_t e
   }
 }
 
-// Node-wise sum of element contributions (ascending element order): thread
-// per (node, slot of the node's 4 S values).
+// Node-wise sum of element contributions (ascending element order): one
+// wave per node, lane j < 4S summing slot j of the node's incident element
+// rows; the incidence list is read with scalar loads.
 template <int K>
-__global__ void k_gather(const int32_t* __restrict__ noff, const int32_t* __restrict__ ninc,
-                         const uint8_t* __restrict__ nflag, const double* __restrict__ ebuf,
-                         double* __restrict__ out, int64_t nn) {
+__global__ void __launch_bounds__(256)
+k_gather(const int32_t* __restrict__ noff, const int32_t* __restrict__ ninc,
+         const uint8_t* __restrict__ nflag, const double* __restrict__ ebuf,
+         double* __restrict__ out, int64_t nn) {
   constexpr int S = Dim<K>::S, S4 = 4 * S;
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= nn * S4) return;
-  const int64_t node = idx / S4;
-  const int j = (int)(idx % S4);
-  double acc = 0.0;
-  if (j >= 3 * S || !(nflag[node] & 1)) {
-    const int k0 = noff[node], k1 = noff[node + 1];
-    for (int k = k0; k < k1; ++k) acc += ebuf[(int64_t)ninc[k] * S4 + j];
+  constexpr int NJ = (S4 + 63) / 64;
+  const int64_t node = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (node >= nn) return;
+  const int lane = threadIdx.x & 63;
+  const int k0 = noff[node], k1 = noff[node + 1];
+  const bool dir = (nflag[node] & 1) != 0;
+  double acc[NJ];
+#pragma unroll
+  for (int r = 0; r < NJ; ++r) acc[r] = 0.0;
+  int k = k0;
+  for (; k + 4 <= k1; k += 4) {
+    const int64_t i0 = (int64_t)ninc[k] * S4, i1 = (int64_t)ninc[k + 1] * S4;
+    const int64_t i2 = (int64_t)ninc[k + 2] * S4, i3 = (int64_t)ninc[k + 3] * S4;
+#pragma unroll
+    for (int r = 0; r < NJ; ++r) {
+      const int j = lane + 64 * r;
+      if (j < S4) {
+        const double a0 = ebuf[i0 + j], a1 = ebuf[i1 + j], a2 = ebuf[i2 + j], a3 = ebuf[i3 + j];
+        acc[r] = (((acc[r] + a0) + a1) + a2) + a3;
+      }
+    }
   }
-  out[idx] = acc;
+  for (; k < k1; ++k) {
+    const int64_t i0 = (int64_t)ninc[k] * S4;
+#pragma unroll
+    for (int r = 0; r < NJ; ++r) {
+      const int j = lane + 64 * r;
+      if (j < S4) acc[r] += ebuf[i0 + j];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NJ; ++r) {
+    const int j = lane + 64 * r;
+    if (j < S4) out[node * S4 + j] = (dir && j < 3 * S) ? 0.0 : acc[r];
+  }
 }
 
 template <int K>
@@ -492,7 +519,7 @@ hipError_t launch_gather(int K, const int32_t* noff, const int32_t* ninc, const 
                          const double* ebuf, double* out, int64_t nn, hipStream_t st) {
   const int64_t tot = nn * 4 * (2 * K + 2);
   if (tot == 0) return hipSuccess;
-  const unsigned grid = (unsigned)((tot + 255) / 256);
+  const unsigned grid = (unsigned)((nn + 3) / 4);
   switch (K) {
 #define CASE(k) case k: k_gather<k><<<grid, 256, 0, st>>>(noff, ninc, nflag, ebuf, out, nn); break;
     TSGLS_FOR_EACH_K(CASE)
