@@ -90,63 +90,68 @@ k_face_lin(DevView v, const double* __restrict__ UTs, double* __restrict__ aneg)
   }
 }
 
-// Thread per (Neumann node, velocity component): gathers the contributions of
-// the node's incident faces in a fixed order (deterministic, one launch).
-// resid != 0: input is the state (unmasked) and the traction term is
-// included; otherwise the input is a direction (Dirichlet entries masked).
+// Backflow and traction terms in two steps.  First one block per (face,
+// face point): lane (i, m) forms y_i[m] = coef sum_c (|A_n|_-)_mc u_i[c] with
+// u the input interpolated at the point (Dirichlet rows of a direction
+// masked), coef = -(rho beta / 2) area / 3.  Then one thread per (Neumann
+// node, component, mode) sums lam_q(node) y over its incident faces and
+// points in a fixed order (deterministic) and adds it to the output.
 template <int K>
-__global__ void k_face_apply(DevView v, const double* __restrict__ Y, int resid,
-                             const double* __restrict__ an, double* __restrict__ out) {
+__global__ void __launch_bounds__(128)
+k_face_point(DevView v, const double* __restrict__ Y, int resid, const double* __restrict__ an) {
   constexpr int n = Dim<K>::n, S = Dim<K>::S, P = Dim<K>::P;
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= v.n_fnodes * 3) return;
-  const int64_t u = idx / 3;
-  const int i = (int)(idx % 3);
-  const int64_t node = v.fnode[u];
-  if (v.nflag[node] & 1) return;
-  double o[n];
-#pragma unroll
-  for (int m = 0; m < n; ++m) o[m] = 0.0;
-  for (int k = v.foff[u]; k < v.foff[u + 1]; ++k) {
-    const int64_t f = v.finc[k] / 3;
-    const int a = v.finc[k] % 3;
-    const double area = v.fgeo[f * 4 + 3];
-    double xb[3][n];
+  __shared__ double su[3 * n];
+  const int64_t fq = blockIdx.x;           // face * 3 + point
+  const int64_t f = fq / 3;
+  const int q = (int)(fq % 3);
+  const int t = threadIdx.x;
+  const int i = t / n, m = t % n;
+  if (t < 3 * n) {
+    double acc = 0.0;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
       const int64_t nb = v.fconn[f * 3 + b];
       const bool z = !resid && (v.nflag[nb] & 1);
-#pragma unroll
-      for (int m = 0; m < n; ++m) xb[b][m] = z ? 0.0 : slot_x(Y + (nb * 4 + i) * S, m);
+      acc += z ? 0.0 : flam(q, b) * slot_x(Y + (nb * 4 + i) * S, m);
     }
-    const double coef = -0.5 * v.rho * v.beta * area / 3.0;
-#pragma unroll 1
-    for (int q = 0; q < 3; ++q) {
-      double uq[n];
+    su[i * n + m] = acc;
+  }
+  __syncthreads();
+  if (t < 3 * n) {
+    const double* ap = an + fq * P;
+    double acc = 0.0;
 #pragma unroll
-      for (int m = 0; m < n; ++m) uq[m] = flam(q, 0) * xb[0][m] + flam(q, 1) * xb[1][m] + flam(q, 2) * xb[2][m];
-      const double* tp = an + (f * 3 + q) * P;
-      const double lw = coef * flam(q, a);
-      int p = 0;
-#pragma unroll
-      for (int r = 0; r < n; ++r)
-#pragma unroll
-        for (int cc = r; cc < n; ++cc) {
-          const double t = lw * tp[p++];
-          o[r] = fma(t, uq[cc], o[r]);
-          if (cc != r) o[cc] = fma(t, uq[r], o[cc]);
-        }
+    for (int cc = 0; cc < n; ++cc) {
+      const int lo = m < cc ? m : cc, hi = m < cc ? cc : m;
+      acc = fma(ap[lo * n - (lo * (lo - 1)) / 2 + (hi - lo)], su[i * n + cc], acc);
     }
-    if (resid && v.fh) {
-      const double ni = v.fgeo[f * 4 + i];
-#pragma unroll
-      for (int m = 0; m < n; ++m) o[m] -= area / 3.0 * v.fh[f * n + m] * ni;
-    }
+    const double coef = -0.5 * v.rho * v.beta * v.fgeo[f * 4 + 3] / 3.0;
+    v.fy[fq * (3 * n) + i * n + m] = coef * acc;
+  }
+}
+
+template <int K>
+__global__ void k_face_apply(DevView v, int resid, double* __restrict__ out) {
+  constexpr int n = Dim<K>::n, S = Dim<K>::S;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= v.n_fnodes * 3 * n) return;
+  const int64_t u = idx / (3 * n);
+  const int i = (int)((idx / n) % 3), m = (int)(idx % n);
+  const int64_t node = v.fnode[u];
+  if (v.nflag[node] & 1) return;
+  double o = 0.0;
+  for (int k = v.foff[u]; k < v.foff[u + 1]; ++k) {
+    const int64_t f = v.finc[k] / 3;
+    const int a = v.finc[k] % 3;
+    const double* y = v.fy + f * 3 * (3 * n) + i * n + m;
+    o += flam(0, a) * y[0] + flam(1, a) * y[3 * n] + flam(2, a) * y[6 * n];
+    if (resid && v.fh) o -= v.fgeo[f * 4 + 3] / 3.0 * v.fh[f * n + m] * v.fgeo[f * 4 + i];
   }
   double* op = out + (node * 4 + i) * S;
-  op[0] += o[0];
-#pragma unroll
-  for (int m = 1; m < n; ++m) op[m + 1] += o[m] * TS_RS2;
+  if (m == 0)
+    op[0] += o;
+  else
+    op[m + 1] += o * TS_RS2;
 }
 
 template <int K>
@@ -202,10 +207,15 @@ hipError_t launch_face_lin(const DevView& v, const double* UTs, double* aneg, hi
 
 hipError_t launch_face_apply(const DevView& v, const double* Y, int resid, const double* an,
                              double* out, hipStream_t st) {
-  if (v.n_fnodes == 0) return hipSuccess;
-  const unsigned grid = (unsigned)((v.n_fnodes * 3 + 127) / 128);
+  if (v.n_fnodes == 0 || v.n_faces == 0) return hipSuccess;
   switch (v.K) {
-#define CASE(k) case k: k_face_apply<k><<<grid, 128, 0, st>>>(v, Y, resid, an, out); break;
+#define CASE(k)                                                                             \
+  case k: {                                                                                 \
+    k_face_point<k><<<(unsigned)(v.n_faces * 3), (3 * Dim<k>::n + 63) / 64 * 64, 0, st>>>(v, Y, resid, an); \
+    const int64_t tot = v.n_fnodes * 3 * Dim<k>::n;                                         \
+    k_face_apply<k><<<(unsigned)((tot + 127) / 128), 128, 0, st>>>(v, resid, out);          \
+    break;                                                                                  \
+  }
     TSGLS_FOR_EACH_K(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;

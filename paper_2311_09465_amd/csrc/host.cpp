@@ -45,6 +45,7 @@ struct tsgls_ctx {
   double* fgeo = nullptr;
   double* fh = nullptr;
   double* aneg = nullptr;
+  double* fy = nullptr;         // [nf][3][3][n] face-point scratch
   // residual-only scratch (keeps the linearization intact)
   double* UTr = nullptr;
   double* taur = nullptr;
@@ -152,6 +153,7 @@ DevView view(const tsgls_ctx* c) {
   v.fgeo = c->fgeo;
   v.fh = c->fh;
   v.aneg = c->aneg;
+  v.fy = c->fy;
   v.rho = c->p.rho;
   v.mu = c->p.mu;
   v.omega = c->p.omega;
@@ -534,12 +536,13 @@ int tsgls_set_neumann(tsgls_ctx* c, const int32_t* tris, int64_t nf, const doubl
   dfree(c, c->fgeo);
   dfree(c, c->fh);
   dfree(c, c->aneg);
+  dfree(c, c->fy);
   dfree(c, c->anegr);
   dfree(c, c->fnode);
   dfree(c, c->foff);
   dfree(c, c->finc);
   c->fconn = c->fnode = c->foff = c->finc = nullptr;
-  c->fgeo = c->fh = c->aneg = c->anegr = nullptr;
+  c->fgeo = c->fh = c->aneg = c->anegr = c->fy = nullptr;
   c->nf = 0;
   c->n_fnodes = 0;
   c->linearized = false;
@@ -596,6 +599,7 @@ int tsgls_set_neumann(tsgls_ctx* c, const int32_t* tris, int64_t nf, const doubl
   CHK(dalloc(c, &c->fconn, nf * 3));
   CHK(dalloc(c, &c->fgeo, nf * 4));
   CHK(dalloc(c, &c->aneg, (size_t)nf * 3 * c->P));
+  CHK(dalloc(c, &c->fy, (size_t)nf * 9 * c->n));
   HIPCHK(c, hipMemcpyAsync(c->fconn, sc.data(), sc.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->fgeo, sg.data(), sg.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
   if (h) {

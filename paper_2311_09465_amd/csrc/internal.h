@@ -57,6 +57,7 @@ struct DevView {
   const double* fgeo;        // [nf][4] unit outward normal, area
   const double* fh;          // [nf][n] traction modes (real basis) or null
   const double* aneg;        // [nf][3][P] |A_n|_- packed per face point
+  double* fy;                // [nf][3][3][n] scratch: |A_n|_- u per face point
   double rho, mu, omega, C_I, beta;
 };
 
