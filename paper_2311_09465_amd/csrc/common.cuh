@@ -186,10 +186,10 @@ __device__ __forceinline__ void jacobi_round(double (&w)[n], double& nrm, int c,
   for (int a = 0; a < n; ++a) o[a] = xor_lane<k>(w[a]);
   const double onrm = xor_lane<k>(nrm);
   const bool low = c < (c ^ k);
-  // same summation order on both lanes: lo . hi
+  // the same sum on both lanes (fma is commutative in its factors)
   double ga = 0.0;
 #pragma unroll
-  for (int a = 0; a < n; ++a) ga = low ? fma(w[a], o[a], ga) : fma(o[a], w[a], ga);
+  for (int a = 0; a < n; ++a) ga = fma(w[a], o[a], ga);
   const double al = low ? nrm : onrm, be = low ? onrm : nrm;
   const double ab = al * be;
   const double g2 = ga * ga;
@@ -202,10 +202,12 @@ __device__ __forceinline__ void jacobi_round(double (&w)[n], double& nrm, int c,
     const double t = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) * rcp_nr(fabs(d) + r);
     const double cs = rsq_nr(fma(t, t, 1.0));
     const double sn = cs * t;
+    // lo' = cs lo - sn hi, hi' = sn lo + cs hi: each lane keeps its own column
+    const double so = low ? -sn : sn;
 #pragma unroll
-    for (int a = 0; a < n; ++a) w[a] = low ? fma(cs, w[a], -sn * o[a]) : fma(sn, o[a], cs * w[a]);
-    const double c2 = cs * cs, s2 = sn * sn, cs2 = 2.0 * cs * sn * ga;
-    nrm = low ? fma(c2, al, fma(s2, be, -cs2)) : fma(s2, al, fma(c2, be, cs2));
+    for (int a = 0; a < n; ++a) w[a] = fma(so, o[a], cs * w[a]);
+    const double c2 = cs * cs, s2 = sn * sn, cs2 = 2.0 * so * cs * ga;
+    nrm = fma(c2, nrm, fma(s2, onrm, cs2));
     rot = 1;
   }
 }
