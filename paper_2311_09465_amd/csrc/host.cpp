@@ -345,7 +345,7 @@ int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv
         double* dh1 = c->dh;            // h  [J]
         double* dh2 = c->dh + J;        // h2 [J]
         double* dnn = c->dh + 2 * J;    // |Vn|^2
-        HIPCHK(c, launch_multidot(c->V, n, J, Vn, c->partial, nb, n, c->st));
+        HIPCHK(c, launch_axpy_dot(c->V, n, J, nullptr, 0.0, Vn, J, 0, c->partial, nb, n, c->st));
         HIPCHK(c, launch_reduce_partials(c->partial, nb, J, dh1, c->st));
         HIPCHK(c, launch_axpy_dot(c->V, n, J, dh1, -1.0, Vn, J, 0, c->partial, nb, n, c->st));
         HIPCHK(c, launch_reduce_partials(c->partial, nb, J, dh2, c->st));

@@ -113,7 +113,7 @@ hipError_t launch_multidot(const double* V, int64_t ldv, int J, const double* w,
 // out[j] = sum_b partial[b*J + j] (fixed order)
 hipError_t launch_reduce_partials(const double* partial, int nblocks, int J,
                                   double* out, hipStream_t st);
-// w += sign sum_j V[j] h[j] (J <= 32), then block partials [nblocks][Jo] of
+// w += sign sum_j V[j] h[j] (J <= 32; no update when h is null), then block partials [nblocks][Jo] of
 // V[j] . w for j < Jd and, if self, w . w in slot Jd (Jo = Jd + self).
 hipError_t launch_axpy_dot(const double* V, int64_t ldv, int J, const double* h, double sign,
                            double* w, int Jd, int self, double* partial, int nblocks, int64_t n,

@@ -135,9 +135,9 @@ hipError_t launch_reduce_partials(const double* partial, int nblocks, int J, dou
   return hipGetLastError();
 }
 
-// Fused Gram-Schmidt update and dots (J <= JT): w += sign * sum_j V[j] h[j],
-// then block partials of V[j] . w_new for j < Jd, and of w_new . w_new in
-// slot Jd when self != 0.  Same chunking and fixed-order block reduction as
+// Fused Gram-Schmidt update and dots (J <= JT): w += sign * sum_j V[j] h[j]
+// (skipped when h is null), then block partials of V[j] . w_new for j < Jd,
+// and of w_new . w_new in slot Jd when self != 0.  Same chunking and fixed-order block reduction as
 // k_multidot, so the result is reproducible.
 template <int JT>
 __global__ void __launch_bounds__(MD_BS)
@@ -148,7 +148,8 @@ k_axpy_dot(const double* __restrict__ V, int64_t ldv, int J, const double* __res
   __shared__ double sh[JT];
   const int b = blockIdx.x, t = threadIdx.x;
   const int Jo = Jd + (self ? 1 : 0);
-  if (t < JT) sh[t] = t < J ? sign * h[t] : 0.0;
+  const bool upd = h != nullptr;
+  if (t < JT) sh[t] = (upd && t < J) ? sign * h[t] : 0.0;
   __syncthreads();
   const int64_t lo = (int64_t)b * chunk;
   const int64_t hi = lo + chunk < n ? lo + chunk : n;
@@ -164,7 +165,7 @@ k_axpy_dot(const double* __restrict__ V, int64_t ldv, int J, const double* __res
       acc = fma(vj[j], sh[j], acc);
     }
     const double wn = w[i] + acc;
-    w[i] = wn;
+    if (upd) w[i] = wn;
 #pragma unroll
     for (int j = 0; j < JT; ++j) d[j] = fma(vj[j], wn, d[j]);
     d[JT] = fma(wn, wn, d[JT]);
