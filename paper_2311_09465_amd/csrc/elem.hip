@@ -62,41 +62,60 @@ hipError_t launch_geometry(const double* xyz, const int32_t* conn, double* geo, 
 }
 
 // ------------------------------------------------------- nodal time samples
-// Thread per (node, field f).  f < 3: XT[node][f][s] = u_f(t_s); every f:
-// XP[node][f][p] = mode pos_mode(p) of field f in the orthonormal basis.
+// One wave per node (a block of four waves loops over nodes).  Lane
+// (field f, position p) writes XP[node][f][p] = mode pos_mode(p) of field f
+// in the orthonormal basis; then lane (j, s) forms XT[node][j][s] = u_j(t_s)
+// from the modes staged in LDS.  masked != 0 zeroes Dirichlet velocity rows.
 template <int K>
-__global__ void k_prep_time(const double* __restrict__ Y, const uint8_t* __restrict__ nflag,
-                            int masked, const double* __restrict__ F, double* __restrict__ XT,
-                            double* __restrict__ XP, int64_t nn) {
+__global__ void __launch_bounds__(256)
+k_prep_time(const double* __restrict__ Y, const uint8_t* __restrict__ nflag, int masked,
+            const double* __restrict__ F, double* __restrict__ XT, double* __restrict__ XP,
+            int64_t nn) {
   constexpr int n = Dim<K>::n, S = Dim<K>::S, M = Dim<K>::M, PW = (n + 15) / 16 * 16;
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= nn * 4) return;
-  const int64_t node = idx >> 2;
-  const int f = (int)(idx & 3);
-  const bool zero = masked && f < 3 && (nflag[node] & 1);
-  double x[n];
-  const double* ys = Y + (node * 4 + f) * S;
+  constexpr int NPT = PW / 16, NR = (3 * M + 63) / 64;
+  constexpr bool HOIST = NR == 1;          // the lane's column of F stays in registers
+  __shared__ double sx[4][4 * PW];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int sj[NR], ss[NR];
 #pragma unroll
-  for (int a = 0; a < n; ++a) x[a] = zero ? 0.0 : slot_x(ys, a);
-  double* xp = XP + idx * PW;
-#pragma unroll
-  for (int p = 0; p < PW; ++p) {
-    const int a = pos_mode(p, K);
-    double val = 0.0;
-#pragma unroll
-    for (int b = 0; b < n; ++b)
-      if (b == a) val = x[b];
-    xp[p] = val;
+  for (int r = 0; r < NR; ++r) {
+    const int it = lane + 64 * r < 3 * M ? lane + 64 * r : 0;
+    sj[r] = it / M;
+    ss[r] = it % M;
   }
-  if (f == 3) return;
-  double* o = XT + (node * 3 + f) * M;
-  constexpr SampleTable<K> TB{};
+  double Fl[HOIST ? n : 1];
+  if (HOIST) {
 #pragma unroll
-  for (int s = 0; s < M; ++s) {
-    double acc = 0.0;
+    for (int a = 0; a < n; ++a) Fl[HOIST ? a : 0] = F[a * M + ss[0]];
+  }
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  // the trip count is the same for the four waves of a block (barriers below)
+  for (int64_t base = (int64_t)blockIdx.x * 4; base < nn; base += stride) {
+    const int64_t node = base + wv;
+    const bool act = node < nn;
+    const bool zero = act && masked && (nflag[node] & 1);
 #pragma unroll
-    for (int a = 0; a < n; ++a) acc = fma(x[a], TB.f[a][s], acc);
-    o[s] = acc;
+    for (int pt = 0; pt < NPT; ++pt) {
+      const int fp = pt * 64 + lane, f = fp / PW, pp = fp % PW;
+      const int a = pos_mode(pp, K);
+      double x = 0.0;
+      if (act && a >= 0 && !(zero && f < 3)) x = slot_x(Y + (node * 4 + f) * S, a);
+      if (act) XP[node * (4 * PW) + fp] = x;
+      sx[wv][fp] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (act && lane + 64 * r < 3 * M) {
+        const double* xr = sx[wv] + sj[r] * PW;
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < n; ++a)
+          acc = fma(xr[mode_pos(a, K)], HOIST ? Fl[HOIST ? a : 0] : F[a * M + ss[r]], acc);
+        XT[(node * 3 + sj[r]) * M + ss[r]] = acc;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -474,8 +493,10 @@ int supported_K_list(int* out, int cap) {
 
 hipError_t launch_prep_time(int K, const double* Y, const uint8_t* nflag, int masked,
                             const double* F, double* XT, double* XP, int64_t nn, hipStream_t st) {
-  const unsigned grid = (unsigned)((nn * 4 + 255) / 256);
   if (nn == 0) return hipSuccess;
+  int64_t nb = (nn + 3) / 4;
+  if (nb > 8192) nb = 8192;
+  const unsigned grid = (unsigned)nb;
   switch (K) {
 #define CASE(k) case k: k_prep_time<k><<<grid, 256, 0, st>>>(Y, nflag, masked, F, XT, XP, nn); break;
     TSGLS_FOR_EACH_K(CASE)
