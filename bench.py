@@ -106,6 +106,110 @@ def cpu_baseline(prob, jv_per_step, n_sample=3000):
                 seconds=wall)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_op_junction_1M_K6_traffic.txt")
+KERNEL_SOURCES = ["paper_2311_09465_amd/csrc/elemop.hip", "paper_2311_09465_amd/csrc/common.cuh",
+                  "paper_2311_09465_amd/csrc/internal.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch of the tangent element kernel from the committed
+    rocprofv3 counter summary, or None when that summary is missing or was
+    taken for a different version of the kernel sources."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if "=" in line and not line.startswith(("#", " ")):
+                    k, v = line.split("=", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_hash") != kernel_source_hash():
+            return None
+        return dict(bytes_per_launch=float(kv["hbm_bytes_per_launch"]),
+                    fetch_bytes=float(kv["fetch_bytes_per_launch"]),
+                    write_bytes=float(kv["write_bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def probe(args):
+    """Counter-collection workload: linearize, three tangent products, then a
+    plain device copy of 512 MiB (the reference for scaling the counters)."""
+    import torch
+    import paper_2311_09465_amd as T
+    from workloads import initial_guess
+    prob, _ = _workload(args.workload)
+    s = T.Solver.from_problem(prob)
+    y = torch.from_numpy(initial_guess(prob)).cuda()
+    s.linearize(y)
+    v = torch.randn_like(y)
+    o = torch.zeros_like(y)
+    for _ in range(3):
+        s.jv(v, o, args.jacobian)
+    a = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print("probe done", flush=True)
+
+
+def summarize_pmc(fetch_csv, write_csv, command):
+    """Writes the traffic summary from two rocprofv3 --pmc CSV files
+    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), scaled by what the same
+    counters read for the 512 MiB copy of the probe."""
+    import csv
+
+    def per_kernel(path, counter):
+        rows = list(csv.DictReader(open(path)))
+        out = []
+        for r in rows:
+            if r["Counter_Name"] == counter:
+                out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0))
+        return out
+
+    copy_bytes = float(64 << 20) * 8.0
+    res = {}
+    for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        rows = per_kernel(path, counter)
+        op = [r for r in rows if "k_op<" in r[1] and ", 0>" in r[1]]
+        cp = [r for r in rows if "copy" in r[1].lower()]
+        if not op or not cp:
+            raise SystemExit(f"{path}: kernel or copy dispatch not found")
+        copy_meas = max(r[2] for r in cp)
+        factor = copy_bytes / copy_meas
+        raw = op[-1][2]
+        res[counter] = (raw, factor, raw * factor, copy_meas)
+    fb, wb = res["FETCH_SIZE"][2], res["WRITE_SIZE"][2]
+    lines = [
+        "# HBM traffic of the tangent element kernel k_op<6,0> (junction 1M tets, K = 6)",
+        "# Commands (repository root, one MI355X):",
+        f"#   {command.format(counter='FETCH_SIZE', d='pmc_fetch')}",
+        f"#   {command.format(counter='WRITE_SIZE', d='pmc_write')}",
+        f"#   python bench.py --summarize-pmc <pmc_fetch csv> <pmc_write csv>",
+        "# Counters are KiB per dispatch; each is scaled by (bytes of the 512 MiB probe copy) /",
+        "# (what the same counter reads for that copy).",
+        f"fetch_raw_bytes = {res['FETCH_SIZE'][0]:.0f}",
+        f"fetch_copy_factor = {res['FETCH_SIZE'][1]:.4f}",
+        f"write_raw_bytes = {res['WRITE_SIZE'][0]:.0f}",
+        f"write_copy_factor = {res['WRITE_SIZE'][1]:.4f}",
+        f"fetch_bytes_per_launch = {fb:.0f}",
+        f"write_bytes_per_launch = {wb:.0f}",
+        f"hbm_bytes_per_launch = {fb + wb:.0f}",
+        f"kernel_source_hash = {kernel_source_hash()}",
+    ]
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,7 +220,16 @@ def main():
     ap.add_argument("--jacobian", default="picard")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--probe", action="store_true",
+                    help="counter-collection workload (linearize, 3 tangent products, a 512 MiB copy)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic summary under profiles/ from two rocprofv3 --pmc CSVs")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc,
+                      "rocprofv3 --pmc {counter} --output-format csv -d gpurun_out/{d} -o p -- "
+                      "python bench.py --probe")
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it "
                           "(mesh-partition sharding is described in the design notes)",
@@ -129,6 +242,9 @@ def main():
     from workloads import initial_guess
 
     torch.cuda.set_device(0)
+    if args.probe:
+        probe(args)
+        return
     prob, cfg = _workload(args.workload)
     s = T.Solver.from_problem(prob)
     info = s.info()
@@ -151,27 +267,30 @@ def main():
     secs = t1 - t0
     value = args.steps * m * dof / secs / 1e9
 
-    # dominant kernel: the element kernel of the tangent products
+    # dominant kernel: the element kernel of the tangent products (one launch
+    # over all elements per product)
     launches, tot_ms = prof["elem_tangent"]
     avg_launch_s = tot_ms / max(launches, 1) / 1e3
-    elems_per_launch = E / info["n_colors"]
-    fl = jv_flops_per_element(K, args.jacobian) * elems_per_launch
+    fl = jv_flops_per_element(K, args.jacobian) * E
     achieved = fl / avg_launch_s / 1e12
+    tr = read_traffic() if (args.workload == "junction_1M_K6" and args.jacobian == "picard") else None
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=None,
-                    kernel="k_elem (tangent product, one launch per colour)",
+                    frac=round(achieved / FP64_PEAK_TFLOPS, 4),
+                    traffic=None if tr is None else round(tr["bytes_per_launch"]),
+                    kernel="k_op<K,0> (tangent product element operator)",
                     avg_launch_us=round(avg_launch_s * 1e6, 2), launches=launches,
-                    elements_per_launch=round(elems_per_launch, 1),
+                    elements_per_launch=E,
                     flops_per_element=jv_flops_per_element(K, args.jacobian),
-                    hbm_gbs_equiv=round(jv_bytes(K, E, nn, args.jacobian) / info["n_colors"]
-                                        / avg_launch_s / 1e9, 1))
+                    algorithmic_bytes_per_launch=round(jv_bytes(K, E, nn, args.jacobian)),
+                    hbm_gbs_algorithmic=round(jv_bytes(K, E, nn, args.jacobian) / avg_launch_s / 1e9, 1))
+    if tr is not None:
+        roofline["hbm_gbs_measured"] = round(tr["bytes_per_launch"] / avg_launch_s / 1e9, 1)
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "GDOF-modes/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(secs / args.steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded junction mesh and inflow waveforms)",
-        "config": dict(cfg, n_tets=E, n_nodes=nn, jv_per_step=m, tangent=args.jacobian,
-                       n_colors=info["n_colors"]),
+        "config": dict(cfg, n_tets=E, n_nodes=nn, jv_per_step=m, tangent=args.jacobian),
         "roofline": roofline,
         "breakdown_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in prof.items()},
         "newton_rel_residual_after": st["rel_residual"],
