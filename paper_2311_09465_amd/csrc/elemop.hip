@@ -77,10 +77,11 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
 
   constexpr int NC = 16 * (RS > RM ? RS : RM);
   __shared__ double sV[16 * RP];               // modes [node][field][position]
-  __shared__ double sT[4 * n * n];             // tau_q rows [q][position][position]
+  constexpr int NT = 4 * n * n > NL * 16 * RP ? 4 * n * n : NL * 16 * RP;
+  __shared__ double sT[NT];                    // tau_q rows [q][position][position], then z
   __shared__ double sL[NL * 12 * RP];          // L [q][i][position] (+ grad p part), then G
   __shared__ double sC[NC];                    // conv(t) [16][RS] / z(t) [16][RM] / W(t) [16][RS]
-  __shared__ double sZ[NL * 16 * RP];          // z [q*4+i][position] (+ tau grad p)
+  double* const sZ = sT;                       // z [q*4+i][position] (+ tau grad p)
   __shared__ double sZf[NEWTON ? 16 * RP : 1];    // stored tau L(u) [q*4+i][position]
   __shared__ double sZft[NEWTON ? 16 * RM : 1];   // its samples [i*4+q][s]
   __shared__ double sWq[NEWTON ? 12 * RM : 1];    // direction at the points [q][j][s]
@@ -145,9 +146,10 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
   constexpr double MD = TS_QA * TS_QA + 3.0 * TS_QB * TS_QB;      // sum_q lam_qb^2
   constexpr double MO = 2.0 * TS_QA * TS_QB + 2.0 * TS_QB * TS_QB;  // sum_q lam_qb lam_qc
 
-  // padding that enters the MFMA k dimension must be finite
+  // padding that enters the MFMA k dimension must be finite (z shares the
+  // tau-row buffer, whose contents are always finite once the first element
+  // has been staged)
   for (int i = lane; i < NC; i += 64) sC[i] = 0.0;
-  for (int i = lane; i < NL * 16 * RP; i += 64) sZ[i] = 0.0;
   if (NEWTON)
     for (int i = lane; i < 16 * RP; i += 64) sZf[i] = 0.0;
   __syncthreads();
