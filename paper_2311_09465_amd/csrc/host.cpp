@@ -293,6 +293,179 @@ int ensure_krylov(tsgls_ctx* c, int m) {
   return TSGLS_OK;
 }
 
+// Right-Jacobi-preconditioned restarted GMRES with delayed classical
+// Gram-Schmidt (restart <= 32): the second Gram-Schmidt pass of basis vector
+// j is merged into step j+1's single reduction, so each Arnoldi step makes
+// one reduction and one update pass over the basis and synchronizes once.
+//   step j: w = A u_j (u_j once-orthogonalized, provisional), reduction of
+//   [Q^T u; Q^T w; u.u; u.w; w.w] over the final Q = [q_0 .. q_{j-1}];
+//   nu = |u - Q a|, q_j = (u - Q a)/nu; column j-1 of H is corrected for
+//   u_j = Q a + nu q_j and then passes through the Givens rotations;
+//   provisional column j: A q_j = (w - A Q a)/nu with A Q = Q H;
+//   update pass: q_j into slot j, u_{j+1} = (w - Q b - q_j h_jj)/sigma.
+// The last column is finalized with one extra reduction (no product).
+int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv, int jac,
+                  double dt, int* mv_out) {
+  const int64_t n = ndof(c);
+  const int nb = multidot_blocks(n);
+  HIPCHK(c, launch_zero(x, n, c->st));
+  double bnorm;
+  CHK(norm2(c, b, &bnorm));
+  if (!std::isfinite(bnorm)) return fail(c, TSGLS_ENONFINITE, "non-finite right-hand side");
+  int mv = 0;
+  if (bnorm == 0.0) {
+    *mv_out = 0;
+    return TSGLS_OK;
+  }
+  const int ld = m + 1;
+  // Hh: Hessenberg of the Arnoldi relation A Q = Q H (unrotated);
+  // R: its finalized columns after the Givens rotations (least squares)
+  std::vector<double> Hh((size_t)ld * m), R((size_t)ld * m), cs(m), sn(m), g(m + 1), yv(m),
+      red(2 * 32 + 3), ab(64), col(m + 2);
+  auto H = [&](int i, int j) -> double& { return Hh[(size_t)j * ld + i]; };
+  auto Rr = [&](int i, int j) -> double& { return R[(size_t)j * ld + i]; };
+  auto commit = [&](int j) {   // column j of H is final: rotate it into R, new rotation j
+    for (int i = 0; i <= j + 1; ++i) Rr(i, j) = H(i, j);
+    for (int i = 0; i < j; ++i) {
+      const double t = cs[i] * Rr(i, j) + sn[i] * Rr(i + 1, j);
+      Rr(i + 1, j) = -sn[i] * Rr(i, j) + cs[i] * Rr(i + 1, j);
+      Rr(i, j) = t;
+    }
+    const double den = std::hypot(Rr(j, j), Rr(j + 1, j));
+    cs[j] = den > 0 ? Rr(j, j) / den : 1.0;
+    sn[j] = den > 0 ? Rr(j + 1, j) / den : 0.0;
+    Rr(j, j) = den;
+    Rr(j + 1, j) = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+  };
+  auto reduce = [&](int J, const double* u, const double* w) -> int {
+    ProfScope ps(c, TSGLS_PROF_ORTHO);
+    HIPCHK(c, launch_gs_reduce(c->V, n, J, u, w, c->partial, nb, n, c->st));
+    HIPCHK(c, launch_reduce_partials(c->partial, nb, 2 * J + 3, c->dh, c->st));
+    HIPCHK(c, hipMemcpyAsync(red.data(), c->dh, (2 * J + 3) * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    return TSGLS_OK;
+  };
+  bool first = true;
+  while (mv < maxmv) {
+    double* V0 = c->V;
+    if (first) {
+      HIPCHK(c, launch_copy(b, V0, n, c->st));
+    } else {
+      CHK(jv_impl(c, x, c->kt, jac, dt));
+      ++mv;
+      HIPCHK(c, launch_copy(b, V0, n, c->st));
+      HIPCHK(c, launch_axpy(-1.0, c->kt, V0, n, c->st));
+    }
+    first = false;
+    double beta;
+    CHK(norm2(c, V0, &beta));
+    if (!std::isfinite(beta)) return fail(c, TSGLS_ENONFINITE, "non-finite GMRES residual");
+    if (beta <= tol * bnorm) break;
+    HIPCHK(c, launch_scal_copy(1.0 / beta, V0, V0, n, c->st));
+    std::fill(Hh.begin(), Hh.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    bool done = false;
+    for (int j = 0; j < m && mv < maxmv; ++j) {
+      double* u = c->V + (int64_t)j * n;
+      double* w = c->V + (int64_t)(j + 1) * n;
+      HIPCHK(c, launch_mul(c->minv, u, c->kt, n, c->st));
+      CHK(jv_impl(c, c->kt, w, jac, dt));
+      ++mv;
+      CHK(reduce(j, u, w));
+      const double* a = red.data();
+      const double* bq = red.data() + j;
+      const double uu = red[2 * j], uw = red[2 * j + 1], ww = red[2 * j + 2];
+      if (!std::isfinite(uu) || !std::isfinite(ww)) return fail(c, TSGLS_ENONFINITE, "non-finite Krylov vector");
+      double aa = 0.0, abq = 0.0, bbq = 0.0;
+      for (int i = 0; i < j; ++i) {
+        aa += a[i] * a[i];
+        abq += a[i] * bq[i];
+        bbq += bq[i] * bq[i];
+      }
+      const double nu = std::sqrt(std::max(uu - aa, 0.0));
+      if (!(nu > 0.0)) {   // u_j in span(Q): column j-1 ends the Krylov space
+        if (j >= 1) {
+          H(j, j - 1) = 0.0;
+          commit(j - 1);
+        }
+        k = j;
+        done = true;
+        break;
+      }
+      if (j >= 1) {        // column j-1 for u_j = Q a + nu q_j; now final
+        const double sj = H(j, j - 1);
+        for (int i = 0; i < j; ++i) H(i, j - 1) += sj * a[i];
+        H(j, j - 1) = sj * nu;
+        commit(j - 1);
+        k = j;
+      }
+      // provisional column j: A q_j = (w - A Q a) / nu, A Q a = Q (H a)
+      const double hj = (uw - abq) / nu;
+      for (int i = 0; i <= j; ++i) {
+        double ha = 0.0;
+        for (int l = (i > 0 ? i - 1 : 0); l < j; ++l) ha += H(i, l) * a[l];
+        H(i, j) = ((i < j ? bq[i] : hj) - ha) / nu;
+      }
+      const double s2 = ww - bbq - hj * hj;
+      const double sigma = std::sqrt(std::max(s2, 1e-30 * ww));
+      H(j + 1, j) = sigma / nu;
+      for (int i = 0; i < j; ++i) {
+        ab[i] = a[i];
+        ab[j + i] = bq[i];
+      }
+      {
+        ProfScope ps(c, TSGLS_PROF_ORTHO);
+        if (j > 0) HIPCHK(c, hipMemcpyAsync(c->dh + 512, ab.data(), 2 * j * sizeof(double), hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, launch_gs_update(c->V, n, j, c->dh + 512, 1.0 / nu, hj, 1.0 / sigma, u, w, n, c->st));
+      }
+      // provisional least-squares residual with column j as it stands
+      bool last = (j + 1 == m) || (mv >= maxmv);
+      if (!last) {
+        for (int i = 0; i <= j + 1; ++i) col[i] = H(i, j);
+        for (int i = 0; i < j; ++i) {
+          const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+          col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+          col[i] = t;
+        }
+        const double den = std::hypot(col[j], col[j + 1]);
+        const double res = den > 0 ? std::fabs(col[j + 1] / den * g[j]) : std::fabs(g[j]);
+        if (res <= tol * bnorm) last = true;
+      }
+      if (last) {          // finalize column j against the once-orthogonalized u_{j+1}
+        CHK(reduce(j + 1, w, w));
+        double a2 = 0.0;
+        for (int i = 0; i <= j; ++i) a2 += red[i] * red[i];
+        const double nu2 = std::sqrt(std::max(red[2 * (j + 1)] - a2, 0.0));
+        const double sj = H(j + 1, j);
+        for (int i = 0; i <= j; ++i) H(i, j) += sj * red[i];
+        H(j + 1, j) = sj * nu2;
+        commit(j);
+        k = j + 1;
+        done = std::fabs(g[k]) <= tol * bnorm;
+        break;
+      }
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int l = i + 1; l < k; ++l) s -= Rr(i, l) * yv[l];
+      yv[i] = s / Rr(i, i);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->dh + 1024, yv.data(), k * sizeof(double), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, launch_zero(c->kt, n, c->st));
+    HIPCHK(c, launch_multiaxpy_add(c->V, n, k, c->dh + 1024, c->kt, n, c->st));
+    HIPCHK(c, launch_mul(c->minv, c->kt, c->kt2, n, c->st));
+    HIPCHK(c, launch_axpy(1.0, c->kt2, x, n, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (done) break;
+  }
+  *mv_out = mv;
+  return TSGLS_OK;
+}
+
 // Right-Jacobi-preconditioned restarted GMRES with classical Gram-Schmidt and
 // one reorthogonalization pass; x = J^{-1} b approximately, x zeroed first.
 int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv, int jac,
@@ -709,7 +882,10 @@ int tsgls_solve(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_
     // b = -r in kt2 is overwritten inside gmres; keep it in the last Krylov slot-free buffer
     HIPCHK(c, launch_scal_copy(-1.0, r, r, n, c->st));
     int mv = 0;
-    CHK(gmres(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, o->dt_pseudo, &mv));
+    if (o->restart <= 32)
+      CHK(gmres_delayed(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, o->dt_pseudo, &mv));
+    else
+      CHK(gmres(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, o->dt_pseudo, &mv));
     st.matvecs += mv;
     HIPCHK(c, launch_axpy(1.0, c->kx, y, n, c->st));
     CHK(linearize_impl(c, y, r));

@@ -118,6 +118,14 @@ hipError_t launch_reduce_partials(const double* partial, int nblocks, int J,
 hipError_t launch_axpy_dot(const double* V, int64_t ldv, int J, const double* h, double sign,
                            double* w, int Jd, int self, double* partial, int nblocks, int64_t n,
                            hipStream_t st);
+// Delayed Gram-Schmidt passes (J <= 32).  Reduction: partials [nblocks][2J+3]
+// of Q^T u, Q^T w, u.u, u.w, w.w.  Update: u <- (u - Q a) inv_nu,
+// w <- (w - Q b - u h) inv_sigma with ab = [a (J); b (J)] on the device.
+hipError_t launch_gs_reduce(const double* Q, int64_t ldq, int J, const double* u, const double* w,
+                            double* partial, int nblocks, int64_t n, hipStream_t st);
+hipError_t launch_gs_update(const double* Q, int64_t ldq, int J, const double* ab, double inv_nu,
+                            double h, double inv_sigma, double* u, double* w, int64_t n,
+                            hipStream_t st);
 // w -= sum_j V[j] h[j]
 hipError_t launch_multiaxpy(const double* V, int64_t ldv, int J, const double* h,
                             double* w, int64_t n, hipStream_t st);

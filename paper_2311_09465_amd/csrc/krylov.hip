@@ -211,6 +211,115 @@ hipError_t launch_axpy_dot(const double* V, int64_t ldv, int J, const double* h,
   return hipGetLastError();
 }
 
+// Delayed classical Gram-Schmidt (one reduction and one update pass over the
+// basis per Arnoldi step).  Reduction: block partials of [Q^T u; Q^T w; u.u;
+// u.w; w.w] for the J rows of Q (fixed chunking and block tree, as
+// k_multidot).  Update: u <- (u - Q a) / nu, then w <- (w - Q b - u h) / sigma
+// with the updated u.
+template <int JT>
+__global__ void __launch_bounds__(MD_BS)
+k_gs_reduce(const double* __restrict__ Q, int64_t ldq, int J, const double* __restrict__ u,
+            const double* __restrict__ w, double* __restrict__ partial, int64_t n, int64_t chunk) {
+  __shared__ double red[MD_TILE][MD_BS];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int Jo = 2 * J + 3;
+  const int64_t lo = (int64_t)b * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  double da[JT], db[JT], uu = 0.0, uw = 0.0, ww = 0.0;
+#pragma unroll
+  for (int j = 0; j < JT; ++j) da[j] = db[j] = 0.0;
+  for (int64_t i = lo + t; i < hi; i += MD_BS) {
+    const double ui = u[i], wi = w[i];
+#pragma unroll
+    for (int j = 0; j < JT; ++j) {
+      const double q = j < J ? Q[(int64_t)j * ldq + i] : 0.0;
+      da[j] = fma(q, ui, da[j]);
+      db[j] = fma(q, wi, db[j]);
+    }
+    uu = fma(ui, ui, uu);
+    uw = fma(ui, wi, uw);
+    ww = fma(wi, wi, ww);
+  }
+  for (int j0 = 0; j0 < Jo; j0 += MD_TILE) {
+#pragma unroll
+    for (int k = 0; k < MD_TILE; ++k) {
+      const int o = j0 + k;
+      double x = 0.0;
+#pragma unroll
+      for (int j = 0; j < JT; ++j) {
+        if (o == j && j < J) x = da[j];
+        if (o == J + j && j < J) x = db[j];
+      }
+      if (o == 2 * J) x = uu;
+      if (o == 2 * J + 1) x = uw;
+      if (o == 2 * J + 2) x = ww;
+      red[k][t] = x;
+    }
+    __syncthreads();
+    for (int s = MD_BS / 2; s > 0; s >>= 1) {
+      if (t < s) {
+#pragma unroll
+        for (int k = 0; k < MD_TILE; ++k) red[k][t] += red[k][t + s];
+      }
+      __syncthreads();
+    }
+    if (t < MD_TILE && j0 + t < Jo) partial[(int64_t)b * Jo + j0 + t] = red[t][0];
+    __syncthreads();
+  }
+}
+
+template <int JT>
+__global__ void __launch_bounds__(MD_BS)
+k_gs_update(const double* __restrict__ Q, int64_t ldq, int J, const double* __restrict__ ab,
+            double inv_nu, double h, double inv_sigma, double* __restrict__ u,
+            double* __restrict__ w, int64_t n) {
+  __shared__ double sa[JT], sb[JT];
+  if (threadIdx.x < JT) {
+    sa[threadIdx.x] = threadIdx.x < J ? ab[threadIdx.x] : 0.0;
+    sb[threadIdx.x] = threadIdx.x < J ? ab[J + threadIdx.x] : 0.0;
+  }
+  __syncthreads();
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double pa = 0.0, pb = 0.0;
+#pragma unroll
+    for (int j = 0; j < JT; ++j) {
+      const double q = j < J ? Q[(int64_t)j * ldq + i] : 0.0;
+      pa = fma(q, sa[j], pa);
+      pb = fma(q, sb[j], pb);
+    }
+    const double un = (u[i] - pa) * inv_nu;
+    u[i] = un;
+    w[i] = (w[i] - pb - un * h) * inv_sigma;
+  }
+}
+
+hipError_t launch_gs_reduce(const double* Q, int64_t ldq, int J, const double* u, const double* w,
+                            double* partial, int nblocks, int64_t n, hipStream_t st) {
+  if (J < 0 || J > 32) return hipErrorInvalidValue;
+  const int64_t chunk = (n + nblocks - 1) / nblocks;
+#define L(JT) k_gs_reduce<JT><<<nblocks, MD_BS, 0, st>>>(Q, ldq, J, u, w, partial, n, chunk)
+  if (J <= 8) L(8);
+  else if (J <= 16) L(16);
+  else L(32);
+#undef L
+  return hipGetLastError();
+}
+
+hipError_t launch_gs_update(const double* Q, int64_t ldq, int J, const double* ab, double inv_nu,
+                            double h, double inv_sigma, double* u, double* w, int64_t n,
+                            hipStream_t st) {
+  if (J < 0 || J > 32) return hipErrorInvalidValue;
+  if (n == 0) return hipSuccess;
+  int64_t g = (n + MD_BS - 1) / MD_BS;
+  if (g > 8192) g = 8192;
+#define L(JT) k_gs_update<JT><<<(unsigned)g, MD_BS, 0, st>>>(Q, ldq, J, ab, inv_nu, h, inv_sigma, u, w, n)
+  if (J <= 8) L(8);
+  else if (J <= 16) L(16);
+  else L(32);
+#undef L
+  return hipGetLastError();
+}
+
 // w -= sum_j V[j] h[j]   (h on device, J <= 1024)
 __global__ void k_multiaxpy(const double* __restrict__ V, int64_t ldv, int J, const double* __restrict__ h,
                             double* __restrict__ w, int64_t n, double sign) {

@@ -136,24 +136,27 @@ def test_residual_bitwise_deterministic():
     assert np.array_equal(to_host(a), to_host(b))
 
 
+@pytest.mark.parametrize("restart", [100, 20])
 @pytest.mark.parametrize("jac", ["picard", "newton"])
-def test_solve_cross_evaluated_by_oracle(jac):
+def test_solve_cross_evaluated_by_oracle(jac, restart):
     """Picard: one solve to 1e-9.  Newton: Picard to 1e-3, then the Newton
-    tangent (tau frozen) from there; both judged by the oracle residual."""
-    log(f"[gpu] solve cross-evaluation {jac}")
+    tangent (tau frozen) from there; both judged by the oracle residual.
+    restart 100 runs GMRES with two-pass classical Gram-Schmidt, restart 20
+    the delayed variant (one reduction per Arnoldi step)."""
+    log(f"[gpu] solve cross-evaluation {jac} restart={restart}")
     from workloads import initial_guess
     prob = womersley_problem(2, 8, K=2)
     s = _solver(prob)
     y0 = initial_guess(prob)
     y = to_dev(y0)
     if jac == "picard":
-        st = s.solve(y, rtol=1e-9, jacobian="picard", max_newton=60)
+        st = s.solve(y, rtol=1e-9, jacobian="picard", max_newton=60, restart=restart)
         assert st["status"] == 0, st
     else:
-        st1 = s.solve(y, rtol=1e-3, jacobian="picard", max_newton=60)
+        st1 = s.solve(y, rtol=1e-3, jacobian="picard", max_newton=60, restart=restart)
         assert st1["status"] == 0, st1
         target = 1e-9 / st1["rel_residual"]
-        st = s.solve(y, rtol=target, jacobian="newton", max_newton=30)
+        st = s.solve(y, rtol=target, jacobian="newton", max_newton=30, restart=restart)
         assert st["status"] == 0, st
     yg = to_host(y)
     par = O.Params.from_problem(prob)
