@@ -177,7 +177,7 @@ __device__ __forceinline__ double rsq_nr(double x) {
 // One round of the one-sided Jacobi: the columns of lanes c and c ^ k are
 // rotated to be orthogonal.  Both lanes of a pair evaluate the same rotation
 // bit for bit (same operands in the same order).  nrm is this lane's |w|^2,
-// kept up to date; big is set when (w_c . w_d)^2 > 1e-20 |w_c|^2 |w_d|^2.
+// kept up to date; big is set when (w_c . w_d)^2 > 1e-14 |w_c|^2 |w_d|^2.
 template <int n, int k>
 __device__ __forceinline__ void jacobi_round(double (&w)[n], double& nrm, int c, int& big,
                                              int& rot) {
@@ -193,7 +193,7 @@ __device__ __forceinline__ void jacobi_round(double (&w)[n], double& nrm, int c,
   const double al = low ? nrm : onrm, be = low ? onrm : nrm;
   const double ab = al * be;
   const double g2 = ga * ga;
-  if (g2 > 1e-20 * ab) big = 1;
+  if (g2 > 1e-14 * ab) big = 1;
   if (g2 > 1e-30 * ab) {
     // tan(theta) = 2 g sgn(d) / (|d| + sqrt(d^2 + 4 g^2)), d = be - al
     const double d = be - al;
@@ -225,8 +225,8 @@ __device__ __forceinline__ void jacobi_rounds(double (&w)[n], double& nrm, int c
 // lanes: lane c holds column c (n entries, zero for c >= n).  Pairs per
 // round are (c, c xor k), k = 1..NP-1, which covers every pair once per
 // sweep.  Sweeps stop after the first one whose largest rotation was below
-// 1e-10 in relative terms (convergence is quadratic, so the columns are then
-// orthogonal to working precision), or that rotated nothing.  The whole wave
+// 1e-7 in relative terms (convergence is quadratic: the columns are then
+// orthogonal to about 1e-14 relative), or that rotated nothing.  The whole wave
 // sweeps until all its groups are done.
 template <int n, int NP>
 __device__ __forceinline__ void jacobi_columns(double (&w)[n], int c) {
