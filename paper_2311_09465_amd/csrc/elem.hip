@@ -402,56 +402,59 @@ k_diag(DevView v, double* __restrict__ d, double shift, int64_t begin, int64_t e
     }
   }
   (void)node;
-  double* op = d + (e * 4 + b) * 4 * S;      // this element's node-b contributions
+  double* op = d + (e * 4 + b) * 4 * n;      // node b's rows [field][position]
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
-    double* o = op + f * S;
+    double* o = op + f * n;
     const double* src = f < 3 ? dm : dc;
-    o[0] = src[0];
-    o[1] = 0.0;
 #pragma unroll
-    for (int a = 1; a < n; ++a) o[a + 1] = src[a];
+    for (int a = 0; a < n; ++a) o[mode_pos(a, K)] = src[a];
   }
 }
 
 // Node-wise sum of element contributions (ascending element order): one
-// wave per node, lane j < 4S summing slot j of the node's incident element
-// rows; the incidence list is read with scalar loads.
+// wave per node, lane j < 4S producing slot j of the node's output from the
+// incident element rows [node][field][position] (slot 1, Im c_0, is zero);
+// the incidence list is read with scalar loads.
 template <int K>
 __global__ void __launch_bounds__(256)
 k_gather(const int32_t* __restrict__ noff, const int32_t* __restrict__ ninc,
          const uint8_t* __restrict__ nflag, const double* __restrict__ ebuf,
          double* __restrict__ out, int64_t nn) {
-  constexpr int S = Dim<K>::S, S4 = 4 * S;
+  constexpr int n = Dim<K>::n, S = Dim<K>::S, S4 = 4 * S, R = 4 * n;
   constexpr int NJ = (S4 + 63) / 64;
   const int64_t node = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (node >= nn) return;
   const int lane = threadIdx.x & 63;
   const int k0 = noff[node], k1 = noff[node + 1];
   const bool dir = (nflag[node] & 1) != 0;
+  int src[NJ];        // offset of slot j inside an element row, -1 for Im c_0
+#pragma unroll
+  for (int r = 0; r < NJ; ++r) {
+    const int j = lane + 64 * r, f = j / S, sl = j % S;
+    src[r] = (j >= S4 || sl == 1) ? -1 : f * n + (sl == 0 ? 2 * K : sl - 2);
+  }
   double acc[NJ];
 #pragma unroll
   for (int r = 0; r < NJ; ++r) acc[r] = 0.0;
   int k = k0;
   for (; k + 4 <= k1; k += 4) {
-    const int64_t i0 = (int64_t)ninc[k] * S4, i1 = (int64_t)ninc[k + 1] * S4;
-    const int64_t i2 = (int64_t)ninc[k + 2] * S4, i3 = (int64_t)ninc[k + 3] * S4;
+    const int64_t i0 = (int64_t)ninc[k] * R, i1 = (int64_t)ninc[k + 1] * R;
+    const int64_t i2 = (int64_t)ninc[k + 2] * R, i3 = (int64_t)ninc[k + 3] * R;
 #pragma unroll
     for (int r = 0; r < NJ; ++r) {
-      const int j = lane + 64 * r;
-      if (j < S4) {
-        const double a0 = ebuf[i0 + j], a1 = ebuf[i1 + j], a2 = ebuf[i2 + j], a3 = ebuf[i3 + j];
+      if (src[r] >= 0) {
+        const double a0 = ebuf[i0 + src[r]], a1 = ebuf[i1 + src[r]];
+        const double a2 = ebuf[i2 + src[r]], a3 = ebuf[i3 + src[r]];
         acc[r] = (((acc[r] + a0) + a1) + a2) + a3;
       }
     }
   }
   for (; k < k1; ++k) {
-    const int64_t i0 = (int64_t)ninc[k] * S4;
+    const int64_t i0 = (int64_t)ninc[k] * R;
 #pragma unroll
-    for (int r = 0; r < NJ; ++r) {
-      const int j = lane + 64 * r;
-      if (j < S4) acc[r] += ebuf[i0 + j];
-    }
+    for (int r = 0; r < NJ; ++r)
+      if (src[r] >= 0) acc[r] += ebuf[i0 + src[r]];
   }
 #pragma unroll
   for (int r = 0; r < NJ; ++r) {

@@ -20,7 +20,8 @@
 //   LS         lane (s, i): W_ji(t_s) = w sum_q u_{q,j} z_{q,i}
 //   to modes   MFMA: rows j*4+i  ->  lane (i=g, p), reg j
 //   assembly   lane (f=g, p), reg b: Galerkin, viscous, pressure, LS and
-//              PSPG terms; one store per node row to the element buffer.
+//              PSPG terms; element buffer rows [node][field][position] in
+//              the slot scaling (the node gather maps positions to slots).
 #include "common.cuh"
 #include "internal.h"
 
@@ -135,13 +136,11 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
     if (tok[j]) packed_rc<n>(pi, r, cc);
     tdst[j] = (r * n + cc) | ((cc * n + r) << 16);
   }
-  int oslot[NPT];        // output slot of position p (-1: none); slot 1 (Im c_0) gets 0
-  double oscale[NPT];
+  double oscale[NPT];    // orthonormal -> slot scale of position p
 #pragma unroll
   for (int pt = 0; pt < NPT; ++pt) {
     const int p = c + 16 * pt;
-    oslot[pt] = p < 2 * K ? p + 2 : (p == 2 * K ? 0 : (p == 2 * K + 1 ? 1 : -1));
-    oscale[pt] = p < 2 * K ? TS_RS2 : (p == 2 * K ? 1.0 : 0.0);
+    oscale[pt] = p < 2 * K ? TS_RS2 : 1.0;
   }
   constexpr double MD = TS_QA * TS_QA + 3.0 * TS_QB * TS_QB;      // sum_q lam_qb^2
   constexpr double MO = 2.0 * TS_QA * TS_QB + 2.0 * TS_QB * TS_QB;  // sum_q lam_qb lam_qc
@@ -462,7 +461,7 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
     }
 
     // ---- assembly: lane (field f = g, position p), node rows b
-    double* oe = out + e * (16 * S);
+    double* oe = out + e * (16 * n);
 #pragma unroll
     for (int pt = 0; pt < NPT; ++pt) {
       const int p = c + 16 * pt;
@@ -511,9 +510,9 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
         for (int b = 0; b < 4; ++b)
           o[b] = wgt * div + wr * (dN[b][0] * zs[0] + dN[b][1] * zs[1] + dN[b][2] * zs[2]);
       }
-      if (oslot[pt] >= 0) {
+      if (p < n) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) oe[(b * 4 + g) * S + oslot[pt]] = o[b] * oscale[pt];
+        for (int b = 0; b < 4; ++b) oe[(b * 4 + g) * n + p] = o[b] * oscale[pt];
       }
     }
     __syncthreads();   // LDS of this element fully consumed before the next one

@@ -25,7 +25,7 @@ struct tsgls_ctx {
   std::vector<int32_t> perm;    // processing position -> input element index (Morton order)
   int32_t* noff = nullptr;      // [n_nodes+1] CSR offsets: node -> incident element slots
   int32_t* ninc = nullptr;      // [4E] incident (element*4 + local node), ascending element
-  double* ebuf = nullptr;       // [E][4][4][2K+2] per-element contributions
+  double* ebuf = nullptr;       // [E][4][4][2K+1] per-element contributions over positions
   std::vector<double> hxyz;     // host copy of the coordinates (face geometry)
   int32_t* conn = nullptr;
   double* geo = nullptr;
@@ -664,7 +664,7 @@ int tsgls_create(const double* xyz, int64_t n_nodes, const int32_t* tets, int64_
   CHK(dalloc(c, &c->Z, (size_t)n_tets * 12 * c->n));
   CHK(dalloc(c, &c->noff, n_nodes + 1));
   CHK(dalloc(c, &c->ninc, n_tets * 4));
-  CHK(dalloc(c, &c->ebuf, (size_t)n_tets * 16 * c->S));
+  CHK(dalloc(c, &c->ebuf, (size_t)n_tets * 16 * c->n));
   CHK(dalloc(c, &c->rs, n_nodes * 4 * c->S));
   HIPCHK(c, hipMemcpyAsync(dxyz, xyz, n_nodes * 3 * sizeof(double), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->conn, sconn.data(), n_tets * 4 * sizeof(int32_t), hipMemcpyHostToDevice, c->st));

@@ -63,7 +63,8 @@ struct DevView {
 
 // Launchers (return hipError_t of the launch).  Element ranges [begin, end)
 // are in processing (Morton) order; element kernels write per-element
-// contributions [E][4 nodes][4 fields][S] that launch_gather sums per node.
+// contributions [E][4 nodes][4 fields][n positions] (slot scaling) that
+// launch_gather sums per node into slots.
 hipError_t launch_geometry(const double* xyz, const int32_t* conn, double* geo,
                            int* bad, int64_t n_tets, hipStream_t st);
 // XT[node][3][M]: time samples of the three velocity components;
@@ -78,14 +79,15 @@ hipError_t launch_tau(const DevView& v, const double* Y, double* tau,
                       hipStream_t st);
 // Element operator over elements [begin, end) (processing order); input
 // modes from XP, direction samples VT (tangent modes), writes the per-element
-// contributions out[E][4][4][S].  Zout (mode & MODE_STOREZ) receives tau L(u).
+// contributions out[E][4][4][n] over positions.  Zout (mode & MODE_STOREZ)
+// receives tau L(u).
 hipError_t launch_elem(const DevView& v, int mode, const double* XP,
                        const double* VT, double* Zout, double* out,
                        double shift, int64_t begin, int64_t end, hipStream_t st);
 hipError_t launch_diag(const DevView& v, double* d, double shift,
                        int64_t begin, int64_t end, hipStream_t st);
-// out[node][4][S] = sum over incident (element, local node) of ebuf, in
-// ascending element order (deterministic).
+// out[node][4][S] = sum over incident (element, local node) of the ebuf rows
+// mapped from positions to slots, in ascending element order (deterministic).
 // Velocity rows of Dirichlet nodes (nflag bit 0) are written as zero.
 hipError_t launch_gather(int K, const int32_t* noff, const int32_t* ninc,
                          const uint8_t* nflag, const double* ebuf, double* out,
