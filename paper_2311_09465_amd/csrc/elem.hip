@@ -65,12 +65,13 @@ hipError_t launch_geometry(const double* xyz, const int32_t* conn, double* geo, 
 // One wave per node (a block of four waves loops over nodes).  Lane
 // (field f, position p) writes XP[node][f][p] = mode pos_mode(p) of field f
 // in the orthonormal basis; then lane (j, s) forms XT[node][j][s] = u_j(t_s)
-// from the modes staged in LDS.  masked != 0 zeroes Dirichlet velocity rows.
+// from the modes staged in LDS.  masked != 0 zeroes Dirichlet velocity rows;
+// Ys, when given, scales the input entrywise (input = Y * Ys).
 template <int K>
 __global__ void __launch_bounds__(256)
-k_prep_time(const double* __restrict__ Y, const uint8_t* __restrict__ nflag, int masked,
-            const double* __restrict__ F, double* __restrict__ XT, double* __restrict__ XP,
-            int64_t nn) {
+k_prep_time(const double* __restrict__ Y, const double* __restrict__ Ys,
+            const uint8_t* __restrict__ nflag, int masked, const double* __restrict__ F,
+            double* __restrict__ XT, double* __restrict__ XP, int64_t nn) {
   constexpr int n = Dim<K>::n, S = Dim<K>::S, M = Dim<K>::M, PW = (n + 15) / 16 * 16;
   constexpr int NPT = PW / 16, NR = (3 * M + 63) / 64;
   constexpr bool HOIST = NR == 1;          // the lane's column of F stays in registers
@@ -99,7 +100,10 @@ k_prep_time(const double* __restrict__ Y, const uint8_t* __restrict__ nflag, int
       const int fp = pt * 64 + lane, f = fp / PW, pp = fp % PW;
       const int a = pos_mode(pp, K);
       double x = 0.0;
-      if (act && a >= 0 && !(zero && f < 3)) x = slot_x(Y + (node * 4 + f) * S, a);
+      if (act && a >= 0 && !(zero && f < 3)) {
+        const int64_t o = (node * 4 + f) * S + (a == 0 ? 0 : a + 1);
+        x = (a == 0 ? 1.0 : TS_SQ2) * (Ys ? Y[o] * Ys[o] : Y[o]);
+      }
       if (act) XP[node * (4 * PW) + fp] = x;
       sx[wv][fp] = x;
     }
@@ -494,14 +498,15 @@ int supported_K_list(int* out, int cap) {
   return cnt;
 }
 
-hipError_t launch_prep_time(int K, const double* Y, const uint8_t* nflag, int masked,
-                            const double* F, double* XT, double* XP, int64_t nn, hipStream_t st) {
+hipError_t launch_prep_time(int K, const double* Y, const double* Ys, const uint8_t* nflag,
+                            int masked, const double* F, double* XT, double* XP, int64_t nn,
+                            hipStream_t st) {
   if (nn == 0) return hipSuccess;
   int64_t nb = (nn + 3) / 4;
   if (nb > 8192) nb = 8192;
   const unsigned grid = (unsigned)nb;
   switch (K) {
-#define CASE(k) case k: k_prep_time<k><<<grid, 256, 0, st>>>(Y, nflag, masked, F, XT, XP, nn); break;
+#define CASE(k) case k: k_prep_time<k><<<grid, 256, 0, st>>>(Y, Ys, nflag, masked, F, XT, XP, nn); break;
     TSGLS_FOR_EACH_K(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;

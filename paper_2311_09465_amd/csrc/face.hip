@@ -98,7 +98,8 @@ k_face_lin(DevView v, const double* __restrict__ UTs, double* __restrict__ aneg)
 // points in a fixed order (deterministic) and adds it to the output.
 template <int K>
 __global__ void __launch_bounds__(128)
-k_face_point(DevView v, const double* __restrict__ Y, int resid, const double* __restrict__ an) {
+k_face_point(DevView v, const double* __restrict__ Y, const double* __restrict__ Ys, int resid,
+             const double* __restrict__ an) {
   constexpr int n = Dim<K>::n, S = Dim<K>::S, P = Dim<K>::P;
   __shared__ double su[3 * n];
   const int64_t fq = blockIdx.x;           // face * 3 + point
@@ -112,7 +113,9 @@ k_face_point(DevView v, const double* __restrict__ Y, int resid, const double* _
     for (int b = 0; b < 3; ++b) {
       const int64_t nb = v.fconn[f * 3 + b];
       const bool z = !resid && (v.nflag[nb] & 1);
-      acc += z ? 0.0 : flam(q, b) * slot_x(Y + (nb * 4 + i) * S, m);
+      const int64_t o = (nb * 4 + i) * S + (m == 0 ? 0 : m + 1);
+      const double x = (m == 0 ? 1.0 : TS_SQ2) * (Ys ? Y[o] * Ys[o] : Y[o]);
+      acc += z ? 0.0 : flam(q, b) * x;
     }
     su[i * n + m] = acc;
   }
@@ -205,13 +208,13 @@ hipError_t launch_face_lin(const DevView& v, const double* UTs, double* aneg, hi
   return hipGetLastError();
 }
 
-hipError_t launch_face_apply(const DevView& v, const double* Y, int resid, const double* an,
-                             double* out, hipStream_t st) {
+hipError_t launch_face_apply(const DevView& v, const double* Y, const double* Ys, int resid,
+                             const double* an, double* out, hipStream_t st) {
   if (v.n_fnodes == 0 || v.n_faces == 0) return hipSuccess;
   switch (v.K) {
 #define CASE(k)                                                                             \
   case k: {                                                                                 \
-    k_face_point<k><<<(unsigned)(v.n_faces * 3), (3 * Dim<k>::n + 63) / 64 * 64, 0, st>>>(v, Y, resid, an); \
+    k_face_point<k><<<(unsigned)(v.n_faces * 3), (3 * Dim<k>::n + 63) / 64 * 64, 0, st>>>(v, Y, Ys, resid, an); \
     const int64_t tot = v.n_fnodes * 3 * Dim<k>::n;                                         \
     k_face_apply<k><<<(unsigned)((tot + 127) / 128), 128, 0, st>>>(v, resid, out);          \
     break;                                                                                  \

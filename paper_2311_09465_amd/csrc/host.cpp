@@ -199,7 +199,8 @@ struct ProfScope {
 // modes must already be in c->XP (launch_prep_time); Y is the input vector
 // itself (face terms).
 int apply_operator(tsgls_ctx* c, const DevView& v, int mode, const double* Y, const double* VTp,
-                   double* Zout, double* out, double shift, const double* an, int resid) {
+                   double* Zout, double* out, double shift, const double* an, int resid,
+                   const double* Ys = nullptr) {
   const int which = (mode & MODE_RESID) ? TSGLS_PROF_ELEM_RESIDUAL : TSGLS_PROF_ELEM_TANGENT;
   {
     ProfScope ps(c, which);
@@ -211,14 +212,14 @@ int apply_operator(tsgls_ctx* c, const DevView& v, int mode, const double* Y, co
   }
   if (c->nf) {
     ProfScope ps(c, TSGLS_PROF_FACE);
-    HIPCHK(c, launch_face_apply(v, Y, resid, an, out, c->st));
+    HIPCHK(c, launch_face_apply(v, Y, Ys, resid, an, out, c->st));
   }
   return TSGLS_OK;
 }
 
 int linearize_impl(tsgls_ctx* c, const double* y, double* r) {
   DevView v = view(c);
-  HIPCHK(c, launch_prep_time(c->K, y, c->nflag, 0, c->F, c->UT, c->XP, c->nn, c->st));
+  HIPCHK(c, launch_prep_time(c->K, y, nullptr, c->nflag, 0, c->F, c->UT, c->XP, c->nn, c->st));
   {
     ProfScope ps(c, TSGLS_PROF_TAU);
     HIPCHK(c, launch_tau(v, y, c->tau, c->st));
@@ -230,13 +231,15 @@ int linearize_impl(tsgls_ctx* c, const double* y, double* r) {
   return TSGLS_OK;
 }
 
-int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt) {
+// out = J (x * xs) (xs: optional entrywise scale of the input, e.g. the
+// right preconditioner inside GMRES).
+int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt, const double* xs = nullptr) {
   if (!c->linearized) return fail(c, TSGLS_ESTATE, "jv before linearize");
   DevView v = view(c);
   const int mode = jac == TSGLS_JAC_PICARD ? 0 : jac == TSGLS_JAC_PICARD_NOLS ? MODE_NOLS : MODE_NEWTON;
   const double shift = dt > 0 ? 1.5 * c->p.rho / dt : 0.0;
-  HIPCHK(c, launch_prep_time(c->K, x, c->nflag, 1, c->F, c->VT, c->XP, c->nn, c->st));
-  return apply_operator(c, v, mode, x, c->VT, nullptr, out, shift, c->aneg, 0);
+  HIPCHK(c, launch_prep_time(c->K, x, xs, c->nflag, 1, c->F, c->VT, c->XP, c->nn, c->st));
+  return apply_operator(c, v, mode, x, c->VT, nullptr, out, shift, c->aneg, 0, xs);
 }
 
 int diag_impl(tsgls_ctx* c, double* d, double dt) {
@@ -372,8 +375,7 @@ int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, i
     for (int j = 0; j < m && mv < maxmv; ++j) {
       double* u = c->V + (int64_t)j * n;
       double* w = c->V + (int64_t)(j + 1) * n;
-      HIPCHK(c, launch_mul(c->minv, u, c->kt, n, c->st));
-      CHK(jv_impl(c, c->kt, w, jac, dt));
+      CHK(jv_impl(c, u, w, jac, dt, c->minv));
       ++mv;
       CHK(reduce(j, u, w));
       const double* a = red.data();
@@ -803,7 +805,7 @@ int tsgls_residual(tsgls_ctx* c, const double* y, double* r) {
   v.UT = c->UTr;
   v.tau = c->taur;
   v.aneg = c->anegr;
-  HIPCHK(c, launch_prep_time(c->K, y, c->nflag, 0, c->F, c->UTr, c->XP, c->nn, c->st));
+  HIPCHK(c, launch_prep_time(c->K, y, nullptr, c->nflag, 0, c->F, c->UTr, c->XP, c->nn, c->st));
   HIPCHK(c, launch_tau(v, y, c->taur, c->st));
   HIPCHK(c, launch_face_lin(v, c->UTr, c->anegr, c->st));
   return apply_operator(c, v, MODE_RESID, y, nullptr, nullptr, r, 0.0, c->anegr, 1);

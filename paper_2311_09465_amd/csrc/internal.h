@@ -69,10 +69,11 @@ hipError_t launch_geometry(const double* xyz, const int32_t* conn, double* geo,
                            int* bad, int64_t n_tets, hipStream_t st);
 // XT[node][3][M]: time samples of the three velocity components;
 // XP[node][4][PW]: the four fields' modes in the orthonormal basis at their
-// positions (zero padding).  masked != 0 zeroes Dirichlet velocity rows.
-hipError_t launch_prep_time(int K, const double* Y, const uint8_t* nflag,
-                            int masked, const double* F, double* XT,
-                            double* XP, int64_t n_nodes, hipStream_t st);
+// positions (zero padding).  masked != 0 zeroes Dirichlet velocity rows.  The
+// input is Y, or Y * Ys entrywise when Ys is not null.
+hipError_t launch_prep_time(int K, const double* Y, const double* Ys,
+                            const uint8_t* nflag, int masked, const double* F,
+                            double* XT, double* XP, int64_t n_nodes, hipStream_t st);
 // Positions per field row of XP (16 or 32).
 int pos_width(int K);
 hipError_t launch_tau(const DevView& v, const double* Y, double* tau,
@@ -94,7 +95,7 @@ hipError_t launch_gather(int K, const int32_t* noff, const int32_t* ninc,
                          int64_t n_nodes, hipStream_t st);
 hipError_t launch_face_lin(const DevView& v, const double* Y, double* aneg,
                            hipStream_t st);
-hipError_t launch_face_apply(const DevView& v, const double* Y, int resid,
+hipError_t launch_face_apply(const DevView& v, const double* Y, const double* Ys, int resid,
                              const double* aneg, double* out, hipStream_t st);
 hipError_t launch_face_diag(const DevView& v, double* d, hipStream_t st);
 hipError_t launch_diag_finish(int K, const uint8_t* nflag, double* d,
