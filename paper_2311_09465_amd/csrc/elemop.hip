@@ -88,7 +88,7 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
   __shared__ double sWq[NEWTON ? 12 * RM : 1];    // direction at the points [q][j][s]
 
   const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
-  const double rho = v.rho, mu = v.mu, omega = v.omega;
+  const double rho = v.rho, mu = v.mu, omega = v.omega, irho = 1.0 / v.rho;
   const double* __restrict__ F = v.F;
   const double* __restrict__ UT = v.UT;
 
@@ -479,19 +479,23 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
         const double Gs = Gq[0] + Gq[1] + Gq[2] + Gq[3];
         const double ps = Vp[0] + Vp[1] + Vp[2] + Vp[3];
         const double Vs = Vf[0] + Vf[1] + Vf[2] + Vf[3];
-        double gV[3];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) gV[j] = dN[0][j] * Vf[0] + dN[1][j] * Vf[1] + dN[2][j] * Vf[2] + dN[3][j] * Vf[3];
+        // sum_j dN_bj (W_ji + 4 w mu grad_j du_i): least-squares and viscous terms together
         const double kv = 4.0 * wgt * mu, ks = shift * wgt;
+        double t[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          t[j] = fma(kv, dN[0][j] * Vf[0] + dN[1][j] * Vf[1] + dN[2][j] * Vf[2] + dN[3][j] * Vf[3], wm[pt][j]);
+        const double wq = wgt * (TS_QA - TS_QB), km = ks * (MD - MO), wps = -wgt * ps;
+        const double base = fma(wgt * TS_QB, Gs, ks * MO * Vs);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           const double dNi = i == 0 ? dN[b][0] : (i == 1 ? dN[b][1] : dN[b][2]);
-          double acc = wgt * (TS_QB * Gs + (TS_QA - TS_QB) * Gq[b]);
-          acc += dN[b][0] * wm[pt][0] + dN[b][1] * wm[pt][1] + dN[b][2] * wm[pt][2];
-          acc -= dNi * wgt * ps;
-          acc += kv * (dN[b][0] * gV[0] + dN[b][1] * gV[1] + dN[b][2] * gV[2]);
-          acc += ks * (MO * Vs + (MD - MO) * Vf[b]);
-          o[b] = acc;
+          double acc = fma(wq, Gq[b], base);       // sum_q w lam_qb G_qi
+          acc = fma(km, Vf[b], acc);               // mass shift
+          acc = fma(wps, dNi, acc);                // - (d_i N_b, p)
+          acc = fma(dN[b][0], t[0], acc);
+          acc = fma(dN[b][1], t[1], acc);
+          o[b] = fma(dN[b][2], t[2], acc);
         }
       } else {
         double div = 0.0;
@@ -505,10 +509,10 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
           const double* zr = sZ + (NOLS ? 16 * RP : 0) + i * RP + p;
           zs[i] = zr[0] + zr[4 * RP] + zr[8 * RP] + zr[12 * RP];
         }
-        const double wr = wgt / rho;
+        const double wr = wgt * irho, wd = wgt * div;
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-          o[b] = wgt * div + wr * (dN[b][0] * zs[0] + dN[b][1] * zs[1] + dN[b][2] * zs[2]);
+          o[b] = fma(wr, dN[b][0] * zs[0] + dN[b][1] * zs[1] + dN[b][2] * zs[2], wd);
       }
       if (p < n) {
 #pragma unroll
