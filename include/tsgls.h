@@ -73,6 +73,17 @@ extern "C" {
 #define TSGLS_JAC_PICARD_NOLS 1  /* eq. K_mat with least-squares terms of G_i, D_i dropped */
 #define TSGLS_JAC_NEWTON 2       /* A_i(u) differentiated, tau and |A_n|_- frozen */
 
+/* Arithmetic of the tangent product (jv, solve).  The residual, the
+ * linearization (tau from the eigendecomposition of eq. 3D-tau), the Jacobi
+ * diagonal, the Newton update and the Krylov orthogonalization are FP64 in
+ * both; with TSGLS_PREC_F32 the element operator of the tangent runs in FP32
+ * (FP32 MFMA transforms, FP32 copies of tau, of the frozen velocity samples
+ * and of tau L(u)) and its element rows are summed per node in FP64, so the
+ * FP64 residual of each Newton step corrects the rounding of the linear
+ * solves (iterative refinement).  Face terms stay FP64. */
+#define TSGLS_PREC_F64 0
+#define TSGLS_PREC_F32 1
+
 typedef struct tsgls_ctx tsgls_ctx;
 
 typedef struct {
@@ -93,6 +104,7 @@ typedef struct {
   int jacobian;      /* TSGLS_JAC_* */
   double dt_pseudo;  /* pseudo-time step; <= 0 disables the mass shift */
   int verbose;       /* 1: one line per Newton step on stderr */
+  int tangent_precision;  /* TSGLS_PREC_F64 (0, default) or TSGLS_PREC_F32 */
 } tsgls_solve_opts;
 
 typedef struct {
@@ -141,6 +153,15 @@ int tsgls_linearize(tsgls_ctx* ctx, const double* y, double* r);
  * adds the pseudo-time mass shift.  v and Jv must not alias. */
 int tsgls_jv(tsgls_ctx* ctx, const double* v, double* Jv, int jacobian,
              double dt_pseudo);
+
+/* tsgls_jv with the tangent's arithmetic chosen by precision (TSGLS_PREC_*);
+ * TSGLS_PREC_F32 needs device memory for FP32 copies of the linearization
+ * (4 P E + 12 n E + 3 M n_nodes floats), allocated on the first such call
+ * (TSGLS_ENOMEM if that fails) and refreshed once after each linearize.  The
+ * result is within FP32 rounding of the FP64 product (relative error of
+ * order 1e-6 of the largest entry). */
+int tsgls_jv_prec(tsgls_ctx* ctx, const double* v, double* Jv, int jacobian,
+                  double dt_pseudo, int precision);
 
 /* d = diagonal of the Picard tangent (with the mass shift if dt_pseudo > 0),
  * 1 on masked slots. */

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libtsgls.so")
 TSGLS_OK = 0
 TSGLS_NOT_CONVERGED = 1
 JAC = {"picard": 0, "picard_nols": 1, "newton": 2}
+PREC = {"f64": 0, "f32": 1}
 ERRORS = {-1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "EMESH", -5: "ENONFINITE", -6: "ESTATE"}
 
 
@@ -29,7 +30,7 @@ class Params(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("lin_rtol", C.c_double), ("restart", C.c_int),
                 ("max_newton", C.c_int), ("max_matvec", C.c_int), ("jacobian", C.c_int),
-                ("dt_pseudo", C.c_double), ("verbose", C.c_int)]
+                ("dt_pseudo", C.c_double), ("verbose", C.c_int), ("tangent_precision", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -61,6 +62,7 @@ def lib():
         L.tsgls_residual.argtypes = [P, P, P]
         L.tsgls_linearize.argtypes = [P, P, P]
         L.tsgls_jv.argtypes = [P, P, P, I32, D]
+        L.tsgls_jv_prec.argtypes = [P, P, P, I32, D, I32]
         L.tsgls_jacobi_diag.argtypes = [P, P, D]
         L.tsgls_get_tau.argtypes = [P, P]
         L.tsgls_solve.argtypes = [P, P, C.POINTER(SolveOpts), C.POINTER(SolveStats)]
@@ -154,9 +156,14 @@ class Solver:
         rp = self._vec(r, "r") if r is not None else None
         self._check(lib().tsgls_linearize(self._h, self._vec(y, "y"), rp), "linearize")
 
-    def jv(self, v, out, jacobian="picard", dt_pseudo=0.0):
-        self._check(lib().tsgls_jv(self._h, self._vec(v, "v"), self._vec(out, "Jv"),
-                                   JAC[jacobian], float(dt_pseudo or 0.0)), "jv")
+    def jv(self, v, out, jacobian="picard", dt_pseudo=0.0, precision=None):
+        if precision is None:
+            self._check(lib().tsgls_jv(self._h, self._vec(v, "v"), self._vec(out, "Jv"),
+                                       JAC[jacobian], float(dt_pseudo or 0.0)), "jv")
+        else:
+            self._check(lib().tsgls_jv_prec(self._h, self._vec(v, "v"), self._vec(out, "Jv"),
+                                            JAC[jacobian], float(dt_pseudo or 0.0), PREC[precision]),
+                        "jv_prec")
 
     def jacobi_diag(self, d, dt_pseudo=0.0):
         self._check(lib().tsgls_jacobi_diag(self._h, self._vec(d, "d"), float(dt_pseudo or 0.0)),
@@ -169,9 +176,9 @@ class Solver:
         return out
 
     def solve(self, y, rtol=1e-8, lin_rtol=0.05, restart=100, max_newton=50, max_matvec=10000,
-              jacobian="picard", dt_pseudo=0.0, verbose=False):
+              jacobian="picard", dt_pseudo=0.0, verbose=False, tangent_precision="f64"):
         o = SolveOpts(rtol, lin_rtol, restart, max_newton, max_matvec, JAC[jacobian],
-                      float(dt_pseudo or 0.0), int(verbose))
+                      float(dt_pseudo or 0.0), int(verbose), PREC[tangent_precision])
         st = SolveStats()
         rc = self._check(lib().tsgls_solve(self._h, self._vec(y, "y"), C.byref(o), C.byref(st)), "solve")
         return dict(status=rc, newton_iters=st.newton_iters, matvecs=st.matvecs,

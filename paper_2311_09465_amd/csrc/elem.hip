@@ -67,11 +67,11 @@ hipError_t launch_geometry(const double* xyz, const int32_t* conn, double* geo, 
 // in the orthonormal basis; then lane (j, s) forms XT[node][j][s] = u_j(t_s)
 // from the modes staged in LDS.  masked != 0 zeroes Dirichlet velocity rows;
 // Ys, when given, scales the input entrywise (input = Y * Ys).
-template <int K>
+template <int K, typename TO>
 __global__ void __launch_bounds__(256)
 k_prep_time(const double* __restrict__ Y, const double* __restrict__ Ys,
             const uint8_t* __restrict__ nflag, int masked, const double* __restrict__ F,
-            double* __restrict__ XT, double* __restrict__ XP, int64_t nn) {
+            TO* __restrict__ XT, TO* __restrict__ XP, int64_t nn) {
   constexpr int n = Dim<K>::n, S = Dim<K>::S, M = Dim<K>::M, PW = (n + 15) / 16 * 16;
   constexpr int NPT = PW / 16, NR = (3 * M + 63) / 64;
   constexpr bool HOIST = NR == 1;          // the lane's column of F stays in registers
@@ -104,7 +104,7 @@ k_prep_time(const double* __restrict__ Y, const double* __restrict__ Ys,
         const int64_t o = (node * 4 + f) * S + (a == 0 ? 0 : a + 1);
         x = (a == 0 ? 1.0 : TS_SQ2) * (Ys ? Y[o] * Ys[o] : Y[o]);
       }
-      if (act) XP[node * (4 * PW) + fp] = x;
+      if (act) XP[node * (4 * PW) + fp] = TO(x);
       sx[wv][fp] = x;
     }
     __syncthreads();
@@ -116,7 +116,7 @@ k_prep_time(const double* __restrict__ Y, const double* __restrict__ Ys,
 #pragma unroll
         for (int a = 0; a < n; ++a)
           acc = fma(xr[mode_pos(a, K)], HOIST ? Fl[HOIST ? a : 0] : F[a * M + ss[r]], acc);
-        XT[(node * 3 + sj[r]) * M + ss[r]] = acc;
+        XT[(node * 3 + sj[r]) * M + ss[r]] = TO(acc);
       }
     }
     __syncthreads();
@@ -420,10 +420,10 @@ k_diag(DevView v, double* __restrict__ d, double shift, int64_t begin, int64_t e
 // wave per node, lane j < 4S producing slot j of the node's output from the
 // incident element rows [node][field][position] (slot 1, Im c_0, is zero);
 // the incidence list is read with scalar loads.
-template <int K>
+template <int K, typename TE>
 __global__ void __launch_bounds__(256)
 k_gather(const int32_t* __restrict__ noff, const int32_t* __restrict__ ninc,
-         const uint8_t* __restrict__ nflag, const double* __restrict__ ebuf,
+         const uint8_t* __restrict__ nflag, const TE* __restrict__ ebuf,
          double* __restrict__ out, int64_t nn) {
   constexpr int n = Dim<K>::n, S = Dim<K>::S, S4 = 4 * S, R = 4 * n;
   constexpr int NJ = (S4 + 63) / 64;
@@ -449,7 +449,7 @@ k_gather(const int32_t* __restrict__ noff, const int32_t* __restrict__ ninc,
     for (int r = 0; r < NJ; ++r) {
       if (src[r] >= 0) {
         const double a0 = ebuf[i0 + src[r]], a1 = ebuf[i1 + src[r]];
-        const double a2 = ebuf[i2 + src[r]], a3 = ebuf[i3 + src[r]];
+        const double a2 = ebuf[i2 + src[r]], a3 = ebuf[i3 + src[r]];   // FP64 sum
         acc[r] = (((acc[r] + a0) + a1) + a2) + a3;
       }
     }
@@ -506,7 +506,23 @@ hipError_t launch_prep_time(int K, const double* Y, const double* Ys, const uint
   if (nb > 8192) nb = 8192;
   const unsigned grid = (unsigned)nb;
   switch (K) {
-#define CASE(k) case k: k_prep_time<k><<<grid, 256, 0, st>>>(Y, Ys, nflag, masked, F, XT, XP, nn); break;
+#define CASE(k) case k: k_prep_time<k, double><<<grid, 256, 0, st>>>(Y, Ys, nflag, masked, F, XT, XP, nn); break;
+    TSGLS_FOR_EACH_K(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_time_f32(int K, const double* Y, const double* Ys, const uint8_t* nflag,
+                                int masked, const double* F, float* XT, float* XP, int64_t nn,
+                                hipStream_t st) {
+  if (nn == 0) return hipSuccess;
+  int64_t nb = (nn + 3) / 4;
+  if (nb > 8192) nb = 8192;
+  const unsigned grid = (unsigned)nb;
+  switch (K) {
+#define CASE(k) case k: k_prep_time<k, float><<<grid, 256, 0, st>>>(Y, Ys, nflag, masked, F, XT, XP, nn); break;
     TSGLS_FOR_EACH_K(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -550,7 +566,21 @@ hipError_t launch_gather(int K, const int32_t* noff, const int32_t* ninc, const 
   if (tot == 0) return hipSuccess;
   const unsigned grid = (unsigned)((nn + 3) / 4);
   switch (K) {
-#define CASE(k) case k: k_gather<k><<<grid, 256, 0, st>>>(noff, ninc, nflag, ebuf, out, nn); break;
+#define CASE(k) case k: k_gather<k, double><<<grid, 256, 0, st>>>(noff, ninc, nflag, ebuf, out, nn); break;
+    TSGLS_FOR_EACH_K(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_f32(int K, const int32_t* noff, const int32_t* ninc, const uint8_t* nflag,
+                             const float* ebuf, double* out, int64_t nn, hipStream_t st) {
+  const int64_t tot = nn * 4 * (2 * K + 2);
+  if (tot == 0) return hipSuccess;
+  const unsigned grid = (unsigned)((nn + 3) / 4);
+  switch (K) {
+#define CASE(k) case k: k_gather<k, float><<<grid, 256, 0, st>>>(noff, ninc, nflag, ebuf, out, nn); break;
     TSGLS_FOR_EACH_K(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;

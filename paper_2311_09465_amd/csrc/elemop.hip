@@ -27,7 +27,32 @@
 
 namespace tsgls {
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
+// Arithmetic type of the element operator: FP64 for the residual and the
+// tangent, FP32 for the mixed-precision tangent.  Both use the 16x16x4 MFMA
+// with the same A/B fragments (lane l: A[l%16][l/16], B[l/16][l%16]); the
+// result fragments differ: lane group g, register r hold result row
+// g + 4r (FP64) or 4g + r (FP32).
+template <typename T>
+struct Mma;
+template <>
+struct Mma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 run(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __host__ __device__ constexpr int row(int g, int r) { return g + 4 * r; }
+};
+template <>
+struct Mma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 run(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __host__ __device__ constexpr int row(int g, int r) { return 4 * g + r; }
+};
+
+__device__ __forceinline__ double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float tfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 template <int K>
 struct OpCfg {
@@ -54,17 +79,36 @@ __device__ __forceinline__ double swap_pair(double x) {
   const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0xB1, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ float swap_pair(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
 
 // Waves per SIMD the register allocation must allow: the Picard tangent
-// (the launch repeated inside GMRES) fits three without spilling.
-template <int MODE>
-constexpr int op_waves() { return MODE == 0 ? 3 : 1; }
+// (the launch repeated inside GMRES) fits three without spilling in FP64,
+// four in FP32.
+template <int MODE, typename T>
+constexpr int op_waves() { return MODE == 0 ? (sizeof(T) == 4 ? 4 : 3) : 1; }
 
-template <int K, int MODE>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(op_waves<MODE>())))
-k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
-     double* __restrict__ Zout, double* __restrict__ out, double shift, int64_t begin,
-     int64_t end) {
+// Frozen fields of the linearization in the kernel's arithmetic type.
+template <typename T>
+struct Frozen {
+  const T* UT;    // [n_nodes][3][M] velocity samples
+  const T* tau;   // [E][4][P] packed tau
+  const T* Z;     // [E][4][3][n] tau L(u) (Newton tangent)
+};
+template <typename T>
+__device__ __forceinline__ Frozen<T> frozen(const DevView& v) {
+  if constexpr (sizeof(T) == 8) return Frozen<T>{v.UT, v.tau, v.Z};
+  else return Frozen<T>{v.UT32, v.tau32, v.Z32};
+}
+
+// XP: [n_nodes][4][PW] input modes at positions; VT: [n_nodes][3][M]
+// direction samples (tangent modes); out: [E][4][4][n] element rows; Zout
+// (MODE_STOREZ, FP64 only): tau L(u) [E][4][3][n].
+template <int K, int MODE, typename T>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(op_waves<MODE, T>())))
+k_op(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
+     double* __restrict__ Zout, T* __restrict__ out, T shift, int64_t begin, int64_t end) {
   using C = OpCfg<K>;
   constexpr int n = C::n, M = C::M, S = C::S, P = C::P, PW = C::PW, NPT = C::NPT;
   constexpr int MS = C::MS, NKB = C::NKB, MT = C::MT, NKF = C::NKF, NPR = C::NPR, NTL = C::NTL;
@@ -75,26 +119,31 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
   constexpr bool STOREZ = (MODE & MODE_STOREZ) != 0;
   constexpr bool KEEPU = C::KEEPU;
   constexpr int NL = NOLS ? 2 : 1;
+  using R = Mma<T>;
+  typedef typename R::v4 T4;
+  const Frozen<T> fz = frozen<T>(v);
+  const T* __restrict__ UT = fz.UT;
+  const T* TAU = fz.tau;
+  const T QB = T(TS_QB), QAB = T(TS_QA - TS_QB);
 
   constexpr int NC = 16 * (RS > RM ? RS : RM);
-  __shared__ double sV[16 * RP];               // modes [node][field][position]
+  __shared__ T sV[16 * RP];               // modes [node][field][position]
   constexpr int NT = 4 * n * n > NL * 16 * RP ? 4 * n * n : NL * 16 * RP;
-  __shared__ double sT[NT];                    // tau_q rows [q][position][position], then z
-  __shared__ double sL[NL * 12 * RP];          // L [q][i][position] (+ grad p part), then G
-  __shared__ double sC[NC];                    // conv(t) [16][RS] / z(t) [16][RM] / W(t) [16][RS]
-  double* const sZ = sT;                       // z [q*4+i][position] (+ tau grad p)
-  __shared__ double sZf[NEWTON ? 16 * RP : 1];    // stored tau L(u) [q*4+i][position]
-  __shared__ double sZft[NEWTON ? 16 * RM : 1];   // its samples [i*4+q][s]
-  __shared__ double sWq[NEWTON ? 12 * RM : 1];    // direction at the points [q][j][s]
+  __shared__ T sT[NT];                    // tau_q rows [q][position][position], then z
+  __shared__ T sL[NL * 12 * RP];          // L [q][i][position] (+ grad p part), then G
+  __shared__ T sC[NC];                    // conv(t) [16][RS] / z(t) [16][RM] / W(t) [16][RS]
+  T* const sZ = sT;                       // z [q*4+i][position] (+ tau grad p)
+  __shared__ T sZf[NEWTON ? 16 * RP : 1];    // stored tau L(u) [q*4+i][position]
+  __shared__ T sZft[NEWTON ? 16 * RM : 1];   // its samples [i*4+q][s]
+  __shared__ T sWq[NEWTON ? 12 * RM : 1];    // direction at the points [q][j][s]
 
   const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
-  const double rho = v.rho, mu = v.mu, omega = v.omega, irho = 1.0 / v.rho;
+  const T rho = T(v.rho), mu = T(v.mu), omega = T(v.omega), irho = T(1.0 / v.rho);
   const double* __restrict__ F = v.F;
-  const double* __restrict__ UT = v.UT;
 
   // ---- per-lane constants (once per wave)
-  double Bb[NKB][NPT];   // B[k = s][col = position] = phi(t_s) / M
-  double Bf[NKF][MT];    // B[k = position][col = s] = phi(t_s)
+  T Bb[NKB][NPT];   // B[k = s][col = position] = phi(t_s) / M
+  T Bf[NKF][MT];    // B[k = position][col = s] = phi(t_s)
 #pragma unroll
   for (int ks = 0; ks < NKB; ++ks)
 #pragma unroll
@@ -118,12 +167,12 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
     sP[r] = okP[r] ? it % M : 0;
     iP[r] = okP[r] ? it / M : 0;
   }
-  double om[NPT];        // (Omega x)_p = om_p x_{p^1}
+  T om[NPT];        // (Omega x)_p = om_p x_{p^1}
   int trow[NPT];         // row of tau_q read by this lane (padding lanes read row 0)
 #pragma unroll
   for (int pt = 0; pt < NPT; ++pt) {
     const int p = c + 16 * pt;
-    om[pt] = p < 2 * K ? ((p & 1) ? ((p + 1) >> 1) * omega : -((p >> 1) + 1) * omega) : 0.0;
+    om[pt] = p < 2 * K ? ((p & 1) ? ((p + 1) >> 1) * omega : -((p >> 1) + 1) * omega) : T(0);
     trow[pt] = (g * n + (p < n ? p : 0)) * n;
   }
   int tdst[NTL];         // unpacking of packed tau: (r*n + c) | (c*n + r) << 16
@@ -136,19 +185,21 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
     if (tok[j]) packed_rc<n>(pi, r, cc);
     tdst[j] = (r * n + cc) | ((cc * n + r) << 16);
   }
-  double oscale[NPT];    // orthonormal -> slot scale of position p
+  T oscale[NPT];    // orthonormal -> slot scale of position p
 #pragma unroll
   for (int pt = 0; pt < NPT; ++pt) {
     const int p = c + 16 * pt;
-    oscale[pt] = p < 2 * K ? TS_RS2 : 1.0;
+    oscale[pt] = p < 2 * K ? T(TS_RS2) : T(1);
   }
-  constexpr double MD = TS_QA * TS_QA + 3.0 * TS_QB * TS_QB;      // sum_q lam_qb^2
-  constexpr double MO = 2.0 * TS_QA * TS_QB + 2.0 * TS_QB * TS_QB;  // sum_q lam_qb lam_qc
+  constexpr T MD = TS_QA * TS_QA + 3.0 * TS_QB * TS_QB;      // sum_q lam_qb^2
+  constexpr T MO = 2.0 * TS_QA * TS_QB + 2.0 * TS_QB * TS_QB;  // sum_q lam_qb lam_qc
 
-  // padding that enters the MFMA k dimension must be finite (z shares the
-  // tau-row buffer, whose contents are always finite once the first element
-  // has been staged)
+  // LDS words that enter an MFMA as padding (k beyond the data, or rows
+  // whose results are discarded) multiply zeros of B, so they must be finite
+  // (0 * NaN = NaN).  LDS is undefined at launch: the buffers read as MFMA
+  // operands are cleared once, and only finite values are stored afterwards.
   for (int i = lane; i < NC; i += 64) sC[i] = 0.0;
+  for (int i = lane; i < NT; i += 64) sT[i] = 0.0;
   if (NEWTON)
     for (int i = lane; i < 16 * RP; i += 64) sZf[i] = 0.0;
   __syncthreads();
@@ -160,71 +211,71 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
 
   // packed tau of the next element is loaded one element ahead (it streams
   // from HBM with no reuse, so its latency is hidden behind the current one)
-  double tv[4][NTL];
+  T tv[4][NTL];
   if (lo + jx < hi) {
     const int64_t e0 = lo + jx;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int j = 0; j < NTL; ++j) tv[q][j] = tok[j] ? v.tau[(e0 * 4 + q) * P + lane + 64 * j] : 0.0;
+      for (int j = 0; j < NTL; ++j) tv[q][j] = tok[j] ? TAU[(e0 * 4 + q) * P + lane + 64 * j] : T(0);
   }
 
   for (int64_t e = lo + jx; e < hi; e += nbx) {
     int nd[4];
-    double dN[4][3];
+    T dN[4][3];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       nd[b] = v.conn[e * 4 + b];
 #pragma unroll
       for (int j = 0; j < 3; ++j) dN[b][j] = v.geo[e * 16 + b * 3 + j];
     }
-    const double wgt = v.geo[e * 16 + 12];
+    const T wgt = v.geo[e * 16 + 12];
 
     // modal input first (consumed after the products)
-    double xv[4][NPT];
+    T xv[4][NPT];
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int pt = 0; pt < NPT; ++pt) xv[b][pt] = XP[(int64_t)nd[b] * (4 * PW) + pt * 64 + lane];
 
     // ---- products at the samples
-    double uq[KEEPU ? NPR : 1][4][3];
+    T uq[KEEPU ? NPR : 1][4][3];
 #pragma unroll
     for (int r = 0; r < NPR; ++r) {
       if (!okP[r]) continue;
       const int s = sP[r], i = iP[r];
-      double U[4][3], Wi[4];
+      T U[4][3], Wi[4];
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        const double* ut = UT + (int64_t)nd[b] * (3 * M) + s;
+        const T* ut = UT + (int64_t)nd[b] * (3 * M) + s;
 #pragma unroll
         for (int j = 0; j < 3; ++j) U[b][j] = ut[j * M];
         Wi[b] = RESID ? ut[i * M] : VT[(int64_t)nd[b] * (3 * M) + i * M + s];
       }
-      double gW[3], su[3];
+      T gW[3], su[3];
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         gW[j] = dN[0][j] * Wi[0] + dN[1][j] * Wi[1] + dN[2][j] * Wi[2] + dN[3][j] * Wi[3];
         su[j] = U[0][j] + U[1][j] + U[2][j] + U[3][j];
       }
-      double u[4][3];
+      T u[4][3];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) u[q][j] = TS_QB * su[j] + (TS_QA - TS_QB) * U[q][j];
-      double conv[4];
+        for (int j = 0; j < 3; ++j) u[q][j] = QB * su[j] + QAB * U[q][j];
+      T conv[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) conv[q] = u[q][0] * gW[0] + u[q][1] * gW[1] + u[q][2] * gW[2];
       if (NEWTON) {
-        double Wd[4][3], Ui[4];
+        T Wd[4][3], Ui[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          const double* vt = VT + (int64_t)nd[b] * (3 * M) + s;
+          const T* vt = VT + (int64_t)nd[b] * (3 * M) + s;
 #pragma unroll
           for (int j = 0; j < 3; ++j) Wd[b][j] = vt[j * M];
           Ui[b] = UT[(int64_t)nd[b] * (3 * M) + i * M + s];
         }
-        double gU[3], sw[3];
+        T gU[3], sw[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
           gU[j] = dN[0][j] * Ui[0] + dN[1][j] * Ui[1] + dN[2][j] * Ui[2] + dN[3][j] * Ui[3];
@@ -232,16 +283,16 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          double wq[3];
+          T wq[3];
 #pragma unroll
-          for (int j = 0; j < 3; ++j) wq[j] = TS_QB * sw[j] + (TS_QA - TS_QB) * Wd[q][j];
+          for (int j = 0; j < 3; ++j) wq[j] = QB * sw[j] + QAB * Wd[q][j];
           conv[q] += wq[0] * gU[0] + wq[1] * gU[1] + wq[2] * gU[2];
           // this lane's component i of the direction at point q
           sWq[(q * 3 + i) * RM + s] = i == 0 ? wq[0] : (i == 1 ? wq[1] : wq[2]);
         }
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) sC[(i * 4 + q) * RS + s] = conv[q];
+      for (int q = 0; q < 4; ++q) sC[R::row(q, i) * RS + s] = conv[q];
       if (KEEPU)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
@@ -269,32 +320,32 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int j = 0; j < NTL; ++j) tv[q][j] = tok[j] ? v.tau[(en * 4 + q) * P + lane + 64 * j] : 0.0;
+        for (int j = 0; j < NTL; ++j) tv[q][j] = tok[j] ? TAU[(en * 4 + q) * P + lane + 64 * j] : T(0);
     }
     __syncthreads();
 
     // ---- conv(t) -> modes: lane (q = g, p), reg i
-    double cm[NPT][3];
+    T cm[NPT][3];
     {
-      double a[NKB];
+      T a[NKB];
 #pragma unroll
       for (int ks = 0; ks < NKB; ++ks) a[ks] = sC[c * RS + ks * 4 + g];
 #pragma unroll
       for (int pt = 0; pt < NPT; ++pt) {
-        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        T4 acc = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int ks = 0; ks < NKB; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], Bb[ks][pt], acc, 0, 0, 0);
+        for (int ks = 0; ks < NKB; ++ks) acc = R::run(a[ks], Bb[ks][pt], acc);
 #pragma unroll
         for (int i = 0; i < 3; ++i) cm[pt][i] = acc[i];
       }
     }
 
     // ---- momentum operator L per (q, position)
-    double gal[NPT][3];
+    T gal[NPT][3];
 #pragma unroll
     for (int pt = 0; pt < NPT; ++pt) {
       const int p = c + 16 * pt;
-      double Vb[4][4], Vq[3];
+      T Vb[4][4], Vq[3];
 #pragma unroll
       for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -303,9 +354,9 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
       for (int i = 0; i < 3; ++i) Vq[i] = sV[(g * 4 + i) * RP + p];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const double du = TS_QB * (Vb[0][i] + Vb[1][i] + Vb[2][i] + Vb[3][i]) + (TS_QA - TS_QB) * Vq[i];
-        const double dp = dN[0][i] * Vb[0][3] + dN[1][i] * Vb[1][3] + dN[2][i] * Vb[2][3] + dN[3][i] * Vb[3][3];
-        gal[pt][i] = rho * fma(om[pt], swap_pair(du), cm[pt][i]);
+        const T du = QB * (Vb[0][i] + Vb[1][i] + Vb[2][i] + Vb[3][i]) + QAB * Vq[i];
+        const T dp = dN[0][i] * Vb[0][3] + dN[1][i] * Vb[1][3] + dN[2][i] * Vb[2][3] + dN[3][i] * Vb[3][3];
+        gal[pt][i] = rho * tfma(om[pt], swap_pair(du), cm[pt][i]);
         sL[(g * 3 + i) * RP + p] = NOLS ? gal[pt][i] : gal[pt][i] + dp;
         if (NOLS) sL[12 * RP + (g * 3 + i) * RP + p] = dp;
       }
@@ -313,20 +364,20 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
     __syncthreads();
 
     // ---- z = tau_q L (and tau_q grad p for the variant without LS coupling)
-    double z[NPT][3], zc[NPT][3];
+    T z[NPT][3], zc[NPT][3];
 #pragma unroll
     for (int pt = 0; pt < NPT; ++pt) {
-      double tr[n];
+      T tr[n];
 #pragma unroll
       for (int k = 0; k < n; ++k) tr[k] = sT[trow[pt] + k];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const double* lr = sL + (g * 3 + i) * RP;
-        double acc = 0.0, accc = 0.0;
+        const T* lr = sL + (g * 3 + i) * RP;
+        T acc = 0.0, accc = 0.0;
 #pragma unroll
         for (int k = 0; k < n; ++k) {
-          acc = fma(tr[k], lr[k], acc);
-          if (NOLS) accc = fma(tr[k], lr[12 * RP + k], accc);
+          acc = tfma(tr[k], lr[k], acc);
+          if (NOLS) accc = tfma(tr[k], lr[12 * RP + k], accc);
         }
         z[pt][i] = acc;
         zc[pt][i] = accc;
@@ -340,12 +391,12 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         sL[(g * 3 + i) * RP + p] = gal[pt][i] - om[pt] * swap_pair(z[pt][i]);
-        sZ[(g * 4 + i) * RP + p] = z[pt][i];
-        if (NOLS) sZ[16 * RP + (g * 4 + i) * RP + p] = zc[pt][i];
+        sZ[R::row(i, g) * RP + p] = z[pt][i];
+        if (NOLS) sZ[16 * RP + R::row(i, g) * RP + p] = zc[pt][i];
         if (p < n) {
           const int64_t zi = ((e * 4 + g) * 3 + i) * n + p;
           if (STOREZ) Zout[zi] = z[pt][i];
-          if (NEWTON) sZf[(g * 4 + i) * RP + p] = v.Z[zi];
+          if (NEWTON) sZf[R::row(i, g) * RP + p] = fz.Z[zi];
         }
       }
     }
@@ -353,31 +404,31 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
 
     // ---- z modes -> samples: lane (i = g, s = c + 16 mt), reg q; staged [i*4+q][s]
     {
-      double a[NKF], af[NEWTON ? NKF : 1];
+      T a[NKF], af[NEWTON ? NKF : 1];
 #pragma unroll
       for (int ks = 0; ks < NKF; ++ks) {
         a[ks] = sZ[c * RP + ks * 4 + g];
         if (NEWTON) af[NEWTON ? ks : 0] = sZf[c * RP + ks * 4 + g];
       }
-      dbl4 zt[MT], zft[NEWTON ? MT : 1];
+      T4 zt[MT], zft[NEWTON ? MT : 1];
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        T4 acc = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int ks = 0; ks < NKF; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], Bf[ks][mt], acc, 0, 0, 0);
+        for (int ks = 0; ks < NKF; ++ks) acc = R::run(a[ks], Bf[ks][mt], acc);
         zt[mt] = acc;
         if (NEWTON) {
-          dbl4 accf = {0.0, 0.0, 0.0, 0.0};
+          T4 accf = {T(0), T(0), T(0), T(0)};
 #pragma unroll
           for (int ks = 0; ks < NKF; ++ks)
-            accf = __builtin_amdgcn_mfma_f64_16x16x4f64(af[NEWTON ? ks : 0], Bf[ks][mt], accf, 0, 0, 0);
+            accf = R::run(af[NEWTON ? ks : 0], Bf[ks][mt], accf);
           zft[NEWTON ? mt : 0] = accf;
         }
       }
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         const int s = c + 16 * mt;
-        if (s < M) {
+        if (s < M && g < 3) {   // lane group 3 holds the padding rows
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             sC[(g * 4 + q) * RM + s] = zt[mt][q];
@@ -390,20 +441,20 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
 
     // ---- least-squares test products W_ji(t_s), lane (s, i)
     {
-      double W[NPR][3];
+      T W[NPR][3];
 #pragma unroll
       for (int r = 0; r < NPR; ++r) {
         W[r][0] = W[r][1] = W[r][2] = 0.0;
         if (!okP[r]) continue;
         const int s = sP[r], i = iP[r];
-        double u[4][3];
+        T u[4][3];
         if (KEEPU) {
 #pragma unroll
           for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int j = 0; j < 3; ++j) u[q][j] = uq[KEEPU ? r : 0][q][j];
         } else {
-          double U[4][3], su[3];
+          T U[4][3], su[3];
 #pragma unroll
           for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -413,24 +464,24 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
 #pragma unroll
           for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) u[q][j] = TS_QB * su[j] + (TS_QA - TS_QB) * U[q][j];
+            for (int j = 0; j < 3; ++j) u[q][j] = QB * su[j] + QAB * U[q][j];
         }
-        double zq[4];
+        T zq[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) zq[q] = sC[(i * 4 + q) * RM + s];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          double acc = 0.0;
+          T acc = 0.0;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc = fma(u[q][j], zq[q], acc);
+          for (int q = 0; q < 4; ++q) acc = tfma(u[q][j], zq[q], acc);
           W[r][j] = acc;
         }
         if (NEWTON) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const double zf = sZft[(i * 4 + q) * RM + s];
+            const T zf = sZft[(i * 4 + q) * RM + s];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) W[r][j] = fma(sWq[(q * 3 + j) * RM + s], zf, W[r][j]);
+            for (int j = 0; j < 3; ++j) W[r][j] = tfma(sWq[(q * 3 + j) * RM + s], zf, W[r][j]);
           }
         }
       }
@@ -439,36 +490,36 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
       for (int r = 0; r < NPR; ++r) {
         if (!okP[r]) continue;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) sC[(j * 4 + iP[r]) * RS + sP[r]] = wgt * W[r][j];
+        for (int j = 0; j < 3; ++j) sC[R::row(iP[r], j) * RS + sP[r]] = wgt * W[r][j];
       }
     }
     __syncthreads();
 
     // ---- W(t) -> modes: lane (i = g, p), reg j
-    double wm[NPT][3];
+    T wm[NPT][3];
     {
-      double a[NKB];
+      T a[NKB];
 #pragma unroll
       for (int ks = 0; ks < NKB; ++ks) a[ks] = sC[c * RS + ks * 4 + g];
 #pragma unroll
       for (int pt = 0; pt < NPT; ++pt) {
-        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        T4 acc = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int ks = 0; ks < NKB; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], Bb[ks][pt], acc, 0, 0, 0);
+        for (int ks = 0; ks < NKB; ++ks) acc = R::run(a[ks], Bb[ks][pt], acc);
 #pragma unroll
         for (int j = 0; j < 3; ++j) wm[pt][j] = acc[j];
       }
     }
 
     // ---- assembly: lane (field f = g, position p), node rows b
-    double* oe = out + e * (16 * n);
+    T* oe = out + e * (16 * n);
 #pragma unroll
     for (int pt = 0; pt < NPT; ++pt) {
       const int p = c + 16 * pt;
-      double o[4];
+      T o[4];
       if (g < 3) {
         const int i = g;
-        double Gq[4], Vf[4], Vp[4];
+        T Gq[4], Vf[4], Vp[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) Gq[q] = sL[(q * 3 + i) * RP + p];
 #pragma unroll
@@ -476,43 +527,43 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
           Vf[b] = sV[(b * 4 + i) * RP + p];
           Vp[b] = sV[(b * 4 + 3) * RP + p];
         }
-        const double Gs = Gq[0] + Gq[1] + Gq[2] + Gq[3];
-        const double ps = Vp[0] + Vp[1] + Vp[2] + Vp[3];
-        const double Vs = Vf[0] + Vf[1] + Vf[2] + Vf[3];
+        const T Gs = Gq[0] + Gq[1] + Gq[2] + Gq[3];
+        const T ps = Vp[0] + Vp[1] + Vp[2] + Vp[3];
+        const T Vs = Vf[0] + Vf[1] + Vf[2] + Vf[3];
         // sum_j dN_bj (W_ji + 4 w mu grad_j du_i): least-squares and viscous terms together
-        const double kv = 4.0 * wgt * mu, ks = shift * wgt;
-        double t[3];
+        const T kv = T(4) * wgt * mu, ks = T(shift) * wgt;
+        T t[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-          t[j] = fma(kv, dN[0][j] * Vf[0] + dN[1][j] * Vf[1] + dN[2][j] * Vf[2] + dN[3][j] * Vf[3], wm[pt][j]);
-        const double wq = wgt * (TS_QA - TS_QB), km = ks * (MD - MO), wps = -wgt * ps;
-        const double base = fma(wgt * TS_QB, Gs, ks * MO * Vs);
+          t[j] = tfma(kv, dN[0][j] * Vf[0] + dN[1][j] * Vf[1] + dN[2][j] * Vf[2] + dN[3][j] * Vf[3], wm[pt][j]);
+        const T wq = wgt * QAB, km = ks * (MD - MO), wps = -wgt * ps;
+        const T base = tfma(wgt * QB, Gs, ks * MO * Vs);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          const double dNi = i == 0 ? dN[b][0] : (i == 1 ? dN[b][1] : dN[b][2]);
-          double acc = fma(wq, Gq[b], base);       // sum_q w lam_qb G_qi
-          acc = fma(km, Vf[b], acc);               // mass shift
-          acc = fma(wps, dNi, acc);                // - (d_i N_b, p)
-          acc = fma(dN[b][0], t[0], acc);
-          acc = fma(dN[b][1], t[1], acc);
-          o[b] = fma(dN[b][2], t[2], acc);
+          const T dNi = i == 0 ? dN[b][0] : (i == 1 ? dN[b][1] : dN[b][2]);
+          T acc = tfma(wq, Gq[b], base);       // sum_q w lam_qb G_qi
+          acc = tfma(km, Vf[b], acc);               // mass shift
+          acc = tfma(wps, dNi, acc);                // - (d_i N_b, p)
+          acc = tfma(dN[b][0], t[0], acc);
+          acc = tfma(dN[b][1], t[1], acc);
+          o[b] = tfma(dN[b][2], t[2], acc);
         }
       } else {
-        double div = 0.0;
+        T div = 0.0;
 #pragma unroll
         for (int b = 0; b < 4; ++b)
 #pragma unroll
-          for (int j = 0; j < 3; ++j) div = fma(dN[b][j], sV[(b * 4 + j) * RP + p], div);
-        double zs[3];
+          for (int j = 0; j < 3; ++j) div = tfma(dN[b][j], sV[(b * 4 + j) * RP + p], div);
+        T zs[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-          const double* zr = sZ + (NOLS ? 16 * RP : 0) + i * RP + p;
-          zs[i] = zr[0] + zr[4 * RP] + zr[8 * RP] + zr[12 * RP];
+          const T* zr = sZ + (NOLS ? 16 * RP : 0) + p;
+          zs[i] = zr[R::row(i, 0) * RP] + zr[R::row(i, 1) * RP] + zr[R::row(i, 2) * RP] + zr[R::row(i, 3) * RP];
         }
-        const double wr = wgt * irho, wd = wgt * div;
+        const T wr = wgt * irho, wd = wgt * div;
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-          o[b] = fma(wr, dN[b][0] * zs[0] + dN[b][1] * zs[1] + dN[b][2] * zs[2], wd);
+          o[b] = tfma(wr, dN[b][0] * zs[0] + dN[b][1] * zs[1] + dN[b][2] * zs[2], wd);
       }
       if (p < n) {
 #pragma unroll
@@ -524,15 +575,23 @@ k_op(DevView v, const double* __restrict__ XP, const double* __restrict__ VT,
 }
 
 // ------------------------------------------------------------- dispatch
-template <int K, int MD>
-static hipError_t op_launch(const DevView& v, const double* XP, const double* VT, double* Zout,
-                            double* out, double shift, int64_t begin, int64_t end, hipStream_t st) {
+template <typename T>
+struct OpArgs {
+  const T* XP;
+  const T* VT;
+  T* out;
+  double* Zout;
+};
+
+template <int K, int MD, typename T>
+static hipError_t op_launch(const DevView& v, const OpArgs<T>& a, double shift, int64_t begin,
+                            int64_t end, hipStream_t st) {
   static int max_blocks = 0;   // resident blocks on the whole device, multiple of 8
   if (max_blocks == 0) {
     int dev = 0, ncu = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_op<K, MD>, 64, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_op<K, MD, T>, 64, 0);
     if (e != hipSuccess) return e;
     const int mb = ncu * (per_cu > 0 ? per_cu : 1);
     max_blocks = mb < 8 ? 8 : mb / 8 * 8;
@@ -540,21 +599,31 @@ static hipError_t op_launch(const DevView& v, const double* XP, const double* VT
   const int64_t cnt = end - begin;
   int64_t nb = (cnt + 7) / 8 * 8;
   if (nb > max_blocks) nb = max_blocks;
-  k_op<K, MD><<<(unsigned)nb, 64, 0, st>>>(v, XP, VT, Zout, out, shift, begin, end);
+  k_op<K, MD, T><<<(unsigned)nb, 64, 0, st>>>(v, a.XP, a.VT, a.Zout, a.out, T(shift), begin, end);
   return hipGetLastError();
 }
 
 template <int K>
-static hipError_t op_dispatch(const DevView& v, int mode, const double* XP, const double* VT,
-                              double* Zout, double* out, double shift, int64_t begin, int64_t end,
-                              hipStream_t st) {
+static hipError_t op_dispatch(const DevView& v, int mode, const OpArgs<double>& a, double shift,
+                              int64_t begin, int64_t end, hipStream_t st) {
   switch (mode) {
-    case MODE_RESID: return op_launch<K, MODE_RESID>(v, XP, VT, Zout, out, shift, begin, end, st);
-    case MODE_RESID | MODE_STOREZ:
-      return op_launch<K, MODE_RESID | MODE_STOREZ>(v, XP, VT, Zout, out, shift, begin, end, st);
-    case 0: return op_launch<K, 0>(v, XP, VT, Zout, out, shift, begin, end, st);
-    case MODE_NOLS: return op_launch<K, MODE_NOLS>(v, XP, VT, Zout, out, shift, begin, end, st);
-    case MODE_NEWTON: return op_launch<K, MODE_NEWTON>(v, XP, VT, Zout, out, shift, begin, end, st);
+    case MODE_RESID: return op_launch<K, MODE_RESID>(v, a, shift, begin, end, st);
+    case MODE_RESID | MODE_STOREZ: return op_launch<K, MODE_RESID | MODE_STOREZ>(v, a, shift, begin, end, st);
+    case 0: return op_launch<K, 0>(v, a, shift, begin, end, st);
+    case MODE_NOLS: return op_launch<K, MODE_NOLS>(v, a, shift, begin, end, st);
+    case MODE_NEWTON: return op_launch<K, MODE_NEWTON>(v, a, shift, begin, end, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// FP32 instantiations: tangent modes only (the residual stays FP64)
+template <int K>
+static hipError_t op_dispatch(const DevView& v, int mode, const OpArgs<float>& a, double shift,
+                              int64_t begin, int64_t end, hipStream_t st) {
+  switch (mode) {
+    case 0: return op_launch<K, 0>(v, a, shift, begin, end, st);
+    case MODE_NOLS: return op_launch<K, MODE_NOLS>(v, a, shift, begin, end, st);
+    case MODE_NEWTON: return op_launch<K, MODE_NEWTON>(v, a, shift, begin, end, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -563,8 +632,23 @@ hipError_t launch_elem(const DevView& v, int mode, const double* XP, const doubl
                        double* Zout, double* out, double shift, int64_t begin, int64_t end,
                        hipStream_t st) {
   if (end <= begin) return hipSuccess;
+  const OpArgs<double> a{XP, VT, out, Zout};
   switch (v.K) {
-#define CASE(k) case k: return op_dispatch<k>(v, mode, XP, VT, Zout, out, shift, begin, end, st);
+#define CASE(k) case k: return op_dispatch<k>(v, mode, a, shift, begin, end, st);
+    TSGLS_FOR_EACH_K(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_elem_f32(const DevView& v, int mode, const float* XP, const float* VT,
+                           float* out, double shift, int64_t begin, int64_t end, hipStream_t st) {
+  if (end <= begin) return hipSuccess;
+  if (mode & (MODE_RESID | MODE_STOREZ)) return hipErrorInvalidValue;
+  if (!v.UT32 || !v.tau32 || (!v.Z32 && (mode & MODE_NEWTON))) return hipErrorInvalidValue;
+  const OpArgs<float> a{XP, VT, out, nullptr};
+  switch (v.K) {
+#define CASE(k) case k: return op_dispatch<k>(v, mode, a, shift, begin, end, st);
     TSGLS_FOR_EACH_K(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;

@@ -60,6 +60,13 @@ struct tsgls_ctx {
   double* partial = nullptr;
   double* dh = nullptr;
   bool linearized = false;
+  // FP32 copies of the linearization for the mixed-precision tangent
+  // (allocated on first use; the FP32 modes, samples and element rows reuse
+  // the FP64 buffers XP, VT and ebuf, which they fit in half)
+  float* tau32 = nullptr;
+  float* UT32 = nullptr;
+  float* Z32 = nullptr;
+  bool lin32 = false;     // the copies match the last linearize
   // optional per-launch timing with HIP events (benchmark support)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -143,6 +150,9 @@ DevView view(const tsgls_ctx* c) {
   v.UT = c->UT;
   v.tau = c->tau;
   v.Z = c->Z;
+  v.UT32 = c->UT32;
+  v.tau32 = c->tau32;
+  v.Z32 = c->Z32;
   v.noff = c->noff;
   v.ninc = c->ninc;
   v.fconn = c->fconn;
@@ -219,6 +229,7 @@ int apply_operator(tsgls_ctx* c, const DevView& v, int mode, const double* Y, co
 
 int linearize_impl(tsgls_ctx* c, const double* y, double* r) {
   DevView v = view(c);
+  c->lin32 = false;
   HIPCHK(c, launch_prep_time(c->K, y, nullptr, c->nflag, 0, c->F, c->UT, c->XP, c->nn, c->st));
   {
     ProfScope ps(c, TSGLS_PROF_TAU);
@@ -231,15 +242,54 @@ int linearize_impl(tsgls_ctx* c, const double* y, double* r) {
   return TSGLS_OK;
 }
 
+// FP32 copies of tau, the velocity samples and tau L(u) of the last
+// linearization (made once per linearization, on the first FP32 product).
+int ensure_lin32(tsgls_ctx* c) {
+  if (c->lin32) return TSGLS_OK;
+  if (!c->tau32) {
+    CHK(dalloc(c, &c->tau32, (size_t)c->E * 4 * c->P));
+    CHK(dalloc(c, &c->UT32, (size_t)c->nn * 3 * c->M));
+    CHK(dalloc(c, &c->Z32, (size_t)c->E * 12 * c->n));
+  }
+  HIPCHK(c, launch_to_f32(c->tau, c->tau32, c->E * 4 * c->P, c->st));
+  HIPCHK(c, launch_to_f32(c->UT, c->UT32, c->nn * 3 * c->M, c->st));
+  HIPCHK(c, launch_to_f32(c->Z, c->Z32, c->E * 12 * c->n, c->st));
+  c->lin32 = true;
+  return TSGLS_OK;
+}
+
 // out = J (x * xs) (xs: optional entrywise scale of the input, e.g. the
-// right preconditioner inside GMRES).
-int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt, const double* xs = nullptr) {
+// right preconditioner inside GMRES).  prec TSGLS_PREC_F32 runs the element
+// operator in FP32; the node sums and the face terms stay FP64.
+int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt, const double* xs = nullptr,
+            int prec = TSGLS_PREC_F64) {
   if (!c->linearized) return fail(c, TSGLS_ESTATE, "jv before linearize");
   DevView v = view(c);
   const int mode = jac == TSGLS_JAC_PICARD ? 0 : jac == TSGLS_JAC_PICARD_NOLS ? MODE_NOLS : MODE_NEWTON;
   const double shift = dt > 0 ? 1.5 * c->p.rho / dt : 0.0;
-  HIPCHK(c, launch_prep_time(c->K, x, xs, c->nflag, 1, c->F, c->VT, c->XP, c->nn, c->st));
-  return apply_operator(c, v, mode, x, c->VT, nullptr, out, shift, c->aneg, 0, xs);
+  if (prec == TSGLS_PREC_F64) {
+    HIPCHK(c, launch_prep_time(c->K, x, xs, c->nflag, 1, c->F, c->VT, c->XP, c->nn, c->st));
+    return apply_operator(c, v, mode, x, c->VT, nullptr, out, shift, c->aneg, 0, xs);
+  }
+  CHK(ensure_lin32(c));
+  v = view(c);
+  float* XP32 = reinterpret_cast<float*>(c->XP);
+  float* VT32 = reinterpret_cast<float*>(c->VT);
+  float* eb32 = reinterpret_cast<float*>(c->ebuf);
+  HIPCHK(c, launch_prep_time_f32(c->K, x, xs, c->nflag, 1, c->F, VT32, XP32, c->nn, c->st));
+  {
+    ProfScope ps(c, TSGLS_PROF_ELEM_TANGENT);
+    HIPCHK(c, launch_elem_f32(v, mode, XP32, VT32, eb32, shift, 0, c->E, c->st));
+  }
+  {
+    ProfScope ps(c, TSGLS_PROF_GATHER);
+    HIPCHK(c, launch_gather_f32(c->K, c->noff, c->ninc, c->nflag, eb32, out, c->nn, c->st));
+  }
+  if (c->nf) {
+    ProfScope ps(c, TSGLS_PROF_FACE);
+    HIPCHK(c, launch_face_apply(v, x, xs, 0, c->aneg, out, c->st));
+  }
+  return TSGLS_OK;
 }
 
 int diag_impl(tsgls_ctx* c, double* d, double dt) {
@@ -308,7 +358,7 @@ int ensure_krylov(tsgls_ctx* c, int m) {
 //   update pass: q_j into slot j, u_{j+1} = (w - Q b - q_j h_jj)/sigma.
 // The last column is finalized with one extra reduction (no product).
 int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv, int jac,
-                  double dt, int* mv_out) {
+                  double dt, int prec, int* mv_out) {
   const int64_t n = ndof(c);
   const int nb = multidot_blocks(n);
   HIPCHK(c, launch_zero(x, n, c->st));
@@ -356,7 +406,7 @@ int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, i
     if (first) {
       HIPCHK(c, launch_copy(b, V0, n, c->st));
     } else {
-      CHK(jv_impl(c, x, c->kt, jac, dt));
+      CHK(jv_impl(c, x, c->kt, jac, dt, nullptr, prec));
       ++mv;
       HIPCHK(c, launch_copy(b, V0, n, c->st));
       HIPCHK(c, launch_axpy(-1.0, c->kt, V0, n, c->st));
@@ -375,7 +425,7 @@ int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, i
     for (int j = 0; j < m && mv < maxmv; ++j) {
       double* u = c->V + (int64_t)j * n;
       double* w = c->V + (int64_t)(j + 1) * n;
-      CHK(jv_impl(c, u, w, jac, dt, c->minv));
+      CHK(jv_impl(c, u, w, jac, dt, c->minv, prec));
       ++mv;
       CHK(reduce(j, u, w));
       const double* a = red.data();
@@ -471,7 +521,7 @@ int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, i
 // Right-Jacobi-preconditioned restarted GMRES with classical Gram-Schmidt and
 // one reorthogonalization pass; x = J^{-1} b approximately, x zeroed first.
 int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv, int jac,
-          double dt, int* mv_out) {
+          double dt, int prec, int* mv_out) {
   const int64_t n = ndof(c);
   HIPCHK(c, launch_zero(x, n, c->st));
   double bnorm;
@@ -489,7 +539,7 @@ int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv
     if (first) {
       HIPCHK(c, launch_copy(b, V0, n, c->st));
     } else {
-      CHK(jv_impl(c, x, c->kt, jac, dt));
+      CHK(jv_impl(c, x, c->kt, jac, dt, nullptr, prec));
       ++mv;
       HIPCHK(c, launch_copy(b, V0, n, c->st));
       HIPCHK(c, launch_axpy(-1.0, c->kt, V0, n, c->st));
@@ -508,7 +558,7 @@ int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv
       double* Vj = c->V + (int64_t)j * n;
       double* Vn = c->V + (int64_t)(j + 1) * n;
       HIPCHK(c, launch_mul(c->minv, Vj, c->kt, n, c->st));
-      CHK(jv_impl(c, c->kt, Vn, jac, dt));
+      CHK(jv_impl(c, c->kt, Vn, jac, dt, nullptr, prec));
       ++mv;
       double hn;
       if (j + 1 <= 32) {
@@ -824,6 +874,16 @@ int tsgls_jv(tsgls_ctx* c, const double* v, double* Jv, int jacobian, double dt_
   return jv_impl(c, v, Jv, jacobian, dt_pseudo);
 }
 
+int tsgls_jv_prec(tsgls_ctx* c, const double* v, double* Jv, int jacobian, double dt_pseudo,
+                  int precision) {
+  if (!c) return TSGLS_EINVAL;
+  if (!v || !Jv || v == Jv) return fail(c, TSGLS_EINVAL, "bad vectors");
+  if (jacobian < 0 || jacobian > 2) return fail(c, TSGLS_EINVAL, "bad tangent variant %d", jacobian);
+  if (precision != TSGLS_PREC_F64 && precision != TSGLS_PREC_F32)
+    return fail(c, TSGLS_EINVAL, "bad precision %d", precision);
+  return jv_impl(c, v, Jv, jacobian, dt_pseudo, nullptr, precision);
+}
+
 int tsgls_jacobi_diag(tsgls_ctx* c, double* d, double dt_pseudo) {
   if (!c) return TSGLS_EINVAL;
   if (!d) return fail(c, TSGLS_EINVAL, "null vector");
@@ -855,7 +915,8 @@ int tsgls_solve(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_
   if (!c) return TSGLS_EINVAL;
   if (!y || !o) return fail(c, TSGLS_EINVAL, "null argument");
   if (o->restart < 1 || o->restart > 1000 || o->max_newton < 0 || o->max_matvec < 1 || !(o->rtol > 0) ||
-      !(o->lin_rtol > 0) || o->jacobian < 0 || o->jacobian > 2)
+      !(o->lin_rtol > 0) || o->jacobian < 0 || o->jacobian > 2 ||
+      (o->tangent_precision != TSGLS_PREC_F64 && o->tangent_precision != TSGLS_PREC_F32))
     return fail(c, TSGLS_EINVAL, "bad solve options");
   const auto t0 = std::chrono::steady_clock::now();
   tsgls_solve_stats st{};
@@ -885,9 +946,11 @@ int tsgls_solve(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_
     HIPCHK(c, launch_scal_copy(-1.0, r, r, n, c->st));
     int mv = 0;
     if (o->restart <= 32)
-      CHK(gmres_delayed(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, o->dt_pseudo, &mv));
+      CHK(gmres_delayed(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, o->dt_pseudo,
+                        o->tangent_precision, &mv));
     else
-      CHK(gmres(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, o->dt_pseudo, &mv));
+      CHK(gmres(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, o->dt_pseudo,
+                o->tangent_precision, &mv));
     st.matvecs += mv;
     HIPCHK(c, launch_axpy(1.0, c->kx, y, n, c->st));
     CHK(linearize_impl(c, y, r));

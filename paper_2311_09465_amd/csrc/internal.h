@@ -47,6 +47,9 @@ struct DevView {
   const double* UT;          // [n_nodes][3][M] frozen velocity samples
   const double* tau;         // [E][4][P] packed tau over positions
   const double* Z;           // [E][4][3][n] tau L(u) over positions
+  const float* UT32;         // FP32 copies of UT, tau, Z (mixed-precision tangent) or null
+  const float* tau32;
+  const float* Z32;
   const int32_t* noff;       // [n_nodes+1] node -> incident element slots
   const int32_t* ninc;       // element*4 + local node, ascending element
   const int32_t* fconn;      // [nf][3] Neumann faces
@@ -74,6 +77,10 @@ hipError_t launch_geometry(const double* xyz, const int32_t* conn, double* geo,
 hipError_t launch_prep_time(int K, const double* Y, const double* Ys,
                             const uint8_t* nflag, int masked, const double* F,
                             double* XT, double* XP, int64_t n_nodes, hipStream_t st);
+// The same with FP32 outputs (the sums are formed in FP64).
+hipError_t launch_prep_time_f32(int K, const double* Y, const double* Ys,
+                                const uint8_t* nflag, int masked, const double* F,
+                                float* XT, float* XP, int64_t n_nodes, hipStream_t st);
 // Positions per field row of XP (16 or 32).
 int pos_width(int K);
 hipError_t launch_tau(const DevView& v, const double* Y, double* tau,
@@ -85,6 +92,10 @@ hipError_t launch_tau(const DevView& v, const double* Y, double* tau,
 hipError_t launch_elem(const DevView& v, int mode, const double* XP,
                        const double* VT, double* Zout, double* out,
                        double shift, int64_t begin, int64_t end, hipStream_t st);
+// Mixed-precision tangent: the same operator in FP32 (modes 0, MODE_NOLS,
+// MODE_NEWTON) on the FP32 copies v.UT32, v.tau32, v.Z32.
+hipError_t launch_elem_f32(const DevView& v, int mode, const float* XP, const float* VT,
+                           float* out, double shift, int64_t begin, int64_t end, hipStream_t st);
 hipError_t launch_diag(const DevView& v, double* d, double shift,
                        int64_t begin, int64_t end, hipStream_t st);
 // out[node][4][S] = sum over incident (element, local node) of the ebuf rows
@@ -93,6 +104,10 @@ hipError_t launch_diag(const DevView& v, double* d, double shift,
 hipError_t launch_gather(int K, const int32_t* noff, const int32_t* ninc,
                          const uint8_t* nflag, const double* ebuf, double* out,
                          int64_t n_nodes, hipStream_t st);
+// The same from FP32 element rows (accumulated in FP64).
+hipError_t launch_gather_f32(int K, const int32_t* noff, const int32_t* ninc,
+                             const uint8_t* nflag, const float* ebuf, double* out,
+                             int64_t n_nodes, hipStream_t st);
 hipError_t launch_face_lin(const DevView& v, const double* Y, double* aneg,
                            hipStream_t st);
 hipError_t launch_face_apply(const DevView& v, const double* Y, const double* Ys, int resid,
@@ -110,6 +125,8 @@ hipError_t launch_axpy(double a, const double* x, double* y, int64_t n, hipStrea
 hipError_t launch_scal_copy(double a, const double* x, double* y, int64_t n, hipStream_t st);
 hipError_t launch_mul(const double* a, const double* x, double* y, int64_t n, hipStream_t st);
 hipError_t launch_recip(double* x, int64_t n, hipStream_t st);
+// y = x rounded to FP32
+hipError_t launch_to_f32(const double* x, float* y, int64_t n, hipStream_t st);
 // partial[b*J + j] = sum over block b's chunk of V[j]*w; J <= 128.
 hipError_t launch_multidot(const double* V, int64_t ldv, int J, const double* w,
                            double* partial, int nblocks, int64_t n, hipStream_t st);
