@@ -44,15 +44,16 @@ def jv_flops_per_element(K: int, variant: str = "picard") -> float:
     return 2.0 * n * M * R + 24.0 * n * n + 300.0 * n
 
 
-def jv_bytes(K: int, E: int, nn: int, variant: str = "picard") -> float:
-    """Algorithmic HBM bytes of one tangent product: packed FP64 tau (4 points
-    x n(n+1)/2), element connectivity + geometry (4 i32 + 13 f64), and per node
-    the direction in, the frozen state and the product out."""
+def jv_bytes(K: int, E: int, nn: int, variant: str = "picard", word: int = 8) -> float:
+    """Algorithmic HBM bytes of one tangent product: packed tau (4 points x
+    n(n+1)/2), element connectivity + geometry (4 i32 + 13 f64), and per node
+    the direction in, the frozen state and the product out; word = 8 for the
+    FP64 tangent, 4 for the FP32 one (tau, state and direction in FP32)."""
     n = 2 * K + 1
     P = n * (n + 1) // 2
-    b = E * (32.0 * P + 120.0) + nn * 8.0 * (4 * n + 3 * n + 4 * n)
+    b = E * (4.0 * word * P + 120.0) + nn * word * (4 * n + 3 * n + 4 * n)
     if variant == "newton":
-        b += E * 96.0 * n
+        b += E * 12.0 * word * n
     return b
 
 
@@ -135,14 +136,16 @@ def read_traffic():
             return None
         return dict(bytes_per_launch=float(kv["hbm_bytes_per_launch"]),
                     fetch_bytes=float(kv["fetch_bytes_per_launch"]),
-                    write_bytes=float(kv["write_bytes_per_launch"]))
+                    write_bytes=float(kv["write_bytes_per_launch"]),
+                    f32_bytes_per_launch=float(kv["f32_hbm_bytes_per_launch"]))
     except (OSError, KeyError, ValueError):
         return None
 
 
 def probe(args):
-    """Counter-collection workload: linearize, three tangent products, then a
-    plain device copy of 512 MiB (the reference for scaling the counters)."""
+    """Counter-collection workload: linearize, three FP64 and three FP32
+    tangent products, then a plain device copy of 512 MiB (the reference for
+    scaling the counters)."""
     import torch
     import paper_2311_09465_amd as T
     from workloads import initial_guess
@@ -154,6 +157,8 @@ def probe(args):
     o = torch.zeros_like(y)
     for _ in range(3):
         s.jv(v, o, args.jacobian)
+    for _ in range(3):
+        s.jv(v, o, args.jacobian, precision="f32")
     a = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
@@ -179,30 +184,40 @@ def summarize_pmc(fetch_csv, write_csv, command):
     res = {}
     for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
         rows = per_kernel(path, counter)
-        op = [r for r in rows if "k_op<" in r[1] and ", 0>" in r[1]]
         cp = [r for r in rows if "copy" in r[1].lower()]
-        if not op or not cp:
-            raise SystemExit(f"{path}: kernel or copy dispatch not found")
+        if not cp:
+            raise SystemExit(f"{path}: copy dispatch not found")
         copy_meas = max(r[2] for r in cp)
         factor = copy_bytes / copy_meas
-        raw = op[-1][2]
-        res[counter] = (raw, factor, raw * factor, copy_meas)
-    fb, wb = res["FETCH_SIZE"][2], res["WRITE_SIZE"][2]
+        for typ in ("double", "float"):
+            op = [r for r in rows if "k_op<" in r[1] and f", 0, {typ}>" in r[1]]
+            if not op:
+                raise SystemExit(f"{path}: k_op<K, 0, {typ}> dispatch not found")
+            raw = op[-1][2]
+            res[(counter, typ)] = (raw, factor, raw * factor, copy_meas)
+    fb, wb = res[("FETCH_SIZE", "double")][2], res[("WRITE_SIZE", "double")][2]
+    fb32, wb32 = res[("FETCH_SIZE", "float")][2], res[("WRITE_SIZE", "float")][2]
     lines = [
-        "# HBM traffic of the tangent element kernel k_op<6,0> (junction 1M tets, K = 6)",
+        "# HBM traffic of the tangent element kernel k_op<6,0,T> (junction 1M tets, K = 6),",
+        "# T = double (FP64 tangent) and T = float (mixed-precision tangent, f32_ lines)",
         "# Commands (repository root, one MI355X):",
         f"#   {command.format(counter='FETCH_SIZE', d='pmc_fetch')}",
         f"#   {command.format(counter='WRITE_SIZE', d='pmc_write')}",
         f"#   python bench.py --summarize-pmc <pmc_fetch csv> <pmc_write csv>",
         "# Counters are KiB per dispatch; each is scaled by (bytes of the 512 MiB probe copy) /",
         "# (what the same counter reads for that copy).",
-        f"fetch_raw_bytes = {res['FETCH_SIZE'][0]:.0f}",
-        f"fetch_copy_factor = {res['FETCH_SIZE'][1]:.4f}",
-        f"write_raw_bytes = {res['WRITE_SIZE'][0]:.0f}",
-        f"write_copy_factor = {res['WRITE_SIZE'][1]:.4f}",
+        f"fetch_raw_bytes = {res[('FETCH_SIZE', 'double')][0]:.0f}",
+        f"fetch_copy_factor = {res[('FETCH_SIZE', 'double')][1]:.4f}",
+        f"write_raw_bytes = {res[('WRITE_SIZE', 'double')][0]:.0f}",
+        f"write_copy_factor = {res[('WRITE_SIZE', 'double')][1]:.4f}",
         f"fetch_bytes_per_launch = {fb:.0f}",
         f"write_bytes_per_launch = {wb:.0f}",
         f"hbm_bytes_per_launch = {fb + wb:.0f}",
+        f"f32_fetch_raw_bytes = {res[('FETCH_SIZE', 'float')][0]:.0f}",
+        f"f32_write_raw_bytes = {res[('WRITE_SIZE', 'float')][0]:.0f}",
+        f"f32_fetch_bytes_per_launch = {fb32:.0f}",
+        f"f32_write_bytes_per_launch = {wb32:.0f}",
+        f"f32_hbm_bytes_per_launch = {fb32 + wb32:.0f}",
         f"kernel_source_hash = {kernel_source_hash()}",
     ]
     with open(TRAFFIC_FILE, "w") as fh:
@@ -256,6 +271,7 @@ def main():
     if args.warmup > 0:
         s.solve(y, max_newton=args.warmup, **step_kw)
     torch.cuda.synchronize()
+    y_start = y.clone()   # the mixed-precision run below starts from the same state
     s.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -309,6 +325,38 @@ def main():
         jv_ms = (time.perf_counter() - a) / reps * 1e3
         out["jv_ms"] = round(jv_ms, 3)
         out["jv_only_gdof_modes_s"] = round(dof / jv_ms / 1e6, 4)
+        # mixed precision: the same steps, from the same state, with the FP32
+        # element operator in the tangent (residual, tau, diagonal and Krylov
+        # stay FP64); one FP32 product first allocates the FP32 copies
+        s.jv(v, o, args.jacobian, precision="f32")
+        y.copy_(y_start)
+        torch.cuda.synchronize()
+        s.profile(True)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        s.solve(y, max_newton=args.steps, tangent_precision="f32", **step_kw)
+        torch.cuda.synchronize()
+        secs32 = time.perf_counter() - a
+        prof32 = {k: s.profile_get(k) for k in s.PROF}
+        s.profile(False)
+        l32, t32 = prof32["elem_tangent"]
+        avg32 = t32 / max(l32, 1) / 1e3
+        s.jv(v, o, args.jacobian, precision="f32")
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            s.jv(v, o, args.jacobian, precision="f32")
+        torch.cuda.synchronize()
+        jv32 = (time.perf_counter() - a) / reps * 1e3
+        out["mixed_f32_tangent"] = dict(
+            value=round(args.steps * m * dof / secs32 / 1e9, 4),
+            ms_per_step=round(secs32 / args.steps * 1e3, 3),
+            breakdown_ms_per_step={k: round(v_[1] / args.steps, 3) for k, v_ in prof32.items()},
+            elem_tangent_avg_launch_us=round(avg32 * 1e6, 2),
+            elem_tangent_tflops_fp32=round(fl / avg32 / 1e12, 3),
+            elem_tangent_algorithmic_bytes=round(jv_bytes(K, E, nn, args.jacobian, word=4)),
+            elem_tangent_traffic=None if tr is None else round(tr["f32_bytes_per_launch"]),
+            jv_ms=round(jv32, 3))
         # time to 1e-8 on the small Womersley case (full solve, FP64, Picard)
         del s
         torch.cuda.empty_cache()
@@ -319,6 +367,14 @@ def main():
         out["time_to_1e8_womersley_6k_K3_s"] = round(stw["seconds"], 4)
         out["time_to_1e8_womersley_6k_K3_newton_iters"] = stw["newton_iters"]
         out["time_to_1e8_womersley_6k_K3_matvecs"] = stw["matvecs"]
+        yw = torch.from_numpy(initial_guess(pw)).cuda()
+        stw = sw.solve(yw, rtol=1e-8, lin_rtol=0.05, restart=100, max_newton=60,
+                       tangent_precision="f32")
+        out["mixed_f32_tangent"].update(
+            time_to_1e8_womersley_6k_K3_s=round(stw["seconds"], 4),
+            time_to_1e8_womersley_6k_K3_newton_iters=stw["newton_iters"],
+            time_to_1e8_womersley_6k_K3_matvecs=stw["matvecs"],
+            time_to_1e8_womersley_6k_K3_status=stw["status"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, m)
     print(json.dumps(out), flush=True)
