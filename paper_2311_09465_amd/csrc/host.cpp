@@ -581,15 +581,24 @@ int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv
         for (int i = 0; i < J; ++i) h[i] = h2[i] + h2[J + i];
         hn = std::sqrt(std::max(h2[2 * J], 0.0));
       } else {
-        {
-          ProfScope ps(c, TSGLS_PROF_ORTHO);
-          CHK(multidot(c, c->V, n, j + 1, Vn, c->dh, h.data()));
-          HIPCHK(c, launch_multiaxpy(c->V, n, j + 1, c->dh, Vn, n, c->st));
-          CHK(multidot(c, c->V, n, j + 1, Vn, c->dh, h2.data()));
-          HIPCHK(c, launch_multiaxpy(c->V, n, j + 1, c->dh, Vn, n, c->st));
-        }
-        for (int i = 0; i <= j; ++i) h[i] += h2[i];
-        CHK(norm2(c, Vn, &hn));
+        // CGS2: two dot/update passes and the norm, one host synchronisation
+        ProfScope ps(c, TSGLS_PROF_ORTHO);
+        const int J = j + 1, nb = multidot_blocks(n);
+        double* dh1 = c->dh;            // h  [J]
+        double* dh2 = c->dh + J;        // h2 [J]
+        double* dnn = c->dh + 2 * J;    // |Vn|^2
+        HIPCHK(c, launch_multidot(c->V, n, J, Vn, c->partial, nb, n, c->st));
+        HIPCHK(c, launch_reduce_partials(c->partial, nb, J, dh1, c->st));
+        HIPCHK(c, launch_multiaxpy(c->V, n, J, dh1, Vn, n, c->st));
+        HIPCHK(c, launch_multidot(c->V, n, J, Vn, c->partial, nb, n, c->st));
+        HIPCHK(c, launch_reduce_partials(c->partial, nb, J, dh2, c->st));
+        HIPCHK(c, launch_multiaxpy(c->V, n, J, dh2, Vn, n, c->st));
+        HIPCHK(c, launch_multidot(Vn, 0, 1, Vn, c->partial, nb, n, c->st));
+        HIPCHK(c, launch_reduce_partials(c->partial, nb, 1, dnn, c->st));
+        HIPCHK(c, hipMemcpyAsync(h2.data(), c->dh, (2 * J + 1) * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(c, hipStreamSynchronize(c->st));
+        for (int i = 0; i < J; ++i) h[i] = h2[i] + h2[J + i];
+        hn = std::sqrt(std::max(h2[2 * J], 0.0));
       }
       if (!std::isfinite(hn)) return fail(c, TSGLS_ENONFINITE, "non-finite Krylov vector");
       if (hn > 0) HIPCHK(c, launch_scal_copy(1.0 / hn, Vn, Vn, n, c->st));

@@ -70,72 +70,81 @@ hipError_t launch_to_f32(const double* x, float* y, int64_t n, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- multi-dot
-// Block b owns the contiguous chunk [b*chunk, min(n, (b+1)*chunk)); for a
-// tile of up to 8 vectors each thread accumulates strided products, then the
-// block reduces in LDS in a fixed tree order.
+// Block b owns the contiguous chunk [b*chunk, min(n, (b+1)*chunk)); each
+// thread accumulates strided products for a tile of up to 8 vectors, then
+// the block sums them in a fixed order (block_sum_tile), so every result is
+// reproducible bit for bit.
 constexpr int MD_BS = 256;
 constexpr int MD_TILE = 8;
 
+// Block-wide sums of NT per-thread values (MD_BS threads = 4 waves): an xor
+// butterfly inside each wave (both partners add the same two numbers, so all
+// lanes agree), then the four wave sums in wave order.  Thread k < NT
+// returns sum k; red holds 4 * NT doubles.
+template <int NT>
+__device__ __forceinline__ double block_sum_tile(double (&x)[NT], double* red, int t) {
+  const int lane = t & 63, wv = t >> 6;
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    double v = x[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) red[wv * NT + k] = v;
+  }
+  __syncthreads();
+  double s = 0.0;
+  if (t < NT) s = ((red[t] + red[NT + t]) + red[2 * NT + t]) + red[3 * NT + t];
+  __syncthreads();   // red may be reused by the caller
+  return s;
+}
+
+// grid (nblocks, ceil(J / 8)): block (b, y) handles vectors 8y .. 8y+7.
 __global__ void __launch_bounds__(MD_BS)
 k_multidot(const double* __restrict__ V, int64_t ldv, int J, const double* __restrict__ w,
            double* __restrict__ partial, int64_t n, int64_t chunk) {
-  __shared__ double red[MD_TILE][MD_BS];
-  const int b = blockIdx.x, t = threadIdx.x;
+  __shared__ double red[4 * MD_TILE];
+  const int b = blockIdx.x, t = threadIdx.x, j0 = blockIdx.y * MD_TILE;
   const int64_t lo = (int64_t)b * chunk;
   const int64_t hi = lo + chunk < n ? lo + chunk : n;
-  for (int j0 = 0; j0 < J; j0 += MD_TILE) {
-    double acc[MD_TILE];
+  double acc[MD_TILE];
 #pragma unroll
-    for (int k = 0; k < MD_TILE; ++k) acc[k] = 0.0;
-    for (int64_t i = lo + t; i < hi; i += MD_BS) {
-      const double wi = w[i];
+  for (int k = 0; k < MD_TILE; ++k) acc[k] = 0.0;
+  for (int64_t i = lo + t; i < hi; i += MD_BS) {
+    const double wi = w[i];
 #pragma unroll
-      for (int k = 0; k < MD_TILE; ++k)
-        if (j0 + k < J) acc[k] = fma(V[(int64_t)(j0 + k) * ldv + i], wi, acc[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < MD_TILE; ++k) red[k][t] = acc[k];
-    __syncthreads();
-    for (int s = MD_BS / 2; s > 0; s >>= 1) {
-      if (t < s) {
-#pragma unroll
-        for (int k = 0; k < MD_TILE; ++k) red[k][t] += red[k][t + s];
-      }
-      __syncthreads();
-    }
-    if (t < MD_TILE && j0 + t < J) partial[(int64_t)b * J + j0 + t] = red[t][0];
-    __syncthreads();
+    for (int k = 0; k < MD_TILE; ++k)
+      if (j0 + k < J) acc[k] = fma(V[(int64_t)(j0 + k) * ldv + i], wi, acc[k]);
   }
+  const double sum = block_sum_tile<MD_TILE>(acc, red, t);
+  if (t < MD_TILE && j0 + t < J) partial[(int64_t)b * J + j0 + t] = sum;
 }
 
+// Chunks of at least 256 entries (one per thread), at most 1024 blocks.
 int multidot_blocks(int64_t n) {
-  int64_t b = (n + 4095) / 4096;
+  int64_t b = (n + 255) / 256;
   if (b > 1024) b = 1024;
   return (int)(b < 1 ? 1 : b);
 }
 
 hipError_t launch_multidot(const double* V, int64_t ldv, int J, const double* w, double* partial,
                            int nblocks, int64_t n, hipStream_t st) {
+  if (J <= 0) return hipSuccess;
   const int64_t chunk = (n + nblocks - 1) / nblocks;
-  k_multidot<<<nblocks, MD_BS, 0, st>>>(V, ldv, J, w, partial, n, chunk);
+  k_multidot<<<dim3(nblocks, (J + MD_TILE - 1) / MD_TILE), MD_BS, 0, st>>>(V, ldv, J, w, partial, n,
+                                                                           chunk);
   return hipGetLastError();
 }
 
 // One block per output j: strided partial sums over the blocks' partials in
-// a fixed assignment, then a fixed-order tree in LDS.
+// a fixed assignment, then the fixed-order block sum.
 __global__ void __launch_bounds__(256)
 k_reduce_partials(const double* __restrict__ partial, int nb, int J, double* __restrict__ out) {
-  __shared__ double red[256];
+  __shared__ double red[4];
   const int j = blockIdx.x, t = threadIdx.x;
-  double s = 0.0;
-  for (int b = t; b < nb; b += 256) s += partial[(int64_t)b * J + j];
-  red[t] = s;
-  __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if (t < k) red[t] += red[t + k];
-    __syncthreads();
-  }
-  if (t == 0) out[j] = red[0];
+  double x[1] = {0.0};
+  for (int b = t; b < nb; b += 256) x[0] += partial[(int64_t)b * J + j];
+  const double sum = block_sum_tile<1>(x, red, t);
+  if (t == 0) out[j] = sum;
 }
 
 hipError_t launch_reduce_partials(const double* partial, int nblocks, int J, double* out, hipStream_t st) {
@@ -152,7 +161,7 @@ __global__ void __launch_bounds__(MD_BS)
 k_axpy_dot(const double* __restrict__ V, int64_t ldv, int J, const double* __restrict__ h,
            double sign, double* __restrict__ w, int Jd, int self, double* __restrict__ partial,
            int64_t n, int64_t chunk) {
-  __shared__ double red[MD_TILE][MD_BS];
+  __shared__ double red[4 * MD_TILE];
   __shared__ double sh[JT];
   const int b = blockIdx.x, t = threadIdx.x;
   const int Jo = Jd + (self ? 1 : 0);
@@ -179,29 +188,21 @@ k_axpy_dot(const double* __restrict__ V, int64_t ldv, int J, const double* __res
     d[JT] = fma(wn, wn, d[JT]);
   }
   for (int j0 = 0; j0 < Jo; j0 += MD_TILE) {
+    double x[MD_TILE];
 #pragma unroll
     for (int k = 0; k < MD_TILE; ++k) {
       const int o = j0 + k;
-      double x = 0.0;
+      x[k] = 0.0;
       if (self && o == Jd) {
-        x = d[JT];
+        x[k] = d[JT];
       } else {
 #pragma unroll
         for (int j = 0; j < JT; ++j)
-          if (j == o) x = d[j];
+          if (j == o) x[k] = d[j];
       }
-      red[k][t] = x;
     }
-    __syncthreads();
-    for (int s = MD_BS / 2; s > 0; s >>= 1) {
-      if (t < s) {
-#pragma unroll
-        for (int k = 0; k < MD_TILE; ++k) red[k][t] += red[k][t + s];
-      }
-      __syncthreads();
-    }
-    if (t < MD_TILE && j0 + t < Jo) partial[(int64_t)b * Jo + j0 + t] = red[t][0];
-    __syncthreads();
+    const double sum = block_sum_tile<MD_TILE>(x, red, t);
+    if (t < MD_TILE && j0 + t < Jo) partial[(int64_t)b * Jo + j0 + t] = sum;
   }
 }
 
@@ -228,7 +229,7 @@ template <int JT>
 __global__ void __launch_bounds__(MD_BS)
 k_gs_reduce(const double* __restrict__ Q, int64_t ldq, int J, const double* __restrict__ u,
             const double* __restrict__ w, double* __restrict__ partial, int64_t n, int64_t chunk) {
-  __shared__ double red[MD_TILE][MD_BS];
+  __shared__ double red[4 * MD_TILE];
   const int b = blockIdx.x, t = threadIdx.x;
   const int Jo = 2 * J + 3;
   const int64_t lo = (int64_t)b * chunk;
@@ -249,30 +250,22 @@ k_gs_reduce(const double* __restrict__ Q, int64_t ldq, int J, const double* __re
     ww = fma(wi, wi, ww);
   }
   for (int j0 = 0; j0 < Jo; j0 += MD_TILE) {
+    double x[MD_TILE];
 #pragma unroll
     for (int k = 0; k < MD_TILE; ++k) {
       const int o = j0 + k;
-      double x = 0.0;
+      x[k] = 0.0;
 #pragma unroll
       for (int j = 0; j < JT; ++j) {
-        if (o == j && j < J) x = da[j];
-        if (o == J + j && j < J) x = db[j];
+        if (o == j && j < J) x[k] = da[j];
+        if (o == J + j && j < J) x[k] = db[j];
       }
-      if (o == 2 * J) x = uu;
-      if (o == 2 * J + 1) x = uw;
-      if (o == 2 * J + 2) x = ww;
-      red[k][t] = x;
+      if (o == 2 * J) x[k] = uu;
+      if (o == 2 * J + 1) x[k] = uw;
+      if (o == 2 * J + 2) x[k] = ww;
     }
-    __syncthreads();
-    for (int s = MD_BS / 2; s > 0; s >>= 1) {
-      if (t < s) {
-#pragma unroll
-        for (int k = 0; k < MD_TILE; ++k) red[k][t] += red[k][t + s];
-      }
-      __syncthreads();
-    }
-    if (t < MD_TILE && j0 + t < Jo) partial[(int64_t)b * Jo + j0 + t] = red[t][0];
-    __syncthreads();
+    const double sum = block_sum_tile<MD_TILE>(x, red, t);
+    if (t < MD_TILE && j0 + t < Jo) partial[(int64_t)b * Jo + j0 + t] = sum;
   }
 }
 
