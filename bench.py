@@ -225,6 +225,79 @@ def summarize_pmc(fetch_csv, write_csv, command):
     print("\n".join(lines))
 
 
+def batched(args):
+    """Batched solves: N inflow waveforms of uneven harmonic count on the
+    Womersley pipe (R = 1, L = 4, 6,144 tets), K drawn from {3, 5, 7, 11},
+    waveform Q(t)/Qbar = 1 + sum_k a k^-2 cos(k omega t + phi_k) with
+    a ~ U[0.1, 1] and seeded phases, each solved to 1e-8 from the initial
+    guess.  Runs them one at a time, then all through tsgls_solve_batch, and
+    prints one JSON line with throughput and per-solve latency percentiles of
+    both.  (On the 200k-tet junction the Jacobi-preconditioned GMRES needs
+    thousands of products per Newton step, so solves to 1e-8 there are not a
+    batch-latency workload.)"""
+    import numpy as np
+    import torch
+    import paper_2311_09465_amd as T
+    from workloads import womersley_problem, initial_guess
+    from workloads.problems import inlet_waveforms
+    from workloads.meshgen import pipe
+    N = args.batched
+    rng = np.random.default_rng(2311)
+    mesh = pipe(4, 16)
+    Ks = rng.choice([3, 5, 7, 11], size=N)
+    amps = rng.uniform(0.1, 1.0, size=N)
+    probs = [womersley_problem(K=int(Ks[i]), mesh=mesh,
+                               waveform=inlet_waveforms(int(Ks[i]), 1000 + i, amps[i], n_inlets=1)[0])
+             for i in range(N)]
+    solvers = [T.Solver.from_problem(p, stream=torch.cuda.Stream()) for p in probs]
+    opts = dict(rtol=1e-8, lin_rtol=0.05, restart=30, max_newton=40)
+    # one short solve per K first (first-use setup of each kernel family)
+    for K in sorted(set(int(k) for k in Ks)):
+        i = int(np.argmax(Ks == K))
+        y = torch.from_numpy(initial_guess(probs[i])).cuda()
+        torch.cuda.synchronize()
+        solvers[i].solve(y, **dict(opts, max_newton=1))
+    torch.cuda.synchronize()
+
+    def pct(x, q):
+        return float(np.percentile(np.asarray(x), q))
+
+    seq_lat, seq_ok, seq_it = [], 0, []
+    t0 = time.perf_counter()
+    for s, p in zip(solvers, probs):
+        y = torch.from_numpy(initial_guess(p)).cuda()
+        torch.cuda.synchronize()
+        st = s.solve(y, **opts)
+        seq_lat.append(time.perf_counter() - t0)
+        seq_ok += st["status"] == 0
+        seq_it.append(st["newton_iters"])
+    seq_wall = time.perf_counter() - t0
+    seq_own = np.diff([0.0] + seq_lat)
+    ys = [torch.from_numpy(initial_guess(p)).cuda() for p in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, stats, fin = T.solve_batch(solvers, ys, max_concurrent=args.batch_concurrency, **opts)
+    bat_wall = time.perf_counter() - t0
+    out = {
+        "metric": "batched solves to 1e-8: throughput and per-solve latency",
+        "n_solves": N, "n_gpus": 1, "data": "synthetic (seeded pipe inflow waveforms)",
+        "config": dict(workload="womersley_6k_batched", n_tets=mesh.n_tets,
+                       n_nodes=mesh.n_nodes, K_choices=[3, 5, 7, 11],
+                       K_counts={int(k): int((Ks == k).sum()) for k in sorted(set(Ks.tolist()))},
+                       restart=30, lin_rtol=0.05, concurrency=args.batch_concurrency),
+        "sequential": dict(wall_s=round(seq_wall, 3), solves_per_s=round(N / seq_wall, 3),
+                           own_p50_s=round(pct(seq_own, 50), 4), own_p99_s=round(pct(seq_own, 99), 4),
+                           converged=int(seq_ok), newton_iters_mean=round(float(np.mean(seq_it)), 2)),
+        "batched": dict(wall_s=round(bat_wall, 3), solves_per_s=round(N / bat_wall, 3),
+                        latency_p50_s=round(pct(fin, 50), 4), latency_p99_s=round(pct(fin, 99), 4),
+                        own_p50_s=round(pct([s_["seconds"] for s_ in stats], 50), 4),
+                        own_p99_s=round(pct([s_["seconds"] for s_ in stats], 99), 4),
+                        converged=int(sum(s_["status"] == 0 for s_ in stats)), status=rc),
+        "throughput_gain": round(seq_wall / bat_wall, 3),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +312,9 @@ def main():
                     help="counter-collection workload (linearize, 3 tangent products, a 512 MiB copy)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary under profiles/ from two rocprofv3 --pmc CSVs")
+    ap.add_argument("--batched", type=int, default=0, metavar="N",
+                    help="batched-solve measurement: N inflow waveforms on the 6k-tet pipe")
+    ap.add_argument("--batch-concurrency", type=int, default=8)
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc,
@@ -259,6 +335,9 @@ def main():
     torch.cuda.set_device(0)
     if args.probe:
         probe(args)
+        return
+    if args.batched:
+        batched(args)
         return
     prob, cfg = _workload(args.workload)
     s = T.Solver.from_problem(prob)

@@ -178,6 +178,23 @@ int tsgls_get_tau(tsgls_ctx* ctx, double* tau_out);
 int tsgls_solve(tsgls_ctx* ctx, double* y, const tsgls_solve_opts* opts,
                 tsgls_solve_stats* stats);
 
+/* Batched solves: nb independent problems, ctxs[i] (distinct contexts, each
+ * with its own stream for the solves to overlap on the device; any harmonic
+ * count K) from the device states ys[i] (in: initial guess, out: solution),
+ * all with the options o.  Up to max_concurrent (<= 0: 8) host threads each
+ * drive one tsgls_solve at a time; every solve's arithmetic and its result
+ * are those of tsgls_solve on the same context (bitwise: no kernel uses
+ * atomics).  stats (host [nb], may be NULL) receives each solve's statistics
+ * (seconds = the solve's own wall time); finish_s (host [nb], may be NULL)
+ * the time from this call's start to the end of solve i, i.e. its latency
+ * in the batch.  Returns the first negative code of a failed solve (the
+ * other solves still run to the end), else TSGLS_NOT_CONVERGED if any solve
+ * did not reach rtol, else TSGLS_OK.  TSGLS_EINVAL for a null or repeated
+ * context or a null state. */
+int tsgls_solve_batch(tsgls_ctx* const* ctxs, double* const* ys, int nb,
+                      const tsgls_solve_opts* o, tsgls_solve_stats* stats,
+                      double* finish_s, int max_concurrent);
+
 /* Introspection: element launches per operator application (1), element and
  * node counts, bytes held on device. */
 int tsgls_info(const tsgls_ctx* ctx, int64_t* n_colors, int64_t* n_tets,

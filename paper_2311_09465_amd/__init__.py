@@ -66,6 +66,7 @@ def lib():
         L.tsgls_jacobi_diag.argtypes = [P, P, D]
         L.tsgls_get_tau.argtypes = [P, P]
         L.tsgls_solve.argtypes = [P, P, C.POINTER(SolveOpts), C.POINTER(SolveStats)]
+        L.tsgls_solve_batch.argtypes = [P, P, I32, C.POINTER(SolveOpts), P, P, I32]
         L.tsgls_info.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]
         L.tsgls_profile.argtypes = [P, I32]
         L.tsgls_profile_get.argtypes = [P, I32, C.POINTER(I64), C.POINTER(D)]
@@ -90,6 +91,42 @@ def _ptr(t):
 def _host(a, dtype):
     a = np.ascontiguousarray(a, dtype=dtype)
     return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _opts(rtol, lin_rtol, restart, max_newton, max_matvec, jacobian, dt_pseudo, verbose,
+          tangent_precision):
+    return SolveOpts(rtol, lin_rtol, restart, max_newton, max_matvec, JAC[jacobian],
+                     float(dt_pseudo or 0.0), int(verbose), PREC[tangent_precision])
+
+
+def _stats_dict(rc, st):
+    return dict(status=rc, newton_iters=st.newton_iters, matvecs=st.matvecs,
+                rel_residual=st.rel_residual, r0_norm=st.r0_norm, seconds=st.seconds,
+                history=list(st.history[:min(64, st.newton_iters)]))
+
+
+def solve_batch(solvers, ys, rtol=1e-8, lin_rtol=0.05, restart=100, max_newton=50,
+                max_matvec=10000, jacobian="picard", dt_pseudo=0.0, verbose=False,
+                tangent_precision="f64", max_concurrent=8):
+    """tsgls_solve_batch: solve every (solver, y) pair with the same options,
+    up to max_concurrent at a time.  Returns (status, per-solve stats dicts,
+    per-solve finish times in seconds from the call's start)."""
+    nb = len(solvers)
+    if nb != len(ys):
+        raise TsglsError("solve_batch: one state per solver")
+    hs = (C.c_void_p * max(nb, 1))(*[s._h.value for s in solvers])
+    yp = (C.c_void_p * max(nb, 1))(*[s._vec(y, "y").value for s, y in zip(solvers, ys)])
+    o = _opts(rtol, lin_rtol, restart, max_newton, max_matvec, jacobian, dt_pseudo, verbose,
+              tangent_precision)
+    st = (SolveStats * max(nb, 1))()
+    fin = (C.c_double * max(nb, 1))()
+    rc = lib().tsgls_solve_batch(hs, yp, nb, C.byref(o), C.cast(st, C.c_void_p),
+                                 C.cast(fin, C.c_void_p), int(max_concurrent))
+    if rc < 0:
+        msgs = [lib().tsgls_last_error(s._h).decode() for s in solvers]
+        raise TsglsError(f"solve_batch: {ERRORS.get(rc, rc)}: " + "; ".join(m for m in msgs if m))
+    return rc, [_stats_dict(0 if st[i].status == 0 else 1, st[i]) for i in range(nb)], \
+        [fin[i] for i in range(nb)]
 
 
 class Solver:
@@ -177,13 +214,11 @@ class Solver:
 
     def solve(self, y, rtol=1e-8, lin_rtol=0.05, restart=100, max_newton=50, max_matvec=10000,
               jacobian="picard", dt_pseudo=0.0, verbose=False, tangent_precision="f64"):
-        o = SolveOpts(rtol, lin_rtol, restart, max_newton, max_matvec, JAC[jacobian],
-                      float(dt_pseudo or 0.0), int(verbose), PREC[tangent_precision])
+        o = _opts(rtol, lin_rtol, restart, max_newton, max_matvec, jacobian, dt_pseudo, verbose,
+                  tangent_precision)
         st = SolveStats()
         rc = self._check(lib().tsgls_solve(self._h, self._vec(y, "y"), C.byref(o), C.byref(st)), "solve")
-        return dict(status=rc, newton_iters=st.newton_iters, matvecs=st.matvecs,
-                    rel_residual=st.rel_residual, r0_norm=st.r0_norm, seconds=st.seconds,
-                    history=list(st.history[:min(64, st.newton_iters)]))
+        return _stats_dict(rc, st)
 
     PROF = {"elem_tangent": 0, "elem_residual": 1, "tau": 2, "diag": 3, "face": 4, "ortho": 5,
             "gather": 6}

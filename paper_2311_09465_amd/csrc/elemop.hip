@@ -22,6 +22,8 @@
 //   assembly   lane (f=g, p), reg b: Galerkin, viscous, pressure, LS and
 //              PSPG terms; element buffer rows [node][field][position] in
 //              the slot scaling (the node gather maps positions to slots).
+#include <atomic>
+
 #include "common.cuh"
 #include "internal.h"
 
@@ -586,7 +588,11 @@ struct OpArgs {
 template <int K, int MD, typename T>
 static hipError_t op_launch(const DevView& v, const OpArgs<T>& a, double shift, int64_t begin,
                             int64_t end, hipStream_t st) {
-  static int max_blocks = 0;   // resident blocks on the whole device, multiple of 8
+  // resident blocks on the whole device, multiple of 8 (computed once; the
+  // library drives one device model, and concurrent first calls store the
+  // same value)
+  static std::atomic<int> max_blocks_cache{0};
+  int max_blocks = max_blocks_cache.load(std::memory_order_relaxed);
   if (max_blocks == 0) {
     int dev = 0, ncu = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -595,6 +601,7 @@ static hipError_t op_launch(const DevView& v, const OpArgs<T>& a, double shift, 
     if (e != hipSuccess) return e;
     const int mb = ncu * (per_cu > 0 ? per_cu : 1);
     max_blocks = mb < 8 ? 8 : mb / 8 * 8;
+    max_blocks_cache.store(max_blocks, std::memory_order_relaxed);
   }
   const int64_t cnt = end - begin;
   int64_t nb = (cnt + 7) / 8 * 8;

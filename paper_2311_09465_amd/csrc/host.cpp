@@ -3,13 +3,16 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <set>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/tsgls.h"
@@ -20,6 +23,7 @@ using namespace tsgls;
 struct tsgls_ctx {
   tsgls_params p{};
   hipStream_t st = nullptr;
+  int dev = 0;                  // HIP device current at tsgls_create
   int K = 0, n = 1, S = 2, M = 1, P = 1;
   int64_t nn = 0, E = 0, nf = 0;
   std::vector<int32_t> perm;    // processing position -> input element index (Morton order)
@@ -653,6 +657,7 @@ int tsgls_create(const double* xyz, int64_t n_nodes, const int32_t* tets, int64_
   *out = c;
   c->p = *params;
   c->st = (hipStream_t)hip_stream;
+  if (hipGetDevice(&c->dev) != hipSuccess) return fail(c, TSGLS_EHIP, "hipGetDevice failed");
   const int K = params->K;
   if (!(params->rho > 0) || !(params->mu > 0) || !(params->C_I >= 0) || !(params->backflow_beta >= 0) ||
       !(params->backflow_beta <= 1) || !std::isfinite(params->omega))
@@ -974,6 +979,53 @@ int tsgls_solve(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_
   st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (stats) *stats = st;
   return status;
+}
+
+int tsgls_solve_batch(tsgls_ctx* const* ctxs, double* const* ys, int nb, const tsgls_solve_opts* o,
+                      tsgls_solve_stats* stats, double* finish_s, int max_concurrent) {
+  if (nb < 0) return TSGLS_EINVAL;
+  if (nb == 0) return TSGLS_OK;
+  if (!ctxs || !ys || !o) return TSGLS_EINVAL;
+  {
+    std::set<const tsgls_ctx*> seen;
+    for (int i = 0; i < nb; ++i) {
+      if (!ctxs[i]) return TSGLS_EINVAL;
+      if (!ys[i] || !seen.insert(ctxs[i]).second) return fail(ctxs[i], TSGLS_EINVAL, "null state or repeated context in batch");
+    }
+  }
+  const int T = std::max(1, std::min(nb, max_concurrent > 0 ? max_concurrent : 8));
+  std::vector<int> rc(nb, TSGLS_OK);
+  std::atomic<int> next{0};
+  const auto t0 = std::chrono::steady_clock::now();
+  auto worker = [&]() {
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= nb) break;
+      tsgls_solve_stats st{};
+      if (hipSetDevice(ctxs[i]->dev) != hipSuccess) {
+        rc[i] = fail(ctxs[i], TSGLS_EHIP, "hipSetDevice failed");
+      } else {
+        rc[i] = tsgls_solve(ctxs[i], ys[i], o, &st);
+      }
+      if (stats) stats[i] = st;
+      if (finish_s)
+        finish_s[i] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+  };
+  std::vector<std::thread> pool;
+  try {
+    for (int t = 1; t < T; ++t) pool.emplace_back(worker);
+  } catch (...) {
+    // fewer workers (down to this thread alone) if threads cannot be created
+  }
+  worker();
+  for (auto& th : pool) th.join();
+  int out = TSGLS_OK;
+  for (int i = 0; i < nb; ++i) {
+    if (rc[i] < 0) return rc[i];
+    if (rc[i] == TSGLS_NOT_CONVERGED) out = TSGLS_NOT_CONVERGED;
+  }
+  return out;
 }
 
 int tsgls_info(const tsgls_ctx* c, int64_t* n_colors, int64_t* n_tets, int64_t* n_nodes,

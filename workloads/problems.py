@@ -99,15 +99,21 @@ def womersley_exact_modes(xyz, K, R, L, rho, mu, omega, Qmodes):
 
 
 def womersley_problem(n_rings=4, n_layers=16, K=3, Re=100.0, Wo=5.0, amp=0.5,
-                      rho=1.0, R=1.0, L=4.0) -> Problem:
-    """Pipe, inlet flow Q(t) = Qbar (1 + amp sin(omega t)), mean velocity 1."""
-    mesh = pipe(n_rings, n_layers, R, L)
+                      rho=1.0, R=1.0, L=4.0, waveform=None, mesh: Mesh = None) -> Problem:
+    """Pipe, inlet flow Q(t) = Qbar (1 + amp sin(omega t)), mean velocity 1.
+
+    waveform, if given, replaces the sinusoid: complex modes k = 0..K of
+    Q(t)/Qbar (waveform[0] = 1), e.g. one row of inlet_waveforms."""
+    if mesh is None:
+        mesh = pipe(n_rings, n_layers, R, L)
     D, U = 2 * R, 1.0
     mu = rho * U * D / Re
     omega = (Wo / D) ** 2 * mu / rho
     Q = np.zeros(K + 1, dtype=complex)
     Q[0] = np.pi * R * R * U
-    if K >= 1:
+    if waveform is not None:
+        Q[1:] = Q[0] * np.asarray(waveform, dtype=complex)[1:K + 1]
+    elif K >= 1:
         Q[1] = -1j * amp * Q[0] / 2
     exact = womersley_exact_modes(mesh.xyz, K, R, L, rho, mu, omega, Q)
     inlet = _nodes_of(mesh.faces["inlet"])
