@@ -195,6 +195,60 @@ int tsgls_solve_batch(tsgls_ctx* const* ctxs, double* const* ys, int nb,
                       const tsgls_solve_opts* o, tsgls_solve_stats* stats,
                       double* finish_s, int max_concurrent);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start.  A reduced basis of modal solutions and a fully
+ * connected tanh network mapping inflow parameters to reduced-basis
+ * coefficients; Newton-GMRES started from its prediction stays the solver
+ * and the judge of the result.  Not part of the paper's method: the
+ * network's training data are solutions of the method itself.
+ *
+ * Reduced basis (all arrays device FP64, vectors of length D, row-major):
+ * tsgls_rb_greedy picks, r times, the snapshot of Y [N][D] (N <= 1024)
+ * worst represented by the basis so far (largest |y - mean - P(y - mean)|),
+ * orthonormalizes it against the basis (classical Gram-Schmidt, two passes)
+ * and stores it in Phi [r][D]; picked (host [r]) receives the snapshot
+ * indices.  Returns the number of basis vectors built (< r when the
+ * snapshots span fewer directions) or a negative error code.  Allocates its
+ * workspace (N*D doubles) on the device.  tsgls_rb_project: coef [N][r] =
+ * Phi (Y_i - mean).  tsgls_rb_expand: y = mean + Phi^T coef (coef device
+ * [r]).  All run on hip_stream. */
+int tsgls_rb_greedy(const double* Y, int64_t N, int64_t D, const double* mean, int r,
+                    double* Phi, int32_t* picked, void* hip_stream);
+int tsgls_rb_project(const double* Phi, int r, int64_t D, const double* Y, int64_t N,
+                     const double* mean, double* coef, void* hip_stream);
+int tsgls_rb_expand(const double* Phi, int r, int64_t D, const double* coef,
+                    const double* mean, double* y, void* hip_stream);
+
+/* Network: n_in -> n_hidden layers of width (tanh) -> n_out (linear).
+ * Weights W_l [d_{l+1}][d_l] and biases b_l, l = 0..n_hidden, stored as one
+ * FP32 parameter vector in that order (W_0, b_0, W_1, b_1, ...); initial W
+ * uniform in +-1/sqrt(d_l) from splitmix64(seed), b = 0.  precision
+ * TSGLS_MLP_BF16: products on bf16 MFMA with FP32 accumulation (operands
+ * rounded from the FP32 master weights and activations); TSGLS_MLP_F32:
+ * FP32 MFMA (for checking).  x [B][n_in], y and targets [B][n_out] are
+ * device FP32 arrays.  tsgls_mlp_gradient evaluates the loss
+ * mean_{b,j} (y - t)^2 and its gradient with respect to the parameters
+ * (kept on the device; loss to host if not NULL); tsgls_mlp_adam_step
+ * applies one bias-corrected Adam step with that gradient.
+ * tsgls_mlp_get_params copies parameters and/or the last gradient to host
+ * arrays of tsgls_mlp_num_params floats.  Errors: TSGLS_EINVAL for bad
+ * sizes or pointers, TSGLS_EHIP, TSGLS_ENOMEM; message in
+ * tsgls_mlp_last_error. */
+#define TSGLS_MLP_BF16 0
+#define TSGLS_MLP_F32 1
+typedef struct tsgls_mlp tsgls_mlp;
+int tsgls_mlp_create(int n_in, int width, int n_hidden, int n_out, int precision,
+                     uint64_t seed, void* hip_stream, tsgls_mlp** out);
+int tsgls_mlp_num_params(const tsgls_mlp* m, int64_t* count);
+int tsgls_mlp_get_params(tsgls_mlp* m, float* params_out, float* grad_out);
+int tsgls_mlp_set_params(tsgls_mlp* m, const float* params_in);
+int tsgls_mlp_forward(tsgls_mlp* m, const float* x, int B, float* y);
+int tsgls_mlp_gradient(tsgls_mlp* m, const float* x, const float* targets, int B,
+                       float* loss);
+int tsgls_mlp_adam_step(tsgls_mlp* m, float lr, float beta1, float beta2, float eps);
+const char* tsgls_mlp_last_error(const tsgls_mlp* m);
+void tsgls_mlp_destroy(tsgls_mlp* m);
+
 /* Introspection: element launches per operator application (1), element and
  * node counts, bytes held on device. */
 int tsgls_info(const tsgls_ctx* ctx, int64_t* n_colors, int64_t* n_tets,

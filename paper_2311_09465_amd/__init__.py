@@ -70,6 +70,20 @@ def lib():
         L.tsgls_info.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]
         L.tsgls_profile.argtypes = [P, I32]
         L.tsgls_profile_get.argtypes = [P, I32, C.POINTER(I64), C.POINTER(D)]
+        L.tsgls_rb_greedy.argtypes = [P, I64, I64, P, I32, P, P, P]
+        L.tsgls_rb_project.argtypes = [P, I32, I64, P, I64, P, P, P]
+        L.tsgls_rb_expand.argtypes = [P, I32, I64, P, P, P, P]
+        L.tsgls_mlp_create.argtypes = [I32, I32, I32, I32, I32, C.c_uint64, P, C.POINTER(P)]
+        L.tsgls_mlp_num_params.argtypes = [P, C.POINTER(I64)]
+        L.tsgls_mlp_get_params.argtypes = [P, P, P]
+        L.tsgls_mlp_set_params.argtypes = [P, P]
+        L.tsgls_mlp_forward.argtypes = [P, P, I32, P]
+        L.tsgls_mlp_gradient.argtypes = [P, P, P, I32, C.POINTER(C.c_float)]
+        L.tsgls_mlp_adam_step.argtypes = [P, C.c_float, C.c_float, C.c_float, C.c_float]
+        L.tsgls_mlp_last_error.argtypes = [P]
+        L.tsgls_mlp_last_error.restype = C.c_char_p
+        L.tsgls_mlp_destroy.argtypes = [P]
+        L.tsgls_mlp_destroy.restype = None
         L.tsgls_last_error.argtypes = [P]
         L.tsgls_last_error.restype = C.c_char_p
         L.tsgls_destroy.argtypes = [P]
@@ -247,3 +261,134 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- warm start
+def _dev(t, dtype, name, ndim=None):
+    import torch
+    want = {"f64": torch.float64, "f32": torch.float32}[dtype]
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == want and t.is_contiguous()
+            and (ndim is None or t.dim() == ndim)):
+        raise TsglsError(f"{name} must be a contiguous {want} CUDA tensor"
+                         + (f" with {ndim} dimensions" if ndim else ""))
+    return _ptr(t)
+
+
+def _cur_stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def rb_greedy(Y, mean, r, stream=None):
+    """tsgls_rb_greedy on snapshot rows Y [N][D] (float64 CUDA); returns the
+    orthonormal basis rows Phi [k][D] (k <= r) and the picked snapshot
+    indices."""
+    import torch
+    N, D = Y.shape
+    Phi = torch.zeros((r, D), dtype=torch.float64, device=Y.device)
+    picked = (C.c_int32 * r)()
+    k = lib().tsgls_rb_greedy(_dev(Y, "f64", "Y", 2), N, D, _dev(mean, "f64", "mean"), int(r),
+                              _ptr(Phi), C.cast(picked, C.c_void_p), _cur_stream(stream))
+    if k < 0:
+        raise TsglsError(f"rb_greedy: {ERRORS.get(k, k)}")
+    return Phi[:k].contiguous(), [picked[i] for i in range(k)]
+
+
+def rb_project(Phi, Y, mean, stream=None):
+    """coef [N][r] = Phi (Y_i - mean) (tsgls_rb_project)."""
+    import torch
+    r, D = Phi.shape
+    N = Y.shape[0]
+    coef = torch.zeros((N, r), dtype=torch.float64, device=Y.device)
+    rc = lib().tsgls_rb_project(_dev(Phi, "f64", "Phi", 2), r, D, _dev(Y, "f64", "Y"), N,
+                                _dev(mean, "f64", "mean"), _ptr(coef), _cur_stream(stream))
+    if rc < 0:
+        raise TsglsError(f"rb_project: {ERRORS.get(rc, rc)}")
+    return coef
+
+
+def rb_expand(Phi, coef, mean, out, stream=None):
+    """out = mean + Phi^T coef (tsgls_rb_expand); coef float64 CUDA [r]."""
+    r, D = Phi.shape
+    rc = lib().tsgls_rb_expand(_dev(Phi, "f64", "Phi", 2), r, D, _dev(coef, "f64", "coef"),
+                               _dev(mean, "f64", "mean"), _dev(out, "f64", "out"),
+                               _cur_stream(stream))
+    if rc < 0:
+        raise TsglsError(f"rb_expand: {ERRORS.get(rc, rc)}")
+
+
+class MLP:
+    """tsgls_mlp_*: tanh network n_in -> n_hidden x width -> n_out; bf16 MFMA
+    products with FP32 master weights (precision "bf16") or FP32 ("f32")."""
+
+    def __init__(self, n_in, width, n_hidden, n_out, precision="bf16", seed=0, stream=None):
+        self.dims = [int(n_in)] + [int(width)] * int(n_hidden) + [int(n_out)]
+        self._stream = stream
+        h = C.c_void_p()
+        rc = lib().tsgls_mlp_create(int(n_in), int(width), int(n_hidden), int(n_out),
+                                    {"bf16": 0, "f32": 1}[precision], int(seed),
+                                    _cur_stream(stream), C.byref(h))
+        self._h = h
+        if rc != TSGLS_OK:
+            if h.value:
+                lib().tsgls_mlp_destroy(h)
+            self._h = C.c_void_p()
+            raise TsglsError(f"tsgls_mlp_create: {ERRORS.get(rc, rc)}")
+        n = C.c_int64()
+        lib().tsgls_mlp_num_params(h, C.byref(n))
+        self.n_params = n.value
+
+    def _check(self, rc, what):
+        if rc < 0:
+            raise TsglsError(f"{what}: {ERRORS.get(rc, rc)}: {lib().tsgls_mlp_last_error(self._h).decode()}")
+
+    def get_params(self):
+        out = np.empty(self.n_params, dtype=np.float32)
+        self._check(lib().tsgls_mlp_get_params(self._h, out.ctypes.data_as(C.c_void_p), None),
+                    "get_params")
+        return out
+
+    def get_grad(self):
+        out = np.empty(self.n_params, dtype=np.float32)
+        self._check(lib().tsgls_mlp_get_params(self._h, None, out.ctypes.data_as(C.c_void_p)),
+                    "get_grad")
+        return out
+
+    def set_params(self, theta):
+        a, p = _host(theta, np.float32)
+        if a.size != self.n_params:
+            raise TsglsError("set_params: wrong parameter count")
+        self._check(lib().tsgls_mlp_set_params(self._h, p), "set_params")
+
+    def _shapes(self, x, y, what):
+        if x.dim() != 2 or x.shape[1] != self.dims[0] or tuple(y.shape) != (x.shape[0], self.dims[-1]):
+            raise TsglsError(f"{what}: x must be [B][{self.dims[0]}] and the output [B][{self.dims[-1]}]")
+
+    def forward(self, x, y):
+        self._shapes(x, y, "forward")
+        self._check(lib().tsgls_mlp_forward(self._h, _dev(x, "f32", "x", 2), int(x.shape[0]),
+                                            _dev(y, "f32", "y", 2)), "forward")
+
+    def gradient(self, x, t):
+        self._shapes(x, t, "gradient")
+        loss = C.c_float()
+        self._check(lib().tsgls_mlp_gradient(self._h, _dev(x, "f32", "x", 2), _dev(t, "f32", "t", 2),
+                                             int(x.shape[0]), C.byref(loss)), "gradient")
+        return loss.value
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(lib().tsgls_mlp_adam_step(self._h, float(lr), float(beta1), float(beta2),
+                                              float(eps)), "adam_step")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().tsgls_mlp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -154,4 +154,20 @@ hipError_t launch_multiaxpy_add(const double* V, int64_t ldv, int J, const doubl
                                 double* y, int64_t n, hipStream_t st);
 int multidot_blocks(int64_t n);
 
+// Warm-start network (mlp.hip).  C[i][j] (ldc) = epilogue(sum_k A(i,k) B(k,j))
+// with A(i,k) = A[i*sai + k*sak], B(k,j) = B[k*sbk + j*sbj]; bf16 != 0 rounds
+// the operands to bf16 (FP32 accumulation).  epi 0: + bias (if not null),
+// 1: tanh(. + bias), 2: . * (1 - H[i][j]^2).
+hipError_t launch_mlp_gemm(int bf16, int epi, int M, int N, int Kd, const float* A, int64_t sai,
+                           int64_t sak, const float* B, int64_t sbk, int64_t sbj,
+                           const float* bias, const float* H, float* C, int64_t ldc,
+                           hipStream_t st);
+// dO = 2 (O - T) / cnt, loss[0] = mean (O - T)^2 over cnt entries
+hipError_t launch_mse(const float* O, const float* T, float* dO, float* loss, int64_t cnt,
+                      hipStream_t st);
+// db[j] = sum_b dZ[b][j]
+hipError_t launch_colsum(const float* dZ, int B, int N, float* db, hipStream_t st);
+hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, hipStream_t st);
+
 }  // namespace tsgls

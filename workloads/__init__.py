@@ -9,9 +9,9 @@ from .meshgen import (Mesh, cube_kuhn, pipe, junction, boundary_faces,
                       morton_order_elements)
 from .problems import (Problem, womersley_problem, junction_problem,
                        cube_problem, initial_guess, tiny_problem,
-                       womersley_exact_modes)
+                       womersley_exact_modes, pipe_family, inlet_waveforms)
 
 __all__ = ["Mesh", "cube_kuhn", "pipe", "junction", "boundary_faces",
            "morton_order_elements", "Problem", "womersley_problem",
            "junction_problem", "cube_problem", "initial_guess",
-           "tiny_problem", "womersley_exact_modes"]
+           "tiny_problem", "womersley_exact_modes", "pipe_family", "inlet_waveforms"]

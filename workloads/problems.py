@@ -189,6 +189,27 @@ def junction_problem(h=0.081, K=6, Re=500.0, Wo=10.0, seed=0, amp=0.5,
     return prob
 
 
+# ----------------------------------------------------- pipe problem family
+def pipe_family(n, K=3, seed=0, n_rings=4, n_layers=16, Re_range=(60.0, 140.0),
+                Wo_range=(3.0, 7.0), mesh: Mesh = None):
+    """n pipe problems on one mesh with seeded inflow waveforms
+    1 + sum_k a k^-2 cos(k omega t + phi_k), a ~ U[0.1, 1], and Re, Wo drawn
+    uniformly from the ranges.  Returns (problems, features [n][2K+2]) with
+    features = (Re w_1..w_K, Im w_1..w_K, Re, Wo), w_k the waveform modes."""
+    rng = np.random.default_rng(seed)
+    if mesh is None:
+        mesh = pipe(n_rings, n_layers)
+    probs, feats = [], []
+    for _ in range(n):
+        a = rng.uniform(0.1, 1.0)
+        Re = rng.uniform(*Re_range)
+        Wo = rng.uniform(*Wo_range)
+        wf = inlet_waveforms(K, int(rng.integers(1 << 31)), a, n_inlets=1)[0]
+        probs.append(womersley_problem(K=K, Re=Re, Wo=Wo, waveform=wf, mesh=mesh))
+        feats.append(np.concatenate([wf[1:].real, wf[1:].imag, [Re, Wo]]))
+    return probs, np.asarray(feats)
+
+
 # --------------------------------------------------------------- test cubes
 def cube_problem(n=3, K=2, Re=50.0, Wo=3.0, rho=1.0, seed=0, amp=0.5) -> Problem:
     """Unit cube; inflow at x=0 (parabola-like bump per mode), outflow at x=1
