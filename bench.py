@@ -298,6 +298,88 @@ def batched(args):
     print(json.dumps(out), flush=True)
 
 
+def learned(args):
+    """Learned warm start on the pipe family (6,144 tets, K = 3; inflow
+    waveform amplitude, phases, Re and Wo drawn per member): solves the
+    training members (batched), builds the reduced basis, trains the
+    network, then solves held-out members from the plain initial guess and
+    from the prediction to the same absolute residual (1e-8 of the initial
+    guess's).  Prints one JSON line."""
+    import numpy as np
+    import torch
+    import paper_2311_09465_amd as T
+    from paper_2311_09465_amd.warmstart import WarmStart, fix_dirichlet
+    from workloads import pipe_family, initial_guess
+    ntr, nte, r = args.learned, args.learned_test, args.learned_basis
+    probs, feats = pipe_family(ntr + nte, K=3, seed=11)
+    opts = dict(lin_rtol=0.05, restart=30, max_newton=60)
+    t0 = time.perf_counter()
+    solvers = [T.Solver.from_problem(probs[i], stream=torch.cuda.Stream()) for i in range(ntr)]
+    ys = [torch.from_numpy(initial_guess(probs[i])).cuda() for i in range(ntr)]
+    torch.cuda.synchronize()
+    rc, st, _ = T.solve_batch(solvers, ys, rtol=1e-9, max_concurrent=8, **opts)
+    t_data = time.perf_counter() - t0
+    del solvers
+    Y = torch.stack([y.view(-1) for y in ys]).contiguous()
+    del ys
+    t0 = time.perf_counter()
+    ws = WarmStart.fit(feats[:ntr], Y, r=r, steps=args.learned_steps, lr=1e-3, seed=1,
+                       precision=args.learned_precision)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    rows = []
+    for i in range(ntr, ntr + nte):
+        p = probs[i]
+        s = T.Solver.from_problem(p)
+        y0 = torch.from_numpy(initial_guess(p)).cuda()
+        r_cold = s.solve(y0.clone(), rtol=1.0, max_newton=0)["r0_norm"]
+        yc = y0.clone()
+        sc = s.solve(yc, rtol=1e-8, **opts)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        yp = fix_dirichlet(ws.predict(feats[i:i + 1], [y0])[0], y0, p.dirichlet_nodes)
+        torch.cuda.synchronize()
+        t_pred = time.perf_counter() - a
+        r_warm = s.solve(yp.clone(), rtol=1.0, max_newton=0)["r0_norm"]
+        fallback = not r_warm < r_cold
+        if fallback:
+            yp, r_warm = y0.clone(), r_cold
+        sw = s.solve(yp, rtol=1e-8 * r_cold / r_warm, **opts)
+        # best the basis can do: the converged solution projected on it
+        coef = T.rb_project(ws.Phi, yc.view(1, -1), ws.mean)[0].contiguous()
+        ypr = torch.empty_like(yc)
+        T.rb_expand(ws.Phi, coef, ws.mean, ypr.view(-1))
+        ypr = fix_dirichlet(ypr, y0, p.dirichlet_nodes)
+        r_proj = s.solve(ypr, rtol=1.0, max_newton=0)["r0_norm"]
+        rows.append(dict(cold_it=sc["newton_iters"], warm_it=sw["newton_iters"], cold_s=sc["seconds"],
+                         warm_s=sw["seconds"] + t_pred, ratio=r_warm / r_cold, proj=r_proj / r_cold,
+                         ok=sc["status"] == 0 and sw["status"] == 0, fallback=fallback))
+
+    def col(k):
+        return np.array([row[k] for row in rows], dtype=float)
+
+    out = {
+        "metric": "learned warm start: Newton steps and time to 1e-8 vs the plain initial guess",
+        "n_gpus": 1, "data": "synthetic (seeded pipe inflow waveforms, Re, Wo)",
+        "config": dict(workload="womersley_6k_K3_family", n_tets=probs[0].mesh.n_tets, K=3,
+                       n_train=ntr, n_test=nte, basis=int(ws.Phi.shape[0]), net="8-512x3-r tanh",
+                       precision=("bf16 MFMA, FP32 master weights" if args.learned_precision == "bf16"
+                                  else "FP32 MFMA"), steps=args.learned_steps),
+        "train": dict(data_s=round(t_data, 3), all_converged=rc == 0, fit_s=round(t_fit, 3),
+                      final_loss=ws.train_loss),
+        "cold": dict(newton_mean=round(col("cold_it").mean(), 3), s_mean=round(col("cold_s").mean(), 4),
+                     s_p50=round(float(np.median(col("cold_s"))), 4)),
+        "warm": dict(newton_mean=round(col("warm_it").mean(), 3), s_mean=round(col("warm_s").mean(), 4),
+                     s_p50=round(float(np.median(col("warm_s"))), 4),
+                     residual_ratio_p50=float("%.3e" % np.median(col("ratio"))),
+                     fallbacks=int(col("fallback").sum())),
+        "basis_projection_residual_ratio_p50": float("%.3e" % np.median(col("proj"))),
+        "all_converged": bool(all(row["ok"] for row in rows)),
+        "speedup_time_to_1e8": round(col("cold_s").mean() / col("warm_s").mean(), 3),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -315,6 +397,12 @@ def main():
     ap.add_argument("--batched", type=int, default=0, metavar="N",
                     help="batched-solve measurement: N inflow waveforms on the 6k-tet pipe")
     ap.add_argument("--batch-concurrency", type=int, default=8)
+    ap.add_argument("--learned", type=int, default=0, metavar="N_TRAIN",
+                    help="learned warm-start measurement with N_TRAIN training solves")
+    ap.add_argument("--learned-test", type=int, default=32)
+    ap.add_argument("--learned-basis", type=int, default=64)
+    ap.add_argument("--learned-steps", type=int, default=3000)
+    ap.add_argument("--learned-precision", default="bf16", choices=["bf16", "f32"])
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc,
@@ -338,6 +426,9 @@ def main():
         return
     if args.batched:
         batched(args)
+        return
+    if args.learned:
+        learned(args)
         return
     prob, cfg = _workload(args.workload)
     s = T.Solver.from_problem(prob)

@@ -10,6 +10,9 @@ forms the paper's Toeplitz convolution matrices explicitly, takes tau from a
 LAPACK Hermitian eigendecomposition, and assembles with ``numpy.add.at``.  The
 library works in a real orthonormal basis, uses sampled (dealiased) products
 and its own Jacobi eigensolver, and scatters by element colour.
+
+``oracle.mlp`` is the FP64 reference of the warm-start network (forward,
+backward, Adam) and of the greedy reduced basis.
 """
 from .tsref import (Params, geometry, slots_to_modes, modes_to_slots, toeplitz,
                     tau_from_velocity, residual, linearize, jv, picard_blocks,
