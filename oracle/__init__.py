@@ -9,7 +9,7 @@ Independence by construction: the oracle works with complex modes -K..K,
 forms the paper's Toeplitz convolution matrices explicitly, takes tau from a
 LAPACK Hermitian eigendecomposition, and assembles with ``numpy.add.at``.  The
 library works in a real orthonormal basis, uses sampled (dealiased) products
-and its own Jacobi eigensolver, and scatters by element colour.
+and its own Jacobi eigensolver, and sums element rows per node in a fixed order.
 
 ``oracle.mlp`` is the FP64 reference of the warm-start network (forward,
 backward, Adam) and of the greedy reduced basis.
