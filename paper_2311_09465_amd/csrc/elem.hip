@@ -321,14 +321,40 @@ k_tau(DevView v, const double* __restrict__ Y, double* __restrict__ tau) {
 }
 
 // ------------------------------------------------------- Jacobi diagonal
+// Triple products of the real orthonormal basis, (1/T) int phi_r phi_m phi_a
+// dt, exact from the M = 3K+1 samples (the integrand has degree <= 3K);
+// entries that vanish in exact arithmetic are stored as exact zeros, so the
+// fully unrolled use below keeps only the (at most two per (r, a)) nonzero
+// terms.  A(g) e_a = sum_m g_m T[r][m][a] over output modes r.
+template <int K>
+struct TripleTable {
+  static constexpr int n = 2 * K + 1, M = 3 * K + 1;
+  double t[n][n][n];
+  constexpr TripleTable() : t() {
+    const SampleTable<K> tb{};
+    for (int r = 0; r < n; ++r)
+      for (int m = 0; m < n; ++m)
+        for (int a = 0; a < n; ++a) {
+          double acc = 0.0;
+          for (int s = 0; s < M; ++s) acc += tb.f[r][s] * tb.f[m][s] * tb.f[a][s];
+          acc /= M;
+          t[r][m][a] = (acc < 1e-12 && acc > -1e-12) ? 0.0 : acc;
+        }
+  }
+};
+
 // Diagonal of the Picard tangent (eq. K_mat): per (element, node)
 //  momentum: sum_q w [rho lam A(g)_aa + mu |grad N|^2 + rho b_a^T tau b_a + shift lam^2],
 //            g = grad N_b . u(q,t), b_a = lam Omega e_a + A(g) e_a;
 //  continuity: sum_q (w/rho) |grad N|^2 tau_aa.
+// For K <= 6 the modes of g are formed once per point and A(g) e_a from the
+// triple table (O(n^2) per point instead of O(n^2 M)), with the point's
+// packed tau held in registers; larger K keep the sampled form.
 template <int K>
 __global__ void __launch_bounds__(128)
 k_diag(DevView v, double* __restrict__ d, double shift, int64_t begin, int64_t end) {
   constexpr int n = Dim<K>::n, M = Dim<K>::M, S = Dim<K>::S, P = Dim<K>::P;
+  constexpr bool MODAL = K <= 6;
   const int64_t idx = begin * 4 + xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= end * 4) return;
   const int64_t e = idx >> 2;
@@ -359,6 +385,57 @@ k_diag(DevView v, double* __restrict__ d, double shift, int64_t begin, int64_t e
       gs[s] = gsum;
     }
     const double* tq = v.tau + (e * 4 + q) * P;
+    if constexpr (MODAL) {
+      constexpr TripleTable<K> T3{};
+      double gh[n], tr[P];
+#pragma unroll
+      for (int m = 0; m < n; ++m) {
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < M; ++s) acc = fma(TB.b[m][s], gs[s], acc);
+        gh[m] = acc;
+      }
+#pragma unroll
+      for (int i = 0; i < P; ++i) tr[i] = tq[i];
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        double bcol[n];
+#pragma unroll
+        for (int r = 0; r < n; ++r) {
+          double acc = 0.0;
+#pragma unroll
+          for (int m = 0; m < n; ++m)
+            if (T3.t[r][m][a] != 0.0) acc = fma(T3.t[r][m][a], gh[m], acc);
+          bcol[r] = acc;
+        }
+        const double Aaa = bcol[a];
+        if (a > 0) {   // + lam Omega e_a
+          const int k = (a + 1) >> 1;
+          const double om = k * v.omega * lam;
+          if (a & 1) bcol[a + 1] += om;        // Omega e_{2k-1} = k w e_{2k}
+          else bcol[a - 1] -= om;              // Omega e_{2k} = -k w e_{2k-1}
+        }
+        // b^T tau b = sum_r b_r (tau_rr b_r + 2 sum_{c > r} tau_rc b_c)
+        double quad = 0.0;
+#pragma unroll
+        for (int r = 0; r < n; ++r) {
+          double off = 0.0;
+#pragma unroll
+          for (int c = r + 1; c < n; ++c) {
+            const int pr = mode_pos(r, K), pc = mode_pos(c, K);
+            off = fma(tr[pr < pc ? pk_index(pr, pc, n) : pk_index(pc, pr, n)], bcol[c], off);
+          }
+          const int pp = mode_pos(r, K);
+          quad = fma(bcol[r], fma(2.0, off, tr[pk_index(pp, pp, n)] * bcol[r]), quad);
+        }
+        const int pa = mode_pos(a, K);
+        const double taa = tr[pk_index(pa, pa, n)];
+        dm[a] += wgt * (v.rho * lam * Aaa + v.mu * gn2 + v.rho * quad + shift * lam * lam);
+        dc[a] += (wgt / v.rho) * gn2 * taa;
+        __builtin_amdgcn_sched_barrier(0);   // one mode at a time: bounds the live registers
+      }
+      continue;
+    }
 #pragma unroll 1
     for (int a = 0; a < n; ++a) {
       double bcol[n];
