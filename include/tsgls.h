@@ -105,6 +105,12 @@ typedef struct {
   double dt_pseudo;  /* pseudo-time step; <= 0 disables the mass shift */
   int verbose;       /* 1: one line per Newton step on stderr */
   int tangent_precision;  /* TSGLS_PREC_F64 (0, default) or TSGLS_PREC_F32 */
+  int gmres_graph;   /* 1 (restart <= 32): each GMRES cycle is one HIP graph with
+                        the least-squares update on the device, captured on the
+                        first use of a (restart, tangent, dt_pseudo, precision)
+                        and replayed; one host synchronization per cycle, cycles
+                        always make restart products (whole cycles count against
+                        max_matvec, the first cycle always runs) */
 } tsgls_solve_opts;
 
 typedef struct {

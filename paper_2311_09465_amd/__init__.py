@@ -30,7 +30,8 @@ class Params(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("lin_rtol", C.c_double), ("restart", C.c_int),
                 ("max_newton", C.c_int), ("max_matvec", C.c_int), ("jacobian", C.c_int),
-                ("dt_pseudo", C.c_double), ("verbose", C.c_int), ("tangent_precision", C.c_int)]
+                ("dt_pseudo", C.c_double), ("verbose", C.c_int), ("tangent_precision", C.c_int),
+                ("gmres_graph", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -108,9 +109,10 @@ def _host(a, dtype):
 
 
 def _opts(rtol, lin_rtol, restart, max_newton, max_matvec, jacobian, dt_pseudo, verbose,
-          tangent_precision):
+          tangent_precision, gmres_graph=False):
     return SolveOpts(rtol, lin_rtol, restart, max_newton, max_matvec, JAC[jacobian],
-                     float(dt_pseudo or 0.0), int(verbose), PREC[tangent_precision])
+                     float(dt_pseudo or 0.0), int(verbose), PREC[tangent_precision],
+                     int(bool(gmres_graph)))
 
 
 def _stats_dict(rc, st):
@@ -121,7 +123,7 @@ def _stats_dict(rc, st):
 
 def solve_batch(solvers, ys, rtol=1e-8, lin_rtol=0.05, restart=100, max_newton=50,
                 max_matvec=10000, jacobian="picard", dt_pseudo=0.0, verbose=False,
-                tangent_precision="f64", max_concurrent=8):
+                tangent_precision="f64", max_concurrent=8, gmres_graph=False):
     """tsgls_solve_batch: solve every (solver, y) pair with the same options,
     up to max_concurrent at a time.  Returns (status, per-solve stats dicts,
     per-solve finish times in seconds from the call's start)."""
@@ -131,7 +133,7 @@ def solve_batch(solvers, ys, rtol=1e-8, lin_rtol=0.05, restart=100, max_newton=5
     hs = (C.c_void_p * max(nb, 1))(*[s._h.value for s in solvers])
     yp = (C.c_void_p * max(nb, 1))(*[s._vec(y, "y").value for s, y in zip(solvers, ys)])
     o = _opts(rtol, lin_rtol, restart, max_newton, max_matvec, jacobian, dt_pseudo, verbose,
-              tangent_precision)
+              tangent_precision, gmres_graph)
     st = (SolveStats * max(nb, 1))()
     fin = (C.c_double * max(nb, 1))()
     rc = lib().tsgls_solve_batch(hs, yp, nb, C.byref(o), C.cast(st, C.c_void_p),
@@ -227,9 +229,10 @@ class Solver:
         return out
 
     def solve(self, y, rtol=1e-8, lin_rtol=0.05, restart=100, max_newton=50, max_matvec=10000,
-              jacobian="picard", dt_pseudo=0.0, verbose=False, tangent_precision="f64"):
+              jacobian="picard", dt_pseudo=0.0, verbose=False, tangent_precision="f64",
+              gmres_graph=False):
         o = _opts(rtol, lin_rtol, restart, max_newton, max_matvec, jacobian, dt_pseudo, verbose,
-                  tangent_precision)
+                  tangent_precision, gmres_graph)
         st = SolveStats()
         rc = self._check(lib().tsgls_solve(self._h, self._vec(y, "y"), C.byref(o), C.byref(st)), "solve")
         return _stats_dict(rc, st)

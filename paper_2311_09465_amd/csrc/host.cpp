@@ -64,6 +64,18 @@ struct tsgls_ctx {
   double* partial = nullptr;
   double* dh = nullptr;
   bool linearized = false;
+  // graph-captured GMRES cycles (device-side least squares)
+  hipStream_t gst = nullptr;    // capture / replay stream
+  hipEvent_t gev[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec = nullptr;
+  struct GraphKey {
+    int m = -1, jac = -1, prec = -1;
+    double dt = 0.0;
+    const double* b = nullptr;
+    double* x = nullptr;
+  } gkey;
+  GmDev gm{};
+  double* gmbuf = nullptr;
   // FP32 copies of the linearization for the mixed-precision tangent
   // (allocated on first use; the FP32 modes, samples and element rows reuse
   // the FP64 buffers XP, VT and ebuf, which they fit in half)
@@ -476,7 +488,7 @@ int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, i
       {
         ProfScope ps(c, TSGLS_PROF_ORTHO);
         if (j > 0) HIPCHK(c, hipMemcpyAsync(c->dh + 512, ab.data(), 2 * j * sizeof(double), hipMemcpyHostToDevice, c->st));
-        HIPCHK(c, launch_gs_update(c->V, n, j, c->dh + 512, 1.0 / nu, hj, 1.0 / sigma, u, w, n, c->st));
+        HIPCHK(c, launch_gs_update(c->V, n, j, c->dh + 512, 1.0 / nu, hj, 1.0 / sigma, nullptr, u, w, n, c->st));
       }
       // provisional least-squares residual with column j as it stands
       bool last = (j + 1 == m) || (mv >= maxmv);
@@ -517,6 +529,141 @@ int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, i
     HIPCHK(c, launch_axpy(1.0, c->kt2, x, n, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
     if (done) break;
+  }
+  *mv_out = mv;
+  return TSGLS_OK;
+}
+
+// The same delayed Gram-Schmidt GMRES (m <= 32) with the least-squares
+// update on the device (k_gm_*), so that one cycle -- the residual norm, m
+// Arnoldi steps (tangent product, reduction, update), the final reduction,
+// the triangular solve and the update of x -- is one HIP graph, captured
+// once per (m, tangent, shift, precision) and replayed for every cycle of
+// every Newton step.  The host synchronizes once per cycle to read the
+// convergence flag.  Cycles always run m steps: after convergence the
+// remaining steps see zero update coefficients and leave zero vectors.
+int gmres_graph(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv, int jac,
+                double dt, int prec, int* mv_out) {
+  const int64_t n = ndof(c);
+  const int nb = multidot_blocks(n);
+  if (m > 32) return fail(c, TSGLS_EINVAL, "graph GMRES needs restart <= 32");
+  if (!c->gmbuf) {
+    CHK(dalloc(c, &c->gmbuf, 2400 + 16));
+    const int ld = 33;
+    double* p = c->gmbuf;
+    c->gm.H = p;
+    c->gm.R = p + ld * 32;
+    c->gm.cs = p + 2 * ld * 32;
+    c->gm.sn = c->gm.cs + 32;
+    c->gm.g = c->gm.sn + 32;
+    c->gm.y = c->gm.g + 33;
+    c->gm.ab = c->gm.y + 32;
+    c->gm.sc = c->gm.ab + 64;
+    c->gm.st = reinterpret_cast<int*>(c->gmbuf + 2400);
+  }
+  if (!c->gst) {
+    HIPCHK(c, hipStreamCreateWithFlags(&c->gst, hipStreamNonBlocking));
+    HIPCHK(c, hipEventCreateWithFlags(&c->gev[0], hipEventDisableTiming));
+    HIPCHK(c, hipEventCreateWithFlags(&c->gev[1], hipEventDisableTiming));
+  }
+  c->gm.m = m;
+  if (prec == TSGLS_PREC_F32) CHK(ensure_lin32(c));
+  const tsgls_ctx::GraphKey key{m, jac, prec, dt, b, x};
+  const bool same = c->gexec && c->gkey.m == key.m && c->gkey.jac == key.jac &&
+                    c->gkey.prec == key.prec && c->gkey.dt == key.dt && c->gkey.b == key.b &&
+                    c->gkey.x == key.x;
+  if (!same) {
+    if (c->gexec) {
+      HIPCHK(c, hipGraphExecDestroy(c->gexec));
+      c->gexec = nullptr;
+    }
+    // one eager product first: first-call set-up of the kernels is done outside the capture
+    CHK(jv_impl(c, b, c->kt, jac, dt, c->minv, prec));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    const GmDev d = c->gm;
+    double* red = c->dh;
+    double* bb = c->dh + 2040;
+    auto body = [&]() -> int {
+      double* V0 = c->V;
+      HIPCHK(c, launch_multidot(V0, 0, 1, V0, c->partial, nb, n, c->st));
+      HIPCHK(c, launch_reduce_partials(c->partial, nb, 1, bb, c->st));
+      HIPCHK(c, launch_gm_begin(d, bb, tol, 0, c->st));
+      HIPCHK(c, launch_scal_dev(V0, d.sc + 5, n, c->st));
+      for (int j = 0; j < m; ++j) {
+        double* u = c->V + (int64_t)j * n;
+        double* w = c->V + (int64_t)(j + 1) * n;
+        CHK(jv_impl(c, u, w, jac, dt, c->minv, prec));
+        HIPCHK(c, launch_gs_reduce(c->V, n, j, u, w, c->partial, nb, n, c->st));
+        HIPCHK(c, launch_reduce_partials(c->partial, nb, 2 * j + 3, red, c->st));
+        HIPCHK(c, launch_gm_step(d, j, red, c->st));
+        HIPCHK(c, launch_gs_update(c->V, n, j, d.ab, 0.0, 0.0, 0.0, d.sc, u, w, n, c->st));
+      }
+      double* um = c->V + (int64_t)m * n;
+      HIPCHK(c, launch_gs_reduce(c->V, n, m, um, um, c->partial, nb, n, c->st));
+      HIPCHK(c, launch_reduce_partials(c->partial, nb, 2 * m + 3, red, c->st));
+      HIPCHK(c, launch_gm_final(d, red, c->st));
+      HIPCHK(c, launch_zero(c->kt, n, c->st));
+      HIPCHK(c, launch_multiaxpy_add(c->V, n, m, d.y, c->kt, n, c->st));
+      HIPCHK(c, launch_mul(c->minv, c->kt, c->kt2, n, c->st));
+      HIPCHK(c, launch_axpy(1.0, c->kt2, x, n, c->st));
+      return TSGLS_OK;
+    };
+    hipStream_t orig = c->st;
+    const bool prof = c->prof;
+    c->prof = false;
+    c->st = c->gst;
+    HIPCHK(c, hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal));
+    const int rc = body();
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->gst, &graph);
+    c->st = orig;
+    c->prof = prof;
+    if (rc != TSGLS_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    HIPCHK(c, ec);
+    const hipError_t ei = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHK(c, ei);
+    c->gkey = key;
+  }
+  HIPCHK(c, launch_zero(x, n, c->st));
+  double bnorm;
+  CHK(norm2(c, b, &bnorm));
+  if (!std::isfinite(bnorm)) return fail(c, TSGLS_ENONFINITE, "non-finite right-hand side");
+  if (bnorm == 0.0) {
+    *mv_out = 0;
+    return TSGLS_OK;
+  }
+  double tol_abs = tol * bnorm;
+  HIPCHK(c, hipMemcpyAsync(c->gm.sc + 4, &tol_abs, sizeof(double), hipMemcpyHostToDevice, c->st));
+  int mv = 0;
+  bool first = true;
+  while (mv + m <= maxmv || first) {
+    double* V0 = c->V;
+    if (first) {
+      HIPCHK(c, launch_copy(b, V0, n, c->st));
+    } else {
+      CHK(jv_impl(c, x, c->kt, jac, dt, nullptr, prec));
+      ++mv;
+      HIPCHK(c, launch_copy(b, V0, n, c->st));
+      HIPCHK(c, launch_axpy(-1.0, c->kt, V0, n, c->st));
+    }
+    first = false;
+    HIPCHK(c, hipEventRecord(c->gev[0], c->st));
+    HIPCHK(c, hipStreamWaitEvent(c->gst, c->gev[0], 0));
+    HIPCHK(c, hipGraphLaunch(c->gexec, c->gst));
+    HIPCHK(c, hipEventRecord(c->gev[1], c->gst));
+    HIPCHK(c, hipStreamWaitEvent(c->st, c->gev[1], 0));
+    mv += m;
+    int stv[4];
+    double est = 0.0;
+    HIPCHK(c, hipMemcpyAsync(stv, c->gm.st, sizeof(stv), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(&est, c->gm.sc + 6, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (!std::isfinite(est)) return fail(c, TSGLS_ENONFINITE, "non-finite Krylov quantity");
+    if (stv[3]) break;
   }
   *mv_out = mv;
   return TSGLS_OK;
@@ -959,7 +1106,10 @@ int tsgls_solve(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_
     // b = -r in kt2 is overwritten inside gmres; keep it in the last Krylov slot-free buffer
     HIPCHK(c, launch_scal_copy(-1.0, r, r, n, c->st));
     int mv = 0;
-    if (o->restart <= 32)
+    if (o->restart <= 32 && o->gmres_graph)
+      CHK(gmres_graph(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, o->dt_pseudo,
+                      o->tangent_precision, &mv));
+    else if (o->restart <= 32)
       CHK(gmres_delayed(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, o->dt_pseudo,
                         o->tangent_precision, &mv));
     else
@@ -1070,6 +1220,11 @@ void tsgls_destroy(tsgls_ctx* c) {
   if (!c) return;
   if (c->st) (void)hipStreamSynchronize(c->st);
   else (void)hipDeviceSynchronize();
+  if (c->gst) (void)hipStreamSynchronize(c->gst);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  for (hipEvent_t e : c->gev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->gst) (void)hipStreamDestroy(c->gst);
   for (void* p : c->allocs) (void)hipFree(p);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;

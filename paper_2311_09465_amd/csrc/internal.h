@@ -143,9 +143,24 @@ hipError_t launch_axpy_dot(const double* V, int64_t ldv, int J, const double* h,
 // w <- (w - Q b - u h) inv_sigma with ab = [a (J); b (J)] on the device.
 hipError_t launch_gs_reduce(const double* Q, int64_t ldq, int J, const double* u, const double* w,
                             double* partial, int nblocks, int64_t n, hipStream_t st);
+// (inv_nu, h, inv_sigma) are read from sc[0..2] on the device when sc is not null.
 hipError_t launch_gs_update(const double* Q, int64_t ldq, int J, const double* ab, double inv_nu,
-                            double h, double inv_sigma, double* u, double* w, int64_t n,
-                            hipStream_t st);
+                            double h, double inv_sigma, const double* sc, double* u, double* w,
+                            int64_t n, hipStream_t st);
+// Device-side least-squares state of one GMRES(m) cycle (m <= 32), all device
+// pointers: H, R [(m+1) m] column-major; cs, sn, y [m]; g [m+1]; ab [64];
+// sc [8] = {1/nu, h, 1/sigma, beta, tol |r0|, 1/beta, |g_k|, -};
+// st [4] = {k, cycle over, finalize pending, converged}.
+struct GmDev {
+  double *H, *R, *cs, *sn, *g, *y, *ab, *sc;
+  int* st;
+  int m;
+};
+hipError_t launch_gm_begin(const GmDev& d, const double* bb, double tol, int first, hipStream_t st);
+hipError_t launch_gm_step(const GmDev& d, int j, const double* red, hipStream_t st);
+hipError_t launch_gm_final(const GmDev& d, const double* red, hipStream_t st);
+// x *= s[0]
+hipError_t launch_scal_dev(double* x, const double* s, int64_t n, hipStream_t st);
 // w -= sum_j V[j] h[j]
 hipError_t launch_multiaxpy(const double* V, int64_t ldv, int J, const double* h,
                             double* w, int64_t n, hipStream_t st);

@@ -272,9 +272,14 @@ k_gs_reduce(const double* __restrict__ Q, int64_t ldq, int J, const double* __re
 template <int JT>
 __global__ void __launch_bounds__(MD_BS)
 k_gs_update(const double* __restrict__ Q, int64_t ldq, int J, const double* __restrict__ ab,
-            double inv_nu, double h, double inv_sigma, double* __restrict__ u,
-            double* __restrict__ w, int64_t n) {
+            double inv_nu, double h, double inv_sigma, const double* __restrict__ sc,
+            double* __restrict__ u, double* __restrict__ w, int64_t n) {
   __shared__ double sa[JT], sb[JT];
+  if (sc) {   // scalars from the device-side least-squares update
+    inv_nu = sc[0];
+    h = sc[1];
+    inv_sigma = sc[2];
+  }
   if (threadIdx.x < JT) {
     sa[threadIdx.x] = threadIdx.x < J ? ab[threadIdx.x] : 0.0;
     sb[threadIdx.x] = threadIdx.x < J ? ab[J + threadIdx.x] : 0.0;
@@ -307,13 +312,13 @@ hipError_t launch_gs_reduce(const double* Q, int64_t ldq, int J, const double* u
 }
 
 hipError_t launch_gs_update(const double* Q, int64_t ldq, int J, const double* ab, double inv_nu,
-                            double h, double inv_sigma, double* u, double* w, int64_t n,
-                            hipStream_t st) {
+                            double h, double inv_sigma, const double* sc, double* u, double* w,
+                            int64_t n, hipStream_t st) {
   if (J < 0 || J > 32) return hipErrorInvalidValue;
   if (n == 0) return hipSuccess;
   int64_t g = (n + MD_BS - 1) / MD_BS;
   if (g > 8192) g = 8192;
-#define L(JT) k_gs_update<JT><<<(unsigned)g, MD_BS, 0, st>>>(Q, ldq, J, ab, inv_nu, h, inv_sigma, u, w, n)
+#define L(JT) k_gs_update<JT><<<(unsigned)g, MD_BS, 0, st>>>(Q, ldq, J, ab, inv_nu, h, inv_sigma, sc, u, w, n)
   if (J <= 8) L(8);
   else if (J <= 16) L(16);
   else L(32);
@@ -345,6 +350,186 @@ hipError_t launch_multiaxpy_add(const double* V, int64_t ldv, int J, const doubl
                                 hipStream_t st) {
   if (n == 0 || J == 0) return hipSuccess;
   k_multiaxpy<<<grid_for(n, 256), 256, 0, st>>>(V, ldv, J, c, y, n, 1.0);
+  return hipGetLastError();
+}
+
+// ------------------------------------------- device-side GMRES least squares
+// The host-side update of the delayed Gram-Schmidt GMRES (host.cpp,
+// gmres_delayed) on one thread, so that a whole cycle runs without the host
+// and can be captured as a graph.  State (GmDev): unrotated Hessenberg H and
+// its rotated finalized columns R (column-major, leading dimension m+1),
+// rotations, the rotated right-hand side g, the update scalars sc and the
+// status st = {k committed columns, cycle over, finalize pending, converged}.
+namespace {
+
+__device__ void gm_commit(const GmDev& d, int j) {
+  const int ld = d.m + 1;
+  double* Rj = d.R + (int64_t)j * ld;
+  const double* Hj = d.H + (int64_t)j * ld;
+  for (int i = 0; i <= j + 1; ++i) Rj[i] = Hj[i];
+  for (int i = 0; i < j; ++i) {
+    const double t = d.cs[i] * Rj[i] + d.sn[i] * Rj[i + 1];
+    Rj[i + 1] = -d.sn[i] * Rj[i] + d.cs[i] * Rj[i + 1];
+    Rj[i] = t;
+  }
+  const double den = hypot(Rj[j], Rj[j + 1]);
+  d.cs[j] = den > 0 ? Rj[j] / den : 1.0;
+  d.sn[j] = den > 0 ? Rj[j + 1] / den : 0.0;
+  Rj[j] = den;
+  Rj[j + 1] = 0.0;
+  d.g[j + 1] = -d.sn[j] * d.g[j];
+  d.g[j] = d.cs[j] * d.g[j];
+}
+
+__device__ void gm_silence(const GmDev& d, int j) {   // updates that leave u, w zero
+  for (int i = 0; i < 2 * j; ++i) d.ab[i] = 0.0;
+  d.sc[0] = d.sc[1] = d.sc[2] = 0.0;
+}
+
+}  // namespace
+
+// Cycle start: bb[0] = |r|^2 of the cycle's residual r (already in slot 0).
+// first != 0 fixes the absolute tolerance tol |r| for the whole solve.
+__global__ void k_gm_begin(GmDev d, const double* __restrict__ bb, double tol, int first) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int ld = d.m + 1;
+  const double beta = sqrt(fmax(bb[0], 0.0));
+  if (first) d.sc[4] = tol * beta;
+  for (int i = 0; i < ld * d.m; ++i) d.H[i] = d.R[i] = 0.0;
+  for (int i = 0; i <= d.m; ++i) d.g[i] = 0.0;
+  for (int i = 0; i < d.m; ++i) d.y[i] = 0.0;
+  d.g[0] = beta;
+  d.sc[3] = beta;
+  d.sc[5] = beta > 0 ? 1.0 / beta : 0.0;
+  const int conv = !(beta > d.sc[4]) || !isfinite(beta);
+  d.st[0] = 0;
+  d.st[1] = conv;
+  d.st[2] = 0;
+  d.st[3] = conv;
+  if (conv) gm_silence(d, 0);
+}
+
+// Step j after the reduction red = [Q^T u (j); Q^T w (j); u.u; u.w; w.w].
+__global__ void k_gm_step(GmDev d, int j, const double* __restrict__ red) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (d.st[1]) {
+    gm_silence(d, j);
+    return;
+  }
+  const int ld = d.m + 1;
+  const double* a = red;
+  const double* bq = red + j;
+  const double uu = red[2 * j], uw = red[2 * j + 1], ww = red[2 * j + 2];
+  double aa = 0.0, abq = 0.0, bbq = 0.0;
+  for (int i = 0; i < j; ++i) {
+    aa += a[i] * a[i];
+    abq += a[i] * bq[i];
+    bbq += bq[i] * bq[i];
+  }
+  const double nu = sqrt(fmax(uu - aa, 0.0));
+  auto H = [&](int i, int c) -> double& { return d.H[(int64_t)c * ld + i]; };
+  if (j >= 1) {          // column j-1 for u_j = Q a + nu q_j; now final
+    const double sj = H(j, j - 1);
+    for (int i = 0; i < j; ++i) H(i, j - 1) += sj * a[i];
+    H(j, j - 1) = sj * nu;
+    gm_commit(d, j - 1);
+    d.st[0] = j;
+  }
+  if (d.st[2] || !(nu > 0.0) || !isfinite(uu) || !isfinite(ww)) {
+    d.st[1] = 1;          // converged last step, or u_j in span(Q): the cycle ends here
+    d.st[3] = fabs(d.g[d.st[0]]) <= d.sc[4];
+    gm_silence(d, j);
+    return;
+  }
+  // provisional column j: A q_j = (w - A Q a) / nu, A Q a = Q (H a)
+  const double hj = (uw - abq) / nu;
+  for (int i = 0; i <= j; ++i) {
+    double ha = 0.0;
+    for (int l = (i > 0 ? i - 1 : 0); l < j; ++l) ha += H(i, l) * a[l];
+    H(i, j) = ((i < j ? bq[i] : hj) - ha) / nu;
+  }
+  const double s2 = ww - bbq - hj * hj;
+  const double sigma = sqrt(fmax(s2, 1e-30 * ww));
+  H(j + 1, j) = sigma / nu;
+  for (int i = 0; i < j; ++i) {
+    d.ab[i] = a[i];
+    d.ab[j + i] = bq[i];
+  }
+  d.sc[0] = 1.0 / nu;
+  d.sc[1] = hj;
+  d.sc[2] = 1.0 / sigma;
+  // provisional least-squares residual with column j as it stands
+  double c0 = 0.0, c1 = 0.0;
+  {
+    double col[34];
+    for (int i = 0; i <= j + 1; ++i) col[i] = H(i, j);
+    for (int i = 0; i < j; ++i) {
+      const double t = d.cs[i] * col[i] + d.sn[i] * col[i + 1];
+      col[i + 1] = -d.sn[i] * col[i] + d.cs[i] * col[i + 1];
+      col[i] = t;
+    }
+    c0 = col[j];
+    c1 = col[j + 1];
+  }
+  const double den = hypot(c0, c1);
+  const double res = den > 0 ? fabs(c1 / den * d.g[j]) : fabs(d.g[j]);
+  if (res <= d.sc[4]) d.st[2] = 1;   // finalize column j at the next reduction and stop
+}
+
+// After the last step: red = [Q^T u_m (m); ...; u_m.u_m at 2m] finalizes
+// column m-1 (unless the cycle ended earlier); then R y = g over the k
+// committed columns, y zero beyond k.
+__global__ void k_gm_final(GmDev d, const double* __restrict__ red) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int ld = d.m + 1, m = d.m;
+  if (!d.st[1]) {
+    double a2 = 0.0;
+    for (int i = 0; i < m; ++i) a2 += red[i] * red[i];
+    const double nu2 = sqrt(fmax(red[2 * m] - a2, 0.0));
+    double* Hc = d.H + (int64_t)(m - 1) * ld;
+    const double sj = Hc[m];
+    for (int i = 0; i < m; ++i) Hc[i] += sj * red[i];
+    Hc[m] = sj * nu2;
+    gm_commit(d, m - 1);
+    d.st[0] = m;
+    d.st[1] = 1;
+    d.st[3] = fabs(d.g[m]) <= d.sc[4];
+  }
+  const int k = d.st[0];
+  for (int i = m - 1; i >= 0; --i) {
+    if (i >= k) {
+      d.y[i] = 0.0;
+      continue;
+    }
+    double s = d.g[i];
+    for (int l = i + 1; l < k; ++l) s -= d.R[(int64_t)l * ld + i] * d.y[l];
+    d.y[i] = s / d.R[(int64_t)i * ld + i];
+  }
+  d.sc[6] = fabs(d.g[k]);   // least-squares residual estimate of the cycle
+}
+
+// x *= s[0] (device scalar)
+__global__ void k_scal_dev(double* __restrict__ x, const double* __restrict__ s, int64_t n) {
+  const double a = s[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] *= a;
+}
+
+hipError_t launch_gm_begin(const GmDev& d, const double* bb, double tol, int first, hipStream_t st) {
+  k_gm_begin<<<1, 64, 0, st>>>(d, bb, tol, first);
+  return hipGetLastError();
+}
+hipError_t launch_gm_step(const GmDev& d, int j, const double* red, hipStream_t st) {
+  if (j < 0 || j >= d.m || d.m > 32) return hipErrorInvalidValue;
+  k_gm_step<<<1, 64, 0, st>>>(d, j, red);
+  return hipGetLastError();
+}
+hipError_t launch_gm_final(const GmDev& d, const double* red, hipStream_t st) {
+  k_gm_final<<<1, 64, 0, st>>>(d, red);
+  return hipGetLastError();
+}
+hipError_t launch_scal_dev(double* x, const double* s, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_scal_dev<<<grid_for(n, 256), 256, 0, st>>>(x, s, n);
   return hipGetLastError();
 }
 
