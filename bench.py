@@ -250,7 +250,7 @@ def batched(args):
                                waveform=inlet_waveforms(int(Ks[i]), 1000 + i, amps[i], n_inlets=1)[0])
              for i in range(N)]
     solvers = [T.Solver.from_problem(p, stream=torch.cuda.Stream()) for p in probs]
-    opts = dict(rtol=1e-8, lin_rtol=0.05, restart=30, max_newton=40)
+    opts = dict(rtol=1e-8, lin_rtol=0.05, restart=30, max_newton=40, gmres_graph=args.batch_graph)
     # one short solve per K first (first-use setup of each kernel family)
     for K in sorted(set(int(k) for k in Ks)):
         i = int(np.argmax(Ks == K))
@@ -284,7 +284,8 @@ def batched(args):
         "config": dict(workload="womersley_6k_batched", n_tets=mesh.n_tets,
                        n_nodes=mesh.n_nodes, K_choices=[3, 5, 7, 11],
                        K_counts={int(k): int((Ks == k).sum()) for k in sorted(set(Ks.tolist()))},
-                       restart=30, lin_rtol=0.05, concurrency=args.batch_concurrency),
+                       restart=30, lin_rtol=0.05, concurrency=args.batch_concurrency,
+                       gmres_graph=bool(args.batch_graph)),
         "sequential": dict(wall_s=round(seq_wall, 3), solves_per_s=round(N / seq_wall, 3),
                            own_p50_s=round(pct(seq_own, 50), 4), own_p99_s=round(pct(seq_own, 99), 4),
                            converged=int(seq_ok), newton_iters_mean=round(float(np.mean(seq_it)), 2)),
@@ -380,6 +381,41 @@ def learned(args):
     print(json.dumps(out), flush=True)
 
 
+def dt_sweep(args):
+    """Pseudo-time step sweep: Newton-GMRES with the mass shift 1.5 rho/dt in
+    the tangent (dt = inf: plain Newton) on the pipe (6,144 tets, K = 3,
+    Re 100) and on the 200k-tet junction (K = 3, Re 100); relative residual
+    history per dt.  Prints one JSON line."""
+    import numpy as np
+    import torch
+    import paper_2311_09465_amd as T
+    from workloads import womersley_problem, junction_problem, initial_guess
+    dts = [0.0, 1.0, 0.3, 0.1, 0.03]
+    cases = [("womersley_6k_K3", womersley_problem(4, 16, K=3), 30),
+             ("junction_200k_K3_Re100", junction_problem(h=0.081, K=3, Re=100.0, seed=1), args.dt_sweep)]
+    out = {"metric": "pseudo-time step sweep: relative residual after Newton steps",
+           "n_gpus": 1, "data": "synthetic", "cases": {}}
+    for name, prob, nmax in cases:
+        s = T.Solver.from_problem(prob)
+        res = []
+        for dt in dts:
+            y = torch.from_numpy(initial_guess(prob)).cuda()
+            torch.cuda.synchronize()
+            try:
+                st = s.solve(y, rtol=1e-8, lin_rtol=0.05, restart=30, max_newton=nmax, max_matvec=3000,
+                             dt_pseudo=dt)
+                res.append(dict(dt="inf" if dt == 0 else dt, converged=st["status"] == 0,
+                                newton=st["newton_iters"], matvecs=st["matvecs"],
+                                seconds=round(st["seconds"], 3), final=float("%.3e" % st["rel_residual"]),
+                                history=[float("%.2e" % h) for h in st["history"]]))
+            except T.TsglsError as e:
+                res.append(dict(dt="inf" if dt == 0 else dt, error=str(e)))
+            print(f"{name} dt={dt}: {res[-1].get('final', res[-1].get('error'))}", file=sys.stderr, flush=True)
+        out["cases"][name] = dict(n_tets=prob.mesh.n_tets, max_newton=nmax, runs=res)
+        del s
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -397,6 +433,10 @@ def main():
     ap.add_argument("--batched", type=int, default=0, metavar="N",
                     help="batched-solve measurement: N inflow waveforms on the 6k-tet pipe")
     ap.add_argument("--batch-concurrency", type=int, default=8)
+    ap.add_argument("--batch-graph", action="store_true",
+                    help="batched solves with graph-captured GMRES cycles")
+    ap.add_argument("--dt-sweep", type=int, default=0, metavar="MAX_NEWTON",
+                    help="pseudo-time step sweep (junction runs MAX_NEWTON Newton steps)")
     ap.add_argument("--learned", type=int, default=0, metavar="N_TRAIN",
                     help="learned warm-start measurement with N_TRAIN training solves")
     ap.add_argument("--learned-test", type=int, default=32)
@@ -429,6 +469,9 @@ def main():
         return
     if args.learned:
         learned(args)
+        return
+    if args.dt_sweep:
+        dt_sweep(args)
         return
     prob, cfg = _workload(args.workload)
     s = T.Solver.from_problem(prob)
