@@ -147,6 +147,22 @@ int tsgls_set_dirichlet(tsgls_ctx* ctx, const int32_t* nodes, int64_t n);
 int tsgls_set_neumann(tsgls_ctx* ctx, const int32_t* tris, int64_t nf,
                       const double* h);
 
+/* Tracer mode: from this call on, the context solves the time-spectral GLS
+ * convection-diffusion equation (eq. 3D-weak; tau of eq. 3D-tau with kappa
+ * in place of nu) for a scalar tracer carried by the frozen periodic
+ * velocity of y_velocity (device state [n_nodes][4][2K+2]; its velocity
+ * fields are copied).  States and residuals keep the [n_nodes][4][2K+2]
+ * layout with the tracer in field 0 (fields 1..3 are zero in every
+ * residual and product).  tsgls_set_dirichlet gives the tracer's Dirichlet
+ * nodes (their values are those of the state passed to tsgls_solve); the
+ * context must have no Neumann faces (zero diffusive flux elsewhere).
+ * stabilized = 0 drops the least-squares term (tau = 0): the Galerkin
+ * method.  In tracer mode tsgls_jv ignores the variant and dt_pseudo (the
+ * operator is linear), tsgls_jacobi_diag returns ones (GMRES runs without a
+ * preconditioner) and only FP64 is available.  kappa > 0. */
+int tsgls_set_tracer(tsgls_ctx* ctx, const double* y_velocity, double kappa,
+                     int stabilized);
+
 /* r = residual(y) (eq. Rmc + backflow + Neumann traction), masked.
  * Does not change the linearization used by jv. */
 int tsgls_residual(tsgls_ctx* ctx, const double* y, double* r);

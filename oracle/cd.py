@@ -17,10 +17,12 @@ import scipy.sparse.linalg as spla
 from .tsref import QP_BARY, geometry, toeplitz, tau_from_velocity, omega_diag
 
 
-def element_matrices(xyz, tets, uq, kappa, omega, C_I=3.0):
+def element_matrices(xyz, tets, uq, kappa, omega, C_I=3.0, stabilized=True):
     """B[e, a, b] (N x N complex) of b(N_a e, N_b e') and tau per qp.
 
     uq: (E, 4, 3, N) complex velocity modes at the quadrature points.
+    stabilized=False drops the least-squares term (tau = 0): the Galerkin
+    method of the paper's comparison (section "Importance of stabilization").
     """
     grads, vol, G = geometry(xyz, tets)
     N = uq.shape[-1]
@@ -29,6 +31,8 @@ def element_matrices(xyz, tets, uq, kappa, omega, C_I=3.0):
     w = vol / 4.0
     A = toeplitz(uq)                                               # (E,4,3,N,N)
     tau = tau_from_velocity(uq, G[:, None], kappa, C_I)            # (E,4,N,N)
+    if not stabilized:
+        tau = np.zeros_like(tau)
     AdN = np.einsum("eqimn,ebi->eqbmn", A, grads, optimize=True)  # A_i dN_b/dx_i
     T = np.einsum("qb,mn->qbmn", QP_BARY, Om)[None] + AdN          # Omega N_b + A.grad N_b
     P = -np.einsum("qa,mn->qamn", QP_BARY, Om)[None] + AdN         # adjoint test operator

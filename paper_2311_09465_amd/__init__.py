@@ -63,6 +63,7 @@ def lib():
         L.tsgls_residual.argtypes = [P, P, P]
         L.tsgls_linearize.argtypes = [P, P, P]
         L.tsgls_jv.argtypes = [P, P, P, I32, D]
+        L.tsgls_set_tracer.argtypes = [P, P, D, I32]
         L.tsgls_jv_prec.argtypes = [P, P, P, I32, D, I32]
         L.tsgls_jacobi_diag.argtypes = [P, P, D]
         L.tsgls_get_tau.argtypes = [P, P]
@@ -201,6 +202,12 @@ class Solver:
         if h is not None:
             ha, hp = _host(h, np.float64)
         self._check(lib().tsgls_set_neumann(self._h, p, a.shape[0], hp), "set_neumann")
+
+    def set_tracer(self, y_velocity, kappa, stabilized=True):
+        """Switch to the tracer (convection-diffusion) equation carried by the
+        velocity of y_velocity (tsgls_set_tracer)."""
+        self._check(lib().tsgls_set_tracer(self._h, self._vec(y_velocity, "y_velocity"), float(kappa),
+                                           int(bool(stabilized))), "set_tracer")
 
     def residual(self, y, r):
         self._check(lib().tsgls_residual(self._h, self._vec(y, "y"), self._vec(r, "r")), "residual")

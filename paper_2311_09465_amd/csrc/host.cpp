@@ -64,6 +64,12 @@ struct tsgls_ctx {
   double* partial = nullptr;
   double* dh = nullptr;
   bool linearized = false;
+  // tracer mode (convection-diffusion of a scalar in field 0 by the frozen
+  // velocity of yvel): residual, tangent and solve use the tracer operator
+  bool tracer = false;
+  double kappa = 0.0;
+  int stabilized = 1;
+  double* yvel = nullptr;
   // graph-captured GMRES cycles (device-side least squares)
   hipStream_t gst = nullptr;    // capture / replay stream
   hipEvent_t gev[2] = {nullptr, nullptr};
@@ -243,7 +249,41 @@ int apply_operator(tsgls_ctx* c, const DevView& v, int mode, const double* Y, co
   return TSGLS_OK;
 }
 
+// Tracer operator applied to the modes in c->XP (element kernel + node sums).
+int apply_tracer(tsgls_ctx* c, double* out) {
+  DevView v = view(c);
+  {
+    ProfScope ps(c, TSGLS_PROF_ELEM_TANGENT);
+    HIPCHK(c, launch_cd(v, c->XP, c->kappa, c->ebuf, 0, c->E, c->st));
+  }
+  ProfScope ps(c, TSGLS_PROF_GATHER);
+  HIPCHK(c, launch_gather(c->K, c->noff, c->ninc, c->nflag, c->ebuf, out, c->nn, c->st));
+  return TSGLS_OK;
+}
+
+// Tracer linearization: velocity samples and tau (kappa in place of nu, zero
+// for the Galerkin method) from the frozen velocity; the residual of y (the
+// operator is linear in the tracer) if r is not null.
+int linearize_tracer(tsgls_ctx* c, const double* y, double* r) {
+  DevView v = view(c);
+  v.mu = c->kappa;
+  v.rho = 1.0;
+  HIPCHK(c, launch_prep_time(c->K, c->yvel, nullptr, c->nflag, 0, c->F, c->UT, c->XP, c->nn, c->st));
+  if (c->stabilized) {
+    ProfScope ps(c, TSGLS_PROF_TAU);
+    HIPCHK(c, launch_tau(v, c->yvel, c->tau, c->st));
+  } else {
+    HIPCHK(c, launch_zero(c->tau, c->E * 4 * c->P, c->st));
+  }
+  c->linearized = true;
+  c->lin32 = false;
+  if (!r) return TSGLS_OK;
+  HIPCHK(c, launch_prep_time(c->K, y, nullptr, c->nflag, 0, c->F, c->VT, c->XP, c->nn, c->st));
+  return apply_tracer(c, r);
+}
+
 int linearize_impl(tsgls_ctx* c, const double* y, double* r) {
+  if (c->tracer) return linearize_tracer(c, y, r ? r : c->rs);
   DevView v = view(c);
   c->lin32 = false;
   HIPCHK(c, launch_prep_time(c->K, y, nullptr, c->nflag, 0, c->F, c->UT, c->XP, c->nn, c->st));
@@ -280,6 +320,11 @@ int ensure_lin32(tsgls_ctx* c) {
 int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt, const double* xs = nullptr,
             int prec = TSGLS_PREC_F64) {
   if (!c->linearized) return fail(c, TSGLS_ESTATE, "jv before linearize");
+  if (c->tracer) {   // the tracer operator is linear: its tangent is itself
+    if (prec != TSGLS_PREC_F64) return fail(c, TSGLS_EINVAL, "the tracer operator runs in FP64 only");
+    HIPCHK(c, launch_prep_time(c->K, x, xs, c->nflag, 1, c->F, c->VT, c->XP, c->nn, c->st));
+    return apply_tracer(c, out);
+  }
   DevView v = view(c);
   const int mode = jac == TSGLS_JAC_PICARD ? 0 : jac == TSGLS_JAC_PICARD_NOLS ? MODE_NOLS : MODE_NEWTON;
   const double shift = dt > 0 ? 1.5 * c->p.rho / dt : 0.0;
@@ -310,6 +355,10 @@ int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt, cons
 
 int diag_impl(tsgls_ctx* c, double* d, double dt) {
   if (!c->linearized) return fail(c, TSGLS_ESTATE, "jacobi_diag before linearize");
+  if (c->tracer) {   // no preconditioner for the tracer: unit diagonal
+    HIPCHK(c, launch_fill(d, 1.0, ndof(c), c->st));
+    return TSGLS_OK;
+  }
   DevView v = view(c);
   const double shift = dt > 0 ? 1.5 * c->p.rho / dt : 0.0;
   {
@@ -1005,6 +1054,10 @@ int tsgls_set_neumann(tsgls_ctx* c, const int32_t* tris, int64_t nf, const doubl
 }
 
 int tsgls_residual(tsgls_ctx* c, const double* y, double* r) {
+  if (c && c->tracer) {
+    if (!y || !r) return fail(c, TSGLS_EINVAL, "null vector");
+    return linearize_tracer(c, y, r);
+  }
   if (!c) return TSGLS_EINVAL;
   if (!y || !r) return fail(c, TSGLS_EINVAL, "null vector");
   if (!c->UTr) {
@@ -1020,6 +1073,21 @@ int tsgls_residual(tsgls_ctx* c, const double* y, double* r) {
   HIPCHK(c, launch_tau(v, y, c->taur, c->st));
   HIPCHK(c, launch_face_lin(v, c->UTr, c->anegr, c->st));
   return apply_operator(c, v, MODE_RESID, y, nullptr, nullptr, r, 0.0, c->anegr, 1);
+}
+
+int tsgls_set_tracer(tsgls_ctx* c, const double* y_velocity, double kappa, int stabilized) {
+  if (!c) return TSGLS_EINVAL;
+  if (!y_velocity || !(kappa > 0) || !std::isfinite(kappa) || (stabilized != 0 && stabilized != 1))
+    return fail(c, TSGLS_EINVAL, "bad tracer arguments");
+  if (c->nf) return fail(c, TSGLS_EINVAL, "the tracer context must have no Neumann faces");
+  const int64_t n = ndof(c);
+  if (!c->yvel) CHK(dalloc(c, &c->yvel, n));
+  HIPCHK(c, launch_copy(y_velocity, c->yvel, n, c->st));
+  c->tracer = true;
+  c->kappa = kappa;
+  c->stabilized = stabilized;
+  c->linearized = false;
+  return TSGLS_OK;
 }
 
 int tsgls_linearize(tsgls_ctx* c, const double* y, double* r) {

@@ -125,6 +125,13 @@ hipError_t launch_axpy(double a, const double* x, double* y, int64_t n, hipStrea
 hipError_t launch_scal_copy(double a, const double* x, double* y, int64_t n, hipStream_t st);
 hipError_t launch_mul(const double* a, const double* x, double* y, int64_t n, hipStream_t st);
 hipError_t launch_recip(double* x, int64_t n, hipStream_t st);
+// x[i] = a
+hipError_t launch_fill(double* x, double a, int64_t n, hipStream_t st);
+// Tracer (convection-diffusion) element operator over elements [begin, end):
+// input modes from XP field 0, velocity samples v.UT, tau v.tau (with kappa
+// in place of nu); element rows [E][4][4][n] with the tracer in field 0.
+hipError_t launch_cd(const DevView& v, const double* XP, double kappa, double* out, int64_t begin,
+                     int64_t end, hipStream_t st);
 // y = x rounded to FP32
 hipError_t launch_to_f32(const double* x, float* y, int64_t n, hipStream_t st);
 // partial[b*J + j] = sum over block b's chunk of V[j]*w; J <= 128.

@@ -29,6 +29,9 @@ __global__ void k_mul(const double* __restrict__ a, const double* __restrict__ x
 __global__ void k_recip(double* x, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] = 1.0 / x[i];
 }
+__global__ void k_fill(double* x, double a, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] = a;
+}
 __global__ void k_to_f32(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = (float)x[i];
 }
@@ -61,6 +64,11 @@ hipError_t launch_mul(const double* a, const double* x, double* y, int64_t n, hi
 hipError_t launch_recip(double* x, int64_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   k_recip<<<grid_for(n, 256), 256, 0, st>>>(x, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill(double* x, double a, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_fill<<<grid_for(n, 256), 256, 0, st>>>(x, a, n);
   return hipGetLastError();
 }
 hipError_t launch_to_f32(const double* x, float* y, int64_t n, hipStream_t st) {
