@@ -416,6 +416,60 @@ def dt_sweep(args):
     print(json.dumps(out), flush=True)
 
 
+def tracer(args):
+    """Tracer (convection-diffusion) carried by the converged pipe flow
+    (6,144 tets, K = 3, Re 100, Wo 5): phi = 1 at the inlet, 0 at the outlet,
+    GLS against Galerkin (tau = 0) for several diffusivities; unpreconditioned
+    GMRES to 1e-8, products and time, and the range of phi over the nodes at
+    3K+1 instants of the period (bounded by [0, 1] in the exact solution).
+    Prints one JSON line."""
+    import numpy as np
+    import torch
+    import paper_2311_09465_amd as T
+    from workloads import womersley_problem, initial_guess
+    prob = womersley_problem(4, 16, K=3)
+    K = 3
+    ns = T.Solver.from_problem(prob)
+    yv = torch.from_numpy(initial_guess(prob)).cuda()
+    ns.solve(yv, rtol=1e-8, restart=30)
+
+    def nodes(t):
+        return np.unique(np.asarray(t).ravel())
+
+    wall = nodes(prob.mesh.faces["wall"])
+    dn = np.setdiff1d(np.union1d(nodes(prob.mesh.faces["inlet"]), nodes(prob.mesh.faces["outlet"])), wall)
+    inlet = np.intersect1d(dn, nodes(prob.mesh.faces["inlet"]))
+    M = 3 * K + 1
+    t = 2 * np.pi * np.arange(M) / M
+    runs = []
+    for kappa in (0.02, 0.005, 0.001):
+        for stab in (True, False):
+            s = T.Solver(prob.mesh.xyz, prob.mesh.tets, K, prob.rho, prob.mu, prob.omega)
+            s.set_dirichlet(dn.astype(np.int32))
+            s.set_tracer(yv, kappa, stab)
+            y0 = np.zeros((prob.mesh.n_nodes, 4, 2 * K + 2))
+            y0[inlet, 0, 0] = 1.0
+            y = torch.from_numpy(y0).cuda()
+            st = s.solve(y, rtol=1e-8, lin_rtol=1e-8, restart=100, max_newton=1, max_matvec=20000)
+            ph = y.cpu().numpy()[:, 0]
+            c = ph[:, 0::2] + 1j * ph[:, 1::2]
+            c[:, 0] = ph[:, 0]
+            vals = c[:, :1].real + 2 * np.real(sum(c[:, k:k + 1] * np.exp(1j * k * t)[None, :]
+                                                   for k in range(1, K + 1)))
+            runs.append(dict(kappa=kappa, method="GLS" if stab else "Galerkin",
+                             converged=st["status"] == 0, gmres_products=st["matvecs"],
+                             rel_residual=float("%.2e" % st["rel_residual"]),
+                             seconds=round(st["seconds"], 3),
+                             phi_min=float("%.3e" % vals.min()), phi_max=float("%.3e" % vals.max())))
+            print(runs[-1], file=sys.stderr, flush=True)
+            del s
+    print(json.dumps({"metric": "tracer: GLS vs Galerkin, GMRES products to 1e-8 and range of phi",
+                      "n_gpus": 1, "data": "synthetic (converged pipe flow)",
+                      "config": dict(workload="womersley_6k_K3_tracer", n_tets=prob.mesh.n_tets, K=K,
+                                     restart=100, preconditioner="none"),
+                      "runs": runs}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -437,6 +491,8 @@ def main():
                     help="batched solves with graph-captured GMRES cycles")
     ap.add_argument("--dt-sweep", type=int, default=0, metavar="MAX_NEWTON",
                     help="pseudo-time step sweep (junction runs MAX_NEWTON Newton steps)")
+    ap.add_argument("--tracer", action="store_true",
+                    help="tracer equation: GLS against Galerkin on the pipe flow")
     ap.add_argument("--learned", type=int, default=0, metavar="N_TRAIN",
                     help="learned warm-start measurement with N_TRAIN training solves")
     ap.add_argument("--learned-test", type=int, default=32)
@@ -472,6 +528,9 @@ def main():
         return
     if args.dt_sweep:
         dt_sweep(args)
+        return
+    if args.tracer:
+        tracer(args)
         return
     prob, cfg = _workload(args.workload)
     s = T.Solver.from_problem(prob)
