@@ -318,8 +318,10 @@ def learned(args):
     solvers = [T.Solver.from_problem(probs[i], stream=torch.cuda.Stream()) for i in range(ntr)]
     ys = [torch.from_numpy(initial_guess(probs[i])).cuda() for i in range(ntr)]
     torch.cuda.synchronize()
+    print(f"solving {ntr} training members", file=sys.stderr, flush=True)
     rc, st, _ = T.solve_batch(solvers, ys, rtol=1e-9, max_concurrent=8, **opts)
     t_data = time.perf_counter() - t0
+    print(f"training data in {t_data:.1f} s", file=sys.stderr, flush=True)
     del solvers
     Y = torch.stack([y.view(-1) for y in ys]).contiguous()
     del ys
@@ -336,6 +338,12 @@ def learned(args):
         r_cold = s.solve(y0.clone(), rtol=1.0, max_newton=0)["r0_norm"]
         yc = y0.clone()
         sc = s.solve(yc, rtol=1e-8, **opts)
+        try:   # the Newton tangent from the plain initial guess, for comparison (bounded)
+            scn = s.solve(y0.clone(), rtol=1e-8, jacobian="newton", **dict(opts, max_newton=30),
+                          max_matvec=1000)
+            cn = (scn["newton_iters"], scn["seconds"], scn["status"] == 0)
+        except T.TsglsError:
+            cn = (opts["max_newton"], float("nan"), False)
         torch.cuda.synchronize()
         a = time.perf_counter()
         yp = fix_dirichlet(ws.predict(feats[i:i + 1], [y0])[0], y0, p.dirichlet_nodes)
@@ -345,7 +353,10 @@ def learned(args):
         fallback = not r_warm < r_cold
         if fallback:
             yp, r_warm = y0.clone(), r_cold
+        ypn = yp.clone()
         sw = s.solve(yp, rtol=1e-8 * r_cold / r_warm, **opts)
+        # the prediction is close enough for the Newton tangent (tau frozen)
+        swn = s.solve(ypn, rtol=1e-8 * r_cold / r_warm, jacobian="newton", **opts)
         # best the basis can do: the converged solution projected on it
         coef = T.rb_project(ws.Phi, yc.view(1, -1), ws.mean)[0].contiguous()
         ypr = torch.empty_like(yc)
@@ -354,7 +365,11 @@ def learned(args):
         r_proj = s.solve(ypr, rtol=1.0, max_newton=0)["r0_norm"]
         rows.append(dict(cold_it=sc["newton_iters"], warm_it=sw["newton_iters"], cold_s=sc["seconds"],
                          warm_s=sw["seconds"] + t_pred, ratio=r_warm / r_cold, proj=r_proj / r_cold,
-                         ok=sc["status"] == 0 and sw["status"] == 0, fallback=fallback))
+                         ok=sc["status"] == 0 and sw["status"] == 0, fallback=fallback,
+                         wn_it=swn["newton_iters"], wn_s=swn["seconds"] + t_pred,
+                         wn_ok=swn["status"] == 0, cn_it=cn[0], cn_s=cn[1], cn_ok=cn[2]))
+        print(f"member {i}: cold {sc['newton_iters']} (newton tangent {cn[0]}), warm {sw['newton_iters']}, "
+              f"warm newton tangent {swn['newton_iters']}", file=sys.stderr, flush=True)
 
     def col(k):
         return np.array([row[k] for row in rows], dtype=float)
@@ -374,9 +389,16 @@ def learned(args):
                      s_p50=round(float(np.median(col("warm_s"))), 4),
                      residual_ratio_p50=float("%.3e" % np.median(col("ratio"))),
                      fallbacks=int(col("fallback").sum())),
+        "cold_newton_tangent": dict(newton_mean=round(col("cn_it").mean(), 3),
+                                    s_mean=round(float(np.nanmean(col("cn_s"))), 4),
+                                    converged=int(col("cn_ok").sum())),
+        "warm_newton_tangent": dict(newton_mean=round(col("wn_it").mean(), 3),
+                                    s_mean=round(col("wn_s").mean(), 4),
+                                    converged=int(col("wn_ok").sum())),
         "basis_projection_residual_ratio_p50": float("%.3e" % np.median(col("proj"))),
         "all_converged": bool(all(row["ok"] for row in rows)),
         "speedup_time_to_1e8": round(col("cold_s").mean() / col("warm_s").mean(), 3),
+        "speedup_time_to_1e8_warm_newton": round(col("cold_s").mean() / col("wn_s").mean(), 3),
     }
     print(json.dumps(out), flush=True)
 
