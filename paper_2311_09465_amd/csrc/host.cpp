@@ -63,6 +63,9 @@ struct tsgls_ctx {
   double* minv = nullptr;
   double* partial = nullptr;
   double* dh = nullptr;
+  double* hp = nullptr;         // pinned host staging [4096] for the Krylov scalars:
+                                // [0, 2048) device->host, [2048, 2560) coefficients,
+                                // [2560, 3584) least-squares solution
   bool linearized = false;
   // tracer mode (convection-diffusion of a scalar in field 0 by the frozen
   // velocity of yvel): residual, tangent and solve use the tracer operator
@@ -380,8 +383,9 @@ int multidot(tsgls_ctx* c, const double* V, int64_t ld, int J, const double* w, 
   HIPCHK(c, launch_multidot(V, ld, J, w, c->partial, nb, n, c->st));
   HIPCHK(c, launch_reduce_partials(c->partial, nb, J, out, c->st));
   if (host) {
-    HIPCHK(c, hipMemcpyAsync(host, out, J * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->hp, out, J * sizeof(double), hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
+    std::copy(c->hp, c->hp + J, host);
   }
   return TSGLS_OK;
 }
@@ -406,6 +410,7 @@ int ensure_krylov(tsgls_ctx* c, int m) {
     CHK(dalloc(c, &c->minv, n));
     CHK(dalloc(c, &c->partial, (size_t)multidot_blocks(n) * 1024));
     CHK(dalloc(c, &c->dh, 4096));
+    if (!c->hp) HIPCHK(c, hipHostMalloc((void**)&c->hp, 4096 * sizeof(double), hipHostMallocDefault));
   }
   c->m_alloc = m;
   return TSGLS_OK;
@@ -461,8 +466,9 @@ int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, i
     ProfScope ps(c, TSGLS_PROF_ORTHO);
     HIPCHK(c, launch_gs_reduce(c->V, n, J, u, w, c->partial, nb, n, c->st));
     HIPCHK(c, launch_reduce_partials(c->partial, nb, 2 * J + 3, c->dh, c->st));
-    HIPCHK(c, hipMemcpyAsync(red.data(), c->dh, (2 * J + 3) * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->hp, c->dh, (2 * J + 3) * sizeof(double), hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
+    std::copy(c->hp, c->hp + 2 * J + 3, red.begin());
     return TSGLS_OK;
   };
   bool first = true;
@@ -536,7 +542,10 @@ int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, i
       }
       {
         ProfScope ps(c, TSGLS_PROF_ORTHO);
-        if (j > 0) HIPCHK(c, hipMemcpyAsync(c->dh + 512, ab.data(), 2 * j * sizeof(double), hipMemcpyHostToDevice, c->st));
+        if (j > 0) {   // the previous step's copy finished at this step's synchronization
+          std::copy(ab.begin(), ab.begin() + 2 * j, c->hp + 2048);
+          HIPCHK(c, hipMemcpyAsync(c->dh + 512, c->hp + 2048, 2 * j * sizeof(double), hipMemcpyHostToDevice, c->st));
+        }
         HIPCHK(c, launch_gs_update(c->V, n, j, c->dh + 512, 1.0 / nu, hj, 1.0 / sigma, nullptr, u, w, n, c->st));
       }
       // provisional least-squares residual with column j as it stands
@@ -571,7 +580,8 @@ int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, i
       for (int l = i + 1; l < k; ++l) s -= Rr(i, l) * yv[l];
       yv[i] = s / Rr(i, i);
     }
-    HIPCHK(c, hipMemcpyAsync(c->dh + 1024, yv.data(), k * sizeof(double), hipMemcpyHostToDevice, c->st));
+    std::copy(yv.begin(), yv.begin() + k, c->hp + 2560);
+    HIPCHK(c, hipMemcpyAsync(c->dh + 1024, c->hp + 2560, k * sizeof(double), hipMemcpyHostToDevice, c->st));
     HIPCHK(c, launch_zero(c->kt, n, c->st));
     HIPCHK(c, launch_multiaxpy_add(c->V, n, k, c->dh + 1024, c->kt, n, c->st));
     HIPCHK(c, launch_mul(c->minv, c->kt, c->kt2, n, c->st));
@@ -685,8 +695,8 @@ int gmres_graph(tsgls_ctx* c, const double* b, double* x, double tol, int m, int
     *mv_out = 0;
     return TSGLS_OK;
   }
-  double tol_abs = tol * bnorm;
-  HIPCHK(c, hipMemcpyAsync(c->gm.sc + 4, &tol_abs, sizeof(double), hipMemcpyHostToDevice, c->st));
+  c->hp[3590] = tol * bnorm;
+  HIPCHK(c, hipMemcpyAsync(c->gm.sc + 4, c->hp + 3590, sizeof(double), hipMemcpyHostToDevice, c->st));
   int mv = 0;
   bool first = true;
   while (mv + m <= maxmv || first) {
@@ -708,9 +718,11 @@ int gmres_graph(tsgls_ctx* c, const double* b, double* x, double tol, int m, int
     mv += m;
     int stv[4];
     double est = 0.0;
-    HIPCHK(c, hipMemcpyAsync(stv, c->gm.st, sizeof(stv), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(c, hipMemcpyAsync(&est, c->gm.sc + 6, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->hp + 3584, c->gm.st, sizeof(stv), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->hp + 3586, c->gm.sc + 6, sizeof(double), hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
+    std::memcpy(stv, c->hp + 3584, sizeof(stv));
+    est = c->hp[3586];
     if (!std::isfinite(est)) return fail(c, TSGLS_ENONFINITE, "non-finite Krylov quantity");
     if (stv[3]) break;
   }
@@ -776,8 +788,9 @@ int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv
         HIPCHK(c, launch_reduce_partials(c->partial, nb, J, dh2, c->st));
         HIPCHK(c, launch_axpy_dot(c->V, n, J, dh2, -1.0, Vn, 0, 1, c->partial, nb, n, c->st));
         HIPCHK(c, launch_reduce_partials(c->partial, nb, 1, dnn, c->st));
-        HIPCHK(c, hipMemcpyAsync(h2.data(), c->dh, (2 * J + 1) * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(c, hipMemcpyAsync(c->hp, c->dh, (2 * J + 1) * sizeof(double), hipMemcpyDeviceToHost, c->st));
         HIPCHK(c, hipStreamSynchronize(c->st));
+        std::copy(c->hp, c->hp + 2 * J + 1, h2.begin());
         for (int i = 0; i < J; ++i) h[i] = h2[i] + h2[J + i];
         hn = std::sqrt(std::max(h2[2 * J], 0.0));
       } else {
@@ -795,8 +808,9 @@ int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv
         HIPCHK(c, launch_multiaxpy(c->V, n, J, dh2, Vn, n, c->st));
         HIPCHK(c, launch_multidot(Vn, 0, 1, Vn, c->partial, nb, n, c->st));
         HIPCHK(c, launch_reduce_partials(c->partial, nb, 1, dnn, c->st));
-        HIPCHK(c, hipMemcpyAsync(h2.data(), c->dh, (2 * J + 1) * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(c, hipMemcpyAsync(c->hp, c->dh, (2 * J + 1) * sizeof(double), hipMemcpyDeviceToHost, c->st));
         HIPCHK(c, hipStreamSynchronize(c->st));
+        std::copy(c->hp, c->hp + 2 * J + 1, h2.begin());
         for (int i = 0; i < J; ++i) h[i] = h2[i] + h2[J + i];
         hn = std::sqrt(std::max(h2[2 * J], 0.0));
       }
@@ -825,7 +839,8 @@ int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv
       for (int l = i + 1; l < k; ++l) s -= H[(size_t)i * m + l] * yv[l];
       yv[i] = s / H[(size_t)i * m + i];
     }
-    HIPCHK(c, hipMemcpyAsync(c->dh + 1024, yv.data(), k * sizeof(double), hipMemcpyHostToDevice, c->st));
+    std::copy(yv.begin(), yv.begin() + k, c->hp + 2560);
+    HIPCHK(c, hipMemcpyAsync(c->dh + 1024, c->hp + 2560, k * sizeof(double), hipMemcpyHostToDevice, c->st));
     HIPCHK(c, launch_zero(c->kt, n, c->st));
     HIPCHK(c, launch_multiaxpy_add(c->V, n, k, c->dh + 1024, c->kt, n, c->st));
     HIPCHK(c, launch_mul(c->minv, c->kt, c->kt2, n, c->st));
@@ -1293,6 +1308,7 @@ void tsgls_destroy(tsgls_ctx* c) {
   for (hipEvent_t e : c->gev)
     if (e) (void)hipEventDestroy(e);
   if (c->gst) (void)hipStreamDestroy(c->gst);
+  if (c->hp) (void)hipHostFree(c->hp);
   for (void* p : c->allocs) (void)hipFree(p);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
