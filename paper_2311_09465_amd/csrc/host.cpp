@@ -769,8 +769,7 @@ int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv
     for (int j = 0; j < m && mv < maxmv; ++j) {
       double* Vj = c->V + (int64_t)j * n;
       double* Vn = c->V + (int64_t)(j + 1) * n;
-      HIPCHK(c, launch_mul(c->minv, Vj, c->kt, n, c->st));
-      CHK(jv_impl(c, c->kt, Vn, jac, dt, nullptr, prec));
+      CHK(jv_impl(c, Vj, Vn, jac, dt, c->minv, prec));   // J (M^-1 V_j), the scale applied on load
       ++mv;
       double hn;
       if (j + 1 <= 32) {
