@@ -593,8 +593,11 @@ def main():
                     flops_per_element=jv_flops_per_element(K, args.jacobian),
                     algorithmic_bytes_per_launch=round(jv_bytes(K, E, nn, args.jacobian)),
                     hbm_gbs_algorithmic=round(jv_bytes(K, E, nn, args.jacobian) / avg_launch_s / 1e9, 1))
+    roofline["hbm_frac_algorithmic"] = round(jv_bytes(K, E, nn, args.jacobian) / avg_launch_s / 1e9
+                                             / HBM_PEAK_GBS, 4)
     if tr is not None:
         roofline["hbm_gbs_measured"] = round(tr["bytes_per_launch"] / avg_launch_s / 1e9, 1)
+        roofline["hbm_frac_measured"] = round(tr["bytes_per_launch"] / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4)
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "GDOF-modes/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(secs / args.steps * 1e3, 3),
@@ -603,15 +606,24 @@ def main():
         "config": dict(cfg, n_tets=E, n_nodes=nn, jv_per_step=m, tangent=args.jacobian),
         "roofline": roofline,
         "breakdown_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in prof.items()},
+        # tau: one launch per Newton step over 4 E points; model ~60 n^3 FP64 flops per point
+        # (S, the Jacobi sweeps and Q^T Q), against the FP64 peak
+        "tau": dict(ms_per_launch=round(prof["tau"][1] / max(prof["tau"][0], 1), 3),
+                    tflops_model=round(60.0 * (2 * K + 1) ** 3 * 4 * E
+                                       / (prof["tau"][1] / max(prof["tau"][0], 1) / 1e3) / 1e12, 3),
+                    frac_fp64_peak=round(60.0 * (2 * K + 1) ** 3 * 4 * E
+                                         / (prof["tau"][1] / max(prof["tau"][0], 1) / 1e3) / 1e12
+                                         / FP64_PEAK_TFLOPS, 4)),
         "newton_rel_residual_after": st["rel_residual"],
     }
     if not args.no_extras:
         # pure tangent-product rate, back to back at the current linearization
         v = torch.randn_like(y)
         o = torch.zeros_like(y)
-        s.jv(v, o, args.jacobian)
+        for _ in range(5):
+            s.jv(v, o, args.jacobian)
         torch.cuda.synchronize()
-        reps = 20
+        reps = 50
         a = time.perf_counter()
         for _ in range(reps):
             s.jv(v, o, args.jacobian)
@@ -650,6 +662,10 @@ def main():
             elem_tangent_tflops_fp32=round(fl / avg32 / 1e12, 3),
             elem_tangent_algorithmic_bytes=round(jv_bytes(K, E, nn, args.jacobian, word=4)),
             elem_tangent_traffic=None if tr is None else round(tr["f32_bytes_per_launch"]),
+            elem_tangent_hbm_frac_algorithmic=round(jv_bytes(K, E, nn, args.jacobian, word=4) / avg32
+                                                    / 1e9 / HBM_PEAK_GBS, 4),
+            elem_tangent_hbm_frac_measured=None if tr is None else round(
+                tr["f32_bytes_per_launch"] / avg32 / 1e9 / HBM_PEAK_GBS, 4),
             jv_ms=round(jv32, 3))
         # time to 1e-8 on the small Womersley case (full solve, FP64, Picard)
         del s
