@@ -1,4 +1,4 @@
-// Host side of the library: context, mesh checks, element/face colouring,
+// Host side of the library: context, mesh checks, Morton order and node incidence,
 // the public C ABI (include/tsgls.h) and the Newton-GMRES driver.
 #include <hip/hip_runtime.h>
 
