@@ -225,6 +225,83 @@ def summarize_pmc(fetch_csv, write_csv, command):
     print("\n".join(lines))
 
 
+ISSUE_FILE = os.path.join(ROOT, "profiles", "k_op_junction_1M_K6_issue.txt")
+ISSUE_PASSES = (
+    "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_INST_ANY SQ_WAIT_INST_LDS SQ_ACTIVE_INST_VALU "
+    "SQ_ACTIVE_INST_LDS SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE",
+    "SQ_INSTS_VALU SQ_INSTS_MFMA SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_INSTS_VALU_MFMA_MOPS_F64 "
+    "SQ_INSTS_VALU_FLOPS_FP64 SQ_ACTIVE_INST_VMEM SQ_WAIT_ANY",
+    "SQ_INSTS_SALU SQ_INSTS_SMEM SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_VALU_MFMA_MOPS_F32 "
+    "SQ_INSTS_VALU_FLOPS_FP32 SQ_ACTIVE_INST_SCA SQ_INSTS_BRANCH",
+)
+
+
+def summarize_issue(csvs):
+    """Instruction-issue summary of the tangent element kernel (and tau and
+    the gather) from three rocprofv3 --pmc CSV files of the probe workload:
+    per-dispatch averages, per element, and per SIMD as fractions of the
+    kernel's cycles (GRBM_GUI_ACTIVE is summed over the 8 XCDs; 1,024 SIMDs;
+    SQ_WAVE_CYCLES, SQ_WAIT_* and SQ_ACTIVE_INST_* count 4-cycle units;
+    an FP64 16x16x4 MFMA occupies its SIMD's matrix unit for 64 cycles)."""
+    import csv
+    import collections
+    prob, _ = _workload("junction_1M_K6")
+    E = prob.mesh.n_tets
+    tot = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    for path in csvs:
+        for r in csv.DictReader(open(path)):
+            k = r["Kernel_Name"]
+            tot[k][r["Counter_Name"]] += float(r["Counter_Value"])
+            disp[(k, path)].add(int(r["Dispatch_Id"]))
+    want = [("k_op<6, 0, double>", "k_op FP64 tangent"), ("k_op<6, 0, float>", "k_op FP32 tangent"),
+            ("k_tau<6>", "k_tau"), ("k_gather<6, double>", "k_gather FP64")]
+    lines = [
+        "# Instruction issue of the element kernels, junction 1M tets (E = %d), K = 6" % E,
+        "# Commands (repository root, one MI355X), one rocprofv3 run per counter pass:",
+    ]
+    for i, ctr in enumerate(ISSUE_PASSES):
+        lines.append(f"#   rocprofv3 --pmc {ctr} --output-format csv -d gpurun_out/issue{'ABC'[i]} "
+                     f"-o {'abc'[i]} -- python -u bench.py --probe")
+    lines.append("#   python bench.py --summarize-issue <issueA csv> <issueB csv> <issueC csv>")
+    lines.append("# Values are per dispatch (averaged over the probe's dispatches of the kernel);")
+    lines.append("# 'per element' divides by E for every kernel (the gather runs one wave per node).")
+    for pat, label in want:
+        names = [k for k in tot if pat in k]
+        if not names:
+            raise SystemExit(f"{pat}: no dispatch in the counter files")
+        k = names[0]
+        nd = max(len(disp[(k, p)]) for p in csvs)
+        c = {n: v / nd for n, v in tot[k].items()}
+        cyc = c["GRBM_GUI_ACTIVE"] / 8.0
+        simd = 1024.0
+        lines += [
+            "",
+            f"[{label}]  ({nd} dispatches)",
+            f"kernel_cycles = {cyc:.4g}   (= {cyc / 2.4e3:.1f} us at 2.4 GHz)",
+            f"waves = {c['SQ_WAVES']:.0f}",
+            f"valu_insts_per_element = {c['SQ_INSTS_VALU'] / E:.1f}",
+            f"mfma_insts_per_element = {c['SQ_INSTS_MFMA'] / E:.2f}",
+            f"lds_insts_per_element = {c['SQ_INSTS_LDS'] / E:.1f}",
+            f"salu_insts_per_element = {c['SQ_INSTS_SALU'] / E:.1f}",
+            f"vmem_rd_insts_per_element = {c['SQ_INSTS_VMEM_RD'] / E:.2f}",
+            f"mfma_f64_flops_per_element = {c['SQ_INSTS_VALU_MFMA_MOPS_F64'] * 512 / E:.0f}",
+            f"mfma_f32_flops_per_element = {c['SQ_INSTS_VALU_MFMA_MOPS_F32'] * 512 / E:.0f}",
+            f"simd_frac_mfma_busy = {c['SQ_VALU_MFMA_BUSY_CYCLES'] / (cyc * simd):.3f}",
+            f"simd_frac_valu_issue = {4.0 * c['SQ_ACTIVE_INST_VALU'] / (cyc * simd):.3f}",
+            f"simd_frac_lds_active = {4.0 * c['SQ_ACTIVE_INST_LDS'] / (cyc * simd):.3f}",
+            f"cu_frac_lds_bank_conflict = {c['SQ_LDS_BANK_CONFLICT'] / (cyc * 256.0):.3f}",
+            f"wave_frac_waiting_on_counters = {c['SQ_WAIT_ANY'] / c['SQ_WAVE_CYCLES']:.3f}",
+            f"wave_frac_waiting_to_issue = {c['SQ_WAIT_INST_ANY'] / c['SQ_WAVE_CYCLES']:.3f}",
+            f"wave_frac_waiting_lds_issue = {c['SQ_WAIT_INST_LDS'] / c['SQ_WAVE_CYCLES']:.3f}",
+        ]
+    lines.append("")
+    lines.append(f"kernel_source_hash = {kernel_source_hash()}")
+    with open(ISSUE_FILE, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def batched(args):
     """Batched solves: N inflow waveforms of uneven harmonic count on the
     Womersley pipe (R = 1, L = 4, 6,144 tets), K drawn from {3, 5, 7, 11},
@@ -506,6 +583,9 @@ def main():
                     help="counter-collection workload (linearize, 3 tangent products, a 512 MiB copy)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary under profiles/ from two rocprofv3 --pmc CSVs")
+    ap.add_argument("--summarize-issue", nargs=3, metavar=("A_CSV", "B_CSV", "C_CSV"),
+                    help="write the instruction-issue summary under profiles/ from three rocprofv3 "
+                         "--pmc CSVs of the probe")
     ap.add_argument("--batched", type=int, default=0, metavar="N",
                     help="batched-solve measurement: N inflow waveforms on the 6k-tet pipe")
     ap.add_argument("--batch-concurrency", type=int, default=8)
@@ -522,6 +602,9 @@ def main():
     ap.add_argument("--learned-steps", type=int, default=3000)
     ap.add_argument("--learned-precision", default="bf16", choices=["bf16", "f32"])
     args = ap.parse_args()
+    if args.summarize_issue:
+        summarize_issue(args.summarize_issue)
+        return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc,
                       "rocprofv3 --pmc {counter} --output-format csv -d gpurun_out/{d} -o p -- "
