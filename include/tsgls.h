@@ -98,7 +98,10 @@ typedef struct {
 typedef struct {
   double rtol;       /* Newton stop: ||r|| <= rtol ||r^0||, e.g. 1e-8 */
   double lin_rtol;   /* GMRES relative tolerance, e.g. 0.05 */
-  int restart;       /* Krylov dimension, e.g. 100 (1..1000) */
+  int restart;       /* Krylov dimension, e.g. 100 (1..1000); up to 128 GMRES uses
+                        delayed classical Gram-Schmidt (one reduction and one
+                        host synchronization per Arnoldi step), above that
+                        two-pass classical Gram-Schmidt */
   int max_newton;    /* Newton / pseudo-time iterations */
   int max_matvec;    /* tangent products per linear solve */
   int jacobian;      /* TSGLS_JAC_* */

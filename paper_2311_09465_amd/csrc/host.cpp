@@ -417,7 +417,7 @@ int ensure_krylov(tsgls_ctx* c, int m) {
 }
 
 // Right-Jacobi-preconditioned restarted GMRES with delayed classical
-// Gram-Schmidt (restart <= 32): the second Gram-Schmidt pass of basis vector
+// Gram-Schmidt (restart <= GS_DELAYED_MAX): the second Gram-Schmidt pass of basis vector
 // j is merged into step j+1's single reduction, so each Arnoldi step makes
 // one reduction and one update pass over the basis and synchronizes once.
 //   step j: w = A u_j (u_j once-orthogonalized, provisional), reduction of
@@ -444,7 +444,7 @@ int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, i
   // Hh: Hessenberg of the Arnoldi relation A Q = Q H (unrotated);
   // R: its finalized columns after the Givens rotations (least squares)
   std::vector<double> Hh((size_t)ld * m), R((size_t)ld * m), cs(m), sn(m), g(m + 1), yv(m),
-      red(2 * 32 + 3), ab(64), col(m + 2);
+      red(2 * m + 3), ab(2 * m), col(m + 2);
   auto H = [&](int i, int j) -> double& { return Hh[(size_t)j * ld + i]; };
   auto Rr = [&](int i, int j) -> double& { return R[(size_t)j * ld + i]; };
   auto commit = [&](int j) {   // column j of H is final: rotate it into R, new rotation j
@@ -1191,7 +1191,7 @@ int tsgls_solve(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_
     if (o->restart <= 32 && o->gmres_graph)
       CHK(gmres_graph(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, o->dt_pseudo,
                       o->tangent_precision, &mv));
-    else if (o->restart <= 32)
+    else if (o->restart <= GS_DELAYED_MAX)
       CHK(gmres_delayed(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, o->dt_pseudo,
                         o->tangent_precision, &mv));
     else

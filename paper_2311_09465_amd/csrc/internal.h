@@ -145,9 +145,11 @@ hipError_t launch_reduce_partials(const double* partial, int nblocks, int J,
 hipError_t launch_axpy_dot(const double* V, int64_t ldv, int J, const double* h, double sign,
                            double* w, int Jd, int self, double* partial, int nblocks, int64_t n,
                            hipStream_t st);
-// Delayed Gram-Schmidt passes (J <= 32).  Reduction: partials [nblocks][2J+3]
+// Delayed Gram-Schmidt passes (J <= GS_DELAYED_MAX, the largest restart of
+// the delayed GMRES).  Reduction: partials [nblocks][2J+3]
 // of Q^T u, Q^T w, u.u, u.w, w.w.  Update: u <- (u - Q a) inv_nu,
 // w <- (w - Q b - u h) inv_sigma with ab = [a (J); b (J)] on the device.
+constexpr int GS_DELAYED_MAX = 128;
 hipError_t launch_gs_reduce(const double* Q, int64_t ldq, int J, const double* u, const double* w,
                             double* partial, int nblocks, int64_t n, hipStream_t st);
 // (inv_nu, h, inv_sigma) are read from sc[0..2] on the device when sc is not null.

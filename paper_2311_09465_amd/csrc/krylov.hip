@@ -85,18 +85,40 @@ hipError_t launch_to_f32(const double* x, float* y, int64_t n, hipStream_t st) {
 constexpr int MD_BS = 256;
 constexpr int MD_TILE = 8;
 
-// Block-wide sums of NT per-thread values (MD_BS threads = 4 waves): an xor
-// butterfly inside each wave (both partners add the same two numbers, so all
-// lanes agree), then the four wave sums in wave order.  Thread k < NT
-// returns sum k; red holds 4 * NT doubles.
+// Value of another lane by a DPP move within a 16-lane row (CTRL: the DPP
+// control word), for a double.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false),
+                          __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ double read_lane(double x, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                          __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), the same on every lane:
+// pairs inside each 16-lane row by DPP moves (lane ^ 1, lane ^ 2, the two
+// quads of each half row, the two halves of each row; both partners add the
+// same two numbers), then the four row sums in row order.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);   // row_half_mirror
+  v += dpp_move<0x128>(v);   // row_ror:8
+  return ((read_lane(v, 0) + read_lane(v, 16)) + read_lane(v, 32)) + read_lane(v, 48);
+}
+
+// Block-wide sums of NT per-thread values (MD_BS threads = 4 waves): the sum
+// inside each wave (wave_sum), then the four wave sums in wave order.
+// Thread k < NT returns sum k; red holds 4 * NT doubles.
 template <int NT>
 __device__ __forceinline__ double block_sum_tile(double (&x)[NT], double* red, int t) {
   const int lane = t & 63, wv = t >> 6;
 #pragma unroll
   for (int k = 0; k < NT; ++k) {
-    double v = x[k];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const double v = wave_sum(x[k]);
     if (lane == 0) red[wv * NT + k] = v;
   }
   __syncthreads();
@@ -231,14 +253,19 @@ hipError_t launch_axpy_dot(const double* V, int64_t ldv, int J, const double* h,
 // Delayed classical Gram-Schmidt (one reduction and one update pass over the
 // basis per Arnoldi step).  Reduction: block partials of [Q^T u; Q^T w; u.u;
 // u.w; w.w] for the J rows of Q (fixed chunking and block tree, as
-// k_multidot).  Update: u <- (u - Q a) / nu, then w <- (w - Q b - u h) / sigma
-// with the updated u.
+// k_multidot), on a grid (nblocks, ceil(J / JT)): block (b, y) handles basis
+// vectors JT y .. JT y + JT - 1 of chunk b, and tile 0 also the three norms.
+// Update: u <- (u - Q a) / nu, then w <- (w - Q b - u h) / sigma with the
+// updated u.
 template <int JT>
 __global__ void __launch_bounds__(MD_BS)
 k_gs_reduce(const double* __restrict__ Q, int64_t ldq, int J, const double* __restrict__ u,
             const double* __restrict__ w, double* __restrict__ partial, int64_t n, int64_t chunk) {
   __shared__ double red[4 * MD_TILE];
   const int b = blockIdx.x, t = threadIdx.x;
+  const int jb = blockIdx.y * JT;                  // first basis vector of this tile
+  const int Jt = J - jb < JT ? J - jb : JT;        // vectors in this tile (0 when J = 0)
+  const bool norms = blockIdx.y == 0;
   const int Jo = 2 * J + 3;
   const int64_t lo = (int64_t)b * chunk;
   const int64_t hi = lo + chunk < n ? lo + chunk : n;
@@ -249,7 +276,7 @@ k_gs_reduce(const double* __restrict__ Q, int64_t ldq, int J, const double* __re
     const double ui = u[i], wi = w[i];
 #pragma unroll
     for (int j = 0; j < JT; ++j) {
-      const double q = j < J ? Q[(int64_t)j * ldq + i] : 0.0;
+      const double q = j < Jt ? Q[(int64_t)(jb + j) * ldq + i] : 0.0;
       da[j] = fma(q, ui, da[j]);
       db[j] = fma(q, wi, db[j]);
     }
@@ -257,23 +284,25 @@ k_gs_reduce(const double* __restrict__ Q, int64_t ldq, int J, const double* __re
     uw = fma(ui, wi, uw);
     ww = fma(wi, wi, ww);
   }
-  for (int j0 = 0; j0 < Jo; j0 += MD_TILE) {
+  // local outputs k: da (k < JT), db (JT <= k < 2 JT), the norms (2 JT + 0..2)
+  constexpr int NO = 2 * JT + 3;
+#pragma unroll
+  for (int k0 = 0; k0 < NO; k0 += MD_TILE) {
     double x[MD_TILE];
 #pragma unroll
-    for (int k = 0; k < MD_TILE; ++k) {
-      const int o = j0 + k;
-      x[k] = 0.0;
-#pragma unroll
-      for (int j = 0; j < JT; ++j) {
-        if (o == j && j < J) x[k] = da[j];
-        if (o == J + j && j < J) x[k] = db[j];
-      }
-      if (o == 2 * J) x[k] = uu;
-      if (o == 2 * J + 1) x[k] = uw;
-      if (o == 2 * J + 2) x[k] = ww;
+    for (int kk = 0; kk < MD_TILE; ++kk) {
+      const int k = k0 + kk;
+      x[kk] = k < JT ? da[k < JT ? k : 0]
+            : k < 2 * JT ? db[k < 2 * JT ? k - JT : 0]
+            : k == 2 * JT ? uu : k == 2 * JT + 1 ? uw : ww;
     }
     const double sum = block_sum_tile<MD_TILE>(x, red, t);
-    if (t < MD_TILE && j0 + t < Jo) partial[(int64_t)b * Jo + j0 + t] = sum;
+    const int k = k0 + t;
+    int o = -1;
+    if (k < JT) o = k < Jt ? jb + k : -1;
+    else if (k < 2 * JT) o = k - JT < Jt ? J + jb + (k - JT) : -1;
+    else if (k < NO && norms) o = 2 * J + (k - 2 * JT);
+    if (t < MD_TILE && o >= 0) partial[(int64_t)b * Jo + o] = sum;
   }
 }
 
@@ -307,13 +336,75 @@ k_gs_update(const double* __restrict__ Q, int64_t ldq, int J, const double* __re
   }
 }
 
+// The same update for 32 < J <= GS_DELAYED_MAX: the four waves of a block
+// take four contiguous ranges of basis vectors for the same 64 entries, and
+// their partial sums are added in wave order (deterministic), so that each
+// thread keeps only a quarter of the loads in flight.
+__global__ void __launch_bounds__(MD_BS)
+k_gs_update_wide(const double* __restrict__ Q, int64_t ldq, int J, const double* __restrict__ ab,
+                 double inv_nu, double h, double inv_sigma, const double* __restrict__ sc,
+                 double* __restrict__ u, double* __restrict__ w, int64_t n) {
+  __shared__ double sa[GS_DELAYED_MAX], sb[GS_DELAYED_MAX];
+  __shared__ double spa[4][64], spb[4][64];
+  if (sc) {
+    inv_nu = sc[0];
+    h = sc[1];
+    inv_sigma = sc[2];
+  }
+  for (int j = threadIdx.x; j < J; j += MD_BS) {
+    sa[j] = ab[j];
+    sb[j] = ab[J + j];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int per = (J + 3) / 4, j0 = wv * per, j1 = j0 + per < J ? j0 + per : J;
+  for (int64_t base = (int64_t)blockIdx.x * 64; base < n; base += (int64_t)gridDim.x * 64) {
+    const int64_t i = base + lane;
+    double pa = 0.0, pb = 0.0;
+    if (i < n) {
+      int j = j0;
+      for (; j + 8 <= j1; j += 8) {
+        double q[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) q[k] = Q[(int64_t)(j + k) * ldq + i];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          pa = fma(q[k], sa[j + k], pa);
+          pb = fma(q[k], sb[j + k], pb);
+        }
+      }
+      for (; j < j1; ++j) {
+        const double q = Q[(int64_t)j * ldq + i];
+        pa = fma(q, sa[j], pa);
+        pb = fma(q, sb[j], pb);
+      }
+    }
+    spa[wv][lane] = pa;
+    spb[wv][lane] = pb;
+    __syncthreads();
+    if (wv == 0 && i < n) {
+      const double ta = ((spa[0][lane] + spa[1][lane]) + spa[2][lane]) + spa[3][lane];
+      const double tb = ((spb[0][lane] + spb[1][lane]) + spb[2][lane]) + spb[3][lane];
+      const double un = (u[i] - ta) * inv_nu;
+      u[i] = un;
+      w[i] = (w[i] - tb - un * h) * inv_sigma;
+    }
+    __syncthreads();
+  }
+}
+
 hipError_t launch_gs_reduce(const double* Q, int64_t ldq, int J, const double* u, const double* w,
                             double* partial, int nblocks, int64_t n, hipStream_t st) {
-  if (J < 0 || J > 32) return hipErrorInvalidValue;
+  if (J < 0 || J > GS_DELAYED_MAX) return hipErrorInvalidValue;
   const int64_t chunk = (n + nblocks - 1) / nblocks;
-#define L(JT) k_gs_reduce<JT><<<nblocks, MD_BS, 0, st>>>(Q, ldq, J, u, w, partial, n, chunk)
-  if (J <= 8) L(8);
-  else if (J <= 16) L(16);
+  // Tiles of eight vectors when there are few chunks (short vectors: more
+  // blocks, and a shorter block reduction per block); every output sums the
+  // same terms in the same order whatever the tile width.
+  const int jt = (J <= 8 || nblocks < 512) ? 8 : J <= 16 ? 16 : 32;
+  const dim3 grid((unsigned)nblocks, J == 0 ? 1u : (unsigned)((J + jt - 1) / jt));
+#define L(JT) k_gs_reduce<JT><<<grid, MD_BS, 0, st>>>(Q, ldq, J, u, w, partial, n, chunk)
+  if (jt == 8) L(8);
+  else if (jt == 16) L(16);
   else L(32);
 #undef L
   return hipGetLastError();
@@ -322,15 +413,20 @@ hipError_t launch_gs_reduce(const double* Q, int64_t ldq, int J, const double* u
 hipError_t launch_gs_update(const double* Q, int64_t ldq, int J, const double* ab, double inv_nu,
                             double h, double inv_sigma, const double* sc, double* u, double* w,
                             int64_t n, hipStream_t st) {
-  if (J < 0 || J > 32) return hipErrorInvalidValue;
+  if (J < 0 || J > GS_DELAYED_MAX) return hipErrorInvalidValue;
   if (n == 0) return hipSuccess;
   int64_t g = (n + MD_BS - 1) / MD_BS;
   if (g > 8192) g = 8192;
 #define L(JT) k_gs_update<JT><<<(unsigned)g, MD_BS, 0, st>>>(Q, ldq, J, ab, inv_nu, h, inv_sigma, sc, u, w, n)
   if (J <= 8) L(8);
   else if (J <= 16) L(16);
-  else L(32);
+  else if (J <= 32) L(32);
 #undef L
+  else {
+    int64_t gw = (n + 63) / 64;
+    if (gw > 16384) gw = 16384;
+    k_gs_update_wide<<<(unsigned)gw, MD_BS, 0, st>>>(Q, ldq, J, ab, inv_nu, h, inv_sigma, sc, u, w, n);
+  }
   return hipGetLastError();
 }
 

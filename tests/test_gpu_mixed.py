@@ -102,7 +102,7 @@ def test_jv_f32_follows_relinearization():
     assert emax <= TOL32 and el2 <= TOL32
 
 
-@pytest.mark.parametrize("restart", [100, 20])
+@pytest.mark.parametrize("restart", [150, 100, 20])
 def test_solve_f32_tangent_cross_evaluated_by_oracle(restart):
     log(f"[gpu] solve with FP32 tangent restart={restart}")
     from workloads import initial_guess
