@@ -64,8 +64,9 @@ struct tsgls_ctx {
   double* partial = nullptr;
   double* dh = nullptr;
   double* hp = nullptr;         // pinned host staging [4096] for the Krylov scalars:
-                                // [0, 2048) device->host, [2048, 2560) coefficients,
-                                // [2560, 3584) least-squares solution
+                                // [0, 2048) device->host, [2560, 3584) least-squares
+                                // solution (the Gram-Schmidt coefficients of the delayed
+                                // GMRES go as kernel arguments)
   bool linearized = false;
   // tracer mode (convection-diffusion of a scalar in field 0 by the frozen
   // velocity of yvel): residual, tangent and solve use the tracer operator
@@ -542,11 +543,9 @@ int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, i
       }
       {
         ProfScope ps(c, TSGLS_PROF_ORTHO);
-        if (j > 0) {   // the previous step's copy finished at this step's synchronization
-          std::copy(ab.begin(), ab.begin() + 2 * j, c->hp + 2048);
-          HIPCHK(c, hipMemcpyAsync(c->dh + 512, c->hp + 2048, 2 * j * sizeof(double), hipMemcpyHostToDevice, c->st));
-        }
-        HIPCHK(c, launch_gs_update(c->V, n, j, c->dh + 512, 1.0 / nu, hj, 1.0 / sigma, nullptr, u, w, n, c->st));
+        // the coefficients travel as kernel arguments (no copy before the update)
+        HIPCHK(c, launch_gs_update(c->V, n, j, nullptr, ab.data(), 1.0 / nu, hj, 1.0 / sigma, nullptr,
+                                   u, w, n, c->st));
       }
       // provisional least-squares residual with column j as it stands
       bool last = (j + 1 == m) || (mv >= maxmv);
@@ -655,7 +654,7 @@ int gmres_graph(tsgls_ctx* c, const double* b, double* x, double tol, int m, int
         HIPCHK(c, launch_gs_reduce(c->V, n, j, u, w, c->partial, nb, n, c->st));
         HIPCHK(c, launch_reduce_partials(c->partial, nb, 2 * j + 3, red, c->st));
         HIPCHK(c, launch_gm_step(d, j, red, c->st));
-        HIPCHK(c, launch_gs_update(c->V, n, j, d.ab, 0.0, 0.0, 0.0, d.sc, u, w, n, c->st));
+        HIPCHK(c, launch_gs_update(c->V, n, j, d.ab, nullptr, 0.0, 0.0, 0.0, d.sc, u, w, n, c->st));
       }
       double* um = c->V + (int64_t)m * n;
       HIPCHK(c, launch_gs_reduce(c->V, n, m, um, um, c->partial, nb, n, c->st));

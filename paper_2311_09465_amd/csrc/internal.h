@@ -152,10 +152,13 @@ hipError_t launch_axpy_dot(const double* V, int64_t ldv, int J, const double* h,
 constexpr int GS_DELAYED_MAX = 128;
 hipError_t launch_gs_reduce(const double* Q, int64_t ldq, int J, const double* u, const double* w,
                             double* partial, int nblocks, int64_t n, hipStream_t st);
-// (inv_nu, h, inv_sigma) are read from sc[0..2] on the device when sc is not null.
-hipError_t launch_gs_update(const double* Q, int64_t ldq, int J, const double* ab, double inv_nu,
-                            double h, double inv_sigma, const double* sc, double* u, double* w,
-                            int64_t n, hipStream_t st);
+// The coefficients ab = [a (J); b (J)] come either from device memory (ab) or
+// from host memory (ab_host, passed by value as a kernel argument); exactly
+// one of the two is not null.  (inv_nu, h, inv_sigma) are read from sc[0..2]
+// on the device when sc is not null.
+hipError_t launch_gs_update(const double* Q, int64_t ldq, int J, const double* ab,
+                            const double* ab_host, double inv_nu, double h, double inv_sigma,
+                            const double* sc, double* u, double* w, int64_t n, hipStream_t st);
 // Device-side least-squares state of one GMRES(m) cycle (m <= 32), all device
 // pointers: H, R [(m+1) m] column-major; cs, sn, y [m]; g [m+1]; ab [64];
 // sc [8] = {1/nu, h, 1/sigma, beta, tol |r0|, 1/beta, |g_k|, -};

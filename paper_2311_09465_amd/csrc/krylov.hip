@@ -306,10 +306,18 @@ k_gs_reduce(const double* __restrict__ Q, int64_t ldq, int J, const double* __re
   }
 }
 
+// Gram-Schmidt coefficients [a (J); b (J)] passed by value as a kernel
+// argument, so that no copy to the device precedes the update.
+template <int JT>
+struct GsCoef {
+  double v[2 * JT];
+};
+
+// Coefficients come from ab (device memory) when it is not null, else from cf.
 template <int JT>
 __global__ void __launch_bounds__(MD_BS)
 k_gs_update(const double* __restrict__ Q, int64_t ldq, int J, const double* __restrict__ ab,
-            double inv_nu, double h, double inv_sigma, const double* __restrict__ sc,
+            GsCoef<JT> cf, double inv_nu, double h, double inv_sigma, const double* __restrict__ sc,
             double* __restrict__ u, double* __restrict__ w, int64_t n) {
   __shared__ double sa[JT], sb[JT];
   if (sc) {   // scalars from the device-side least-squares update
@@ -318,8 +326,9 @@ k_gs_update(const double* __restrict__ Q, int64_t ldq, int J, const double* __re
     inv_sigma = sc[2];
   }
   if (threadIdx.x < JT) {
-    sa[threadIdx.x] = threadIdx.x < J ? ab[threadIdx.x] : 0.0;
-    sb[threadIdx.x] = threadIdx.x < J ? ab[J + threadIdx.x] : 0.0;
+    const int t = threadIdx.x;
+    sa[t] = t < J ? (ab ? ab[t] : cf.v[t]) : 0.0;
+    sb[t] = t < J ? (ab ? ab[J + t] : cf.v[J + t]) : 0.0;
   }
   __syncthreads();
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -342,8 +351,9 @@ k_gs_update(const double* __restrict__ Q, int64_t ldq, int J, const double* __re
 // thread keeps only a quarter of the loads in flight.
 __global__ void __launch_bounds__(MD_BS)
 k_gs_update_wide(const double* __restrict__ Q, int64_t ldq, int J, const double* __restrict__ ab,
-                 double inv_nu, double h, double inv_sigma, const double* __restrict__ sc,
-                 double* __restrict__ u, double* __restrict__ w, int64_t n) {
+                 GsCoef<GS_DELAYED_MAX> cf, double inv_nu, double h, double inv_sigma,
+                 const double* __restrict__ sc, double* __restrict__ u, double* __restrict__ w,
+                 int64_t n) {
   __shared__ double sa[GS_DELAYED_MAX], sb[GS_DELAYED_MAX];
   __shared__ double spa[4][64], spb[4][64];
   if (sc) {
@@ -352,8 +362,8 @@ k_gs_update_wide(const double* __restrict__ Q, int64_t ldq, int J, const double*
     inv_sigma = sc[2];
   }
   for (int j = threadIdx.x; j < J; j += MD_BS) {
-    sa[j] = ab[j];
-    sb[j] = ab[J + j];
+    sa[j] = ab ? ab[j] : cf.v[j];
+    sb[j] = ab ? ab[J + j] : cf.v[J + j];
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -410,14 +420,25 @@ hipError_t launch_gs_reduce(const double* Q, int64_t ldq, int J, const double* u
   return hipGetLastError();
 }
 
-hipError_t launch_gs_update(const double* Q, int64_t ldq, int J, const double* ab, double inv_nu,
-                            double h, double inv_sigma, const double* sc, double* u, double* w,
-                            int64_t n, hipStream_t st) {
+template <int JT>
+static GsCoef<JT> gs_coef(const double* ab_host, int J) {
+  GsCoef<JT> cf{};
+  if (ab_host)
+    for (int i = 0; i < 2 * J; ++i) cf.v[i] = ab_host[i];
+  return cf;
+}
+
+hipError_t launch_gs_update(const double* Q, int64_t ldq, int J, const double* ab,
+                            const double* ab_host, double inv_nu, double h, double inv_sigma,
+                            const double* sc, double* u, double* w, int64_t n, hipStream_t st) {
   if (J < 0 || J > GS_DELAYED_MAX) return hipErrorInvalidValue;
+  if ((ab == nullptr) == (ab_host == nullptr) && J > 0) return hipErrorInvalidValue;
   if (n == 0) return hipSuccess;
   int64_t g = (n + MD_BS - 1) / MD_BS;
   if (g > 8192) g = 8192;
-#define L(JT) k_gs_update<JT><<<(unsigned)g, MD_BS, 0, st>>>(Q, ldq, J, ab, inv_nu, h, inv_sigma, sc, u, w, n)
+#define L(JT)                                                                                  \
+  k_gs_update<JT><<<(unsigned)g, MD_BS, 0, st>>>(Q, ldq, J, ab, gs_coef<JT>(ab_host, J), inv_nu, \
+                                                  h, inv_sigma, sc, u, w, n)
   if (J <= 8) L(8);
   else if (J <= 16) L(16);
   else if (J <= 32) L(32);
@@ -425,7 +446,8 @@ hipError_t launch_gs_update(const double* Q, int64_t ldq, int J, const double* a
   else {
     int64_t gw = (n + 63) / 64;
     if (gw > 16384) gw = 16384;
-    k_gs_update_wide<<<(unsigned)gw, MD_BS, 0, st>>>(Q, ldq, J, ab, inv_nu, h, inv_sigma, sc, u, w, n);
+    k_gs_update_wide<<<(unsigned)gw, MD_BS, 0, st>>>(Q, ldq, J, ab, gs_coef<GS_DELAYED_MAX>(ab_host, J),
+                                                     inv_nu, h, inv_sigma, sc, u, w, n);
   }
   return hipGetLastError();
 }
