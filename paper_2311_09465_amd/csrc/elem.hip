@@ -501,7 +501,7 @@ template <int K, typename TE>
 __global__ void __launch_bounds__(256)
 k_gather(const int32_t* __restrict__ noff, const int32_t* __restrict__ ninc,
          const uint8_t* __restrict__ nflag, const TE* __restrict__ ebuf,
-         double* __restrict__ out, int64_t nn) {
+         double* __restrict__ out, int64_t nn, FaceSum fs) {
   constexpr int n = Dim<K>::n, S = Dim<K>::S, S4 = 4 * S, R = 4 * n;
   constexpr int NJ = (S4 + 63) / 64;
   const int64_t node = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -536,6 +536,29 @@ k_gather(const int32_t* __restrict__ noff, const int32_t* __restrict__ ninc,
 #pragma unroll
     for (int r = 0; r < NJ; ++r)
       if (src[r] >= 0) acc[r] += ebuf[i0 + src[r]];
+  }
+  // face terms of a Neumann node: per velocity slot, the sum over its
+  // incident faces (ascending) of the three face points weighted by the
+  // vertex's P1 value there, minus the traction term for the residual
+  const int u = (fs.nfidx && !dir) ? fs.nfidx[node] : -1;
+  if (u >= 0) {
+    const int f0 = fs.foff[u], f1 = fs.foff[u + 1];
+#pragma unroll
+    for (int r = 0; r < NJ; ++r) {
+      const int j = lane + 64 * r, i = j / S, sl = j % S;
+      if (j < 3 * S && sl != 1) {
+        const int m = sl == 0 ? 0 : sl - 1;
+        double o = 0.0;
+        for (int kf = f0; kf < f1; ++kf) {
+          const int64_t f = fs.finc[kf] / 3;
+          const int a = fs.finc[kf] % 3;
+          const double* y = fs.fy + f * 3 * (3 * n) + i * n + m;
+          o += flam(0, a) * y[0] + flam(1, a) * y[3 * n] + flam(2, a) * y[6 * n];
+          if (fs.resid && fs.fh) o -= fs.fgeo[f * 4 + 3] / 3.0 * fs.fh[f * n + m] * fs.fgeo[f * 4 + i];
+        }
+        acc[r] += m == 0 ? o : o * TS_RS2;
+      }
+    }
   }
 #pragma unroll
   for (int r = 0; r < NJ; ++r) {
@@ -638,12 +661,13 @@ hipError_t launch_diag(const DevView& v, double* d, double shift, int64_t begin,
 }
 
 hipError_t launch_gather(int K, const int32_t* noff, const int32_t* ninc, const uint8_t* nflag,
-                         const double* ebuf, double* out, int64_t nn, hipStream_t st) {
+                         const double* ebuf, double* out, int64_t nn, hipStream_t st,
+                         const FaceSum& fs) {
   const int64_t tot = nn * 4 * (2 * K + 2);
   if (tot == 0) return hipSuccess;
   const unsigned grid = (unsigned)((nn + 3) / 4);
   switch (K) {
-#define CASE(k) case k: k_gather<k, double><<<grid, 256, 0, st>>>(noff, ninc, nflag, ebuf, out, nn); break;
+#define CASE(k) case k: k_gather<k, double><<<grid, 256, 0, st>>>(noff, ninc, nflag, ebuf, out, nn, fs); break;
     TSGLS_FOR_EACH_K(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -652,12 +676,13 @@ hipError_t launch_gather(int K, const int32_t* noff, const int32_t* ninc, const 
 }
 
 hipError_t launch_gather_f32(int K, const int32_t* noff, const int32_t* ninc, const uint8_t* nflag,
-                             const float* ebuf, double* out, int64_t nn, hipStream_t st) {
+                             const float* ebuf, double* out, int64_t nn, hipStream_t st,
+                             const FaceSum& fs) {
   const int64_t tot = nn * 4 * (2 * K + 2);
   if (tot == 0) return hipSuccess;
   const unsigned grid = (unsigned)((nn + 3) / 4);
   switch (K) {
-#define CASE(k) case k: k_gather<k, float><<<grid, 256, 0, st>>>(noff, ninc, nflag, ebuf, out, nn); break;
+#define CASE(k) case k: k_gather<k, float><<<grid, 256, 0, st>>>(noff, ninc, nflag, ebuf, out, nn, fs); break;
     TSGLS_FOR_EACH_K(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;

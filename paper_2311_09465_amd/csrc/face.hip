@@ -93,9 +93,9 @@ k_face_lin(DevView v, const double* __restrict__ UTs, double* __restrict__ aneg)
 // Backflow and traction terms in two steps.  First one block per (face,
 // face point): lane (i, m) forms y_i[m] = coef sum_c (|A_n|_-)_mc u_i[c] with
 // u the input interpolated at the point (Dirichlet rows of a direction
-// masked), coef = -(rho beta / 2) area / 3.  Then one thread per (Neumann
-// node, component, mode) sums lam_q(node) y over its incident faces and
-// points in a fixed order (deterministic) and adds it to the output.
+// masked), coef = -(rho beta / 2) area / 3.  Then the node gather (k_gather)
+// sums, per Neumann node, lam_q(node) y over its incident faces and points in
+// a fixed order (deterministic), and for the residual subtracts the traction.
 template <int K>
 __global__ void __launch_bounds__(128)
 k_face_point(DevView v, const double* __restrict__ Y, const double* __restrict__ Ys, int resid,
@@ -131,30 +131,6 @@ k_face_point(DevView v, const double* __restrict__ Y, const double* __restrict__
     const double coef = -0.5 * v.rho * v.beta * v.fgeo[f * 4 + 3] / 3.0;
     v.fy[fq * (3 * n) + i * n + m] = coef * acc;
   }
-}
-
-template <int K>
-__global__ void k_face_apply(DevView v, int resid, double* __restrict__ out) {
-  constexpr int n = Dim<K>::n, S = Dim<K>::S;
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= v.n_fnodes * 3 * n) return;
-  const int64_t u = idx / (3 * n);
-  const int i = (int)((idx / n) % 3), m = (int)(idx % n);
-  const int64_t node = v.fnode[u];
-  if (v.nflag[node] & 1) return;
-  double o = 0.0;
-  for (int k = v.foff[u]; k < v.foff[u + 1]; ++k) {
-    const int64_t f = v.finc[k] / 3;
-    const int a = v.finc[k] % 3;
-    const double* y = v.fy + f * 3 * (3 * n) + i * n + m;
-    o += flam(0, a) * y[0] + flam(1, a) * y[3 * n] + flam(2, a) * y[6 * n];
-    if (resid && v.fh) o -= v.fgeo[f * 4 + 3] / 3.0 * v.fh[f * n + m] * v.fgeo[f * 4 + i];
-  }
-  double* op = out + (node * 4 + i) * S;
-  if (m == 0)
-    op[0] += o;
-  else
-    op[m + 1] += o * TS_RS2;
 }
 
 template <int K>
@@ -208,17 +184,14 @@ hipError_t launch_face_lin(const DevView& v, const double* UTs, double* aneg, hi
   return hipGetLastError();
 }
 
-hipError_t launch_face_apply(const DevView& v, const double* Y, const double* Ys, int resid,
-                             const double* an, double* out, hipStream_t st) {
+hipError_t launch_face_point(const DevView& v, const double* Y, const double* Ys, int resid,
+                             const double* an, hipStream_t st) {
   if (v.n_fnodes == 0 || v.n_faces == 0) return hipSuccess;
   switch (v.K) {
-#define CASE(k)                                                                             \
-  case k: {                                                                                 \
+#define CASE(k)                                                                                   \
+  case k:                                                                                         \
     k_face_point<k><<<(unsigned)(v.n_faces * 3), (3 * Dim<k>::n + 63) / 64 * 64, 0, st>>>(v, Y, Ys, resid, an); \
-    const int64_t tot = v.n_fnodes * 3 * Dim<k>::n;                                         \
-    k_face_apply<k><<<(unsigned)((tot + 127) / 128), 128, 0, st>>>(v, resid, out);          \
-    break;                                                                                  \
-  }
+    break;
     TSGLS_FOR_EACH_K(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;

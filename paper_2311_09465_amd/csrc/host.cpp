@@ -46,6 +46,7 @@ struct tsgls_ctx {
   int32_t* fnode = nullptr;
   int32_t* foff = nullptr;
   int32_t* finc = nullptr;
+  int32_t* nfidx = nullptr;     // [nn] node -> Neumann-node index, -1 elsewhere
   double* fgeo = nullptr;
   double* fh = nullptr;
   double* aneg = nullptr;
@@ -234,21 +235,36 @@ struct ProfScope {
 // Volume + face terms of the operator into out (overwritten).  The input's
 // modes must already be in c->XP (launch_prep_time); Y is the input vector
 // itself (face terms).
+// Face terms for the node gather (none without Neumann faces).
+FaceSum face_sum(const tsgls_ctx* c, int resid) {
+  FaceSum fs;
+  if (c->nf == 0) return fs;
+  fs.nfidx = c->nfidx;
+  fs.foff = c->foff;
+  fs.finc = c->finc;
+  fs.fy = c->fy;
+  fs.fgeo = c->fgeo;
+  fs.fh = c->fh;
+  fs.resid = resid;
+  return fs;
+}
+
 int apply_operator(tsgls_ctx* c, const DevView& v, int mode, const double* Y, const double* VTp,
                    double* Zout, double* out, double shift, const double* an, int resid,
                    const double* Ys = nullptr) {
   const int which = (mode & MODE_RESID) ? TSGLS_PROF_ELEM_RESIDUAL : TSGLS_PROF_ELEM_TANGENT;
+  if (c->nf) {   // face points first (they need only the input); the gather adds them
+    ProfScope ps(c, TSGLS_PROF_FACE);
+    HIPCHK(c, launch_face_point(v, Y, Ys, resid, an, c->st));
+  }
   {
     ProfScope ps(c, which);
     HIPCHK(c, launch_elem(v, mode, c->XP, VTp, Zout, c->ebuf, shift, 0, c->E, c->st));
   }
   {
     ProfScope ps(c, TSGLS_PROF_GATHER);
-    HIPCHK(c, launch_gather(c->K, c->noff, c->ninc, c->nflag, c->ebuf, out, c->nn, c->st));
-  }
-  if (c->nf) {
-    ProfScope ps(c, TSGLS_PROF_FACE);
-    HIPCHK(c, launch_face_apply(v, Y, Ys, resid, an, out, c->st));
+    HIPCHK(c, launch_gather(c->K, c->noff, c->ninc, c->nflag, c->ebuf, out, c->nn, c->st,
+                            face_sum(c, resid)));
   }
   return TSGLS_OK;
 }
@@ -342,17 +358,18 @@ int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt, cons
   float* VT32 = reinterpret_cast<float*>(c->VT);
   float* eb32 = reinterpret_cast<float*>(c->ebuf);
   HIPCHK(c, launch_prep_time_f32(c->K, x, xs, c->nflag, 1, c->F, VT32, XP32, c->nn, c->st));
+  if (c->nf) {
+    ProfScope ps(c, TSGLS_PROF_FACE);
+    HIPCHK(c, launch_face_point(v, x, xs, 0, c->aneg, c->st));
+  }
   {
     ProfScope ps(c, TSGLS_PROF_ELEM_TANGENT);
     HIPCHK(c, launch_elem_f32(v, mode, XP32, VT32, eb32, shift, 0, c->E, c->st));
   }
   {
     ProfScope ps(c, TSGLS_PROF_GATHER);
-    HIPCHK(c, launch_gather_f32(c->K, c->noff, c->ninc, c->nflag, eb32, out, c->nn, c->st));
-  }
-  if (c->nf) {
-    ProfScope ps(c, TSGLS_PROF_FACE);
-    HIPCHK(c, launch_face_apply(v, x, xs, 0, c->aneg, out, c->st));
+    HIPCHK(c, launch_gather_f32(c->K, c->noff, c->ninc, c->nflag, eb32, out, c->nn, c->st,
+                                face_sum(c, 0)));
   }
   return TSGLS_OK;
 }
@@ -989,7 +1006,8 @@ int tsgls_set_neumann(tsgls_ctx* c, const int32_t* tris, int64_t nf, const doubl
   dfree(c, c->fnode);
   dfree(c, c->foff);
   dfree(c, c->finc);
-  c->fconn = c->fnode = c->foff = c->finc = nullptr;
+  dfree(c, c->nfidx);
+  c->fconn = c->fnode = c->foff = c->finc = c->nfidx = nullptr;
   c->fgeo = c->fh = c->aneg = c->anegr = c->fy = nullptr;
   c->nf = 0;
   c->n_fnodes = 0;
@@ -1044,6 +1062,14 @@ int tsgls_set_neumann(tsgls_ctx* c, const int32_t* tris, int64_t nf, const doubl
   HIPCHK(c, hipMemcpyAsync(c->fnode, fnode.data(), fnode.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->foff, foff.data(), foff.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->finc, finc.data(), finc.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+  {
+    std::vector<int32_t> nfidx(c->nn, -1);
+    for (size_t u = 0; u < fnode.size(); ++u) nfidx[fnode[u]] = (int32_t)u;
+    CHK(dalloc(c, &c->nfidx, nfidx.size()));
+    HIPCHK(c, hipMemcpyAsync(c->nfidx, nfidx.data(), nfidx.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                             c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));   // the host arrays are freed at scope end
+  }
   CHK(dalloc(c, &c->fconn, nf * 3));
   CHK(dalloc(c, &c->fgeo, nf * 4));
   CHK(dalloc(c, &c->aneg, (size_t)nf * 3 * c->P));

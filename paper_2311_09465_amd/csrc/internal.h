@@ -98,20 +98,39 @@ hipError_t launch_elem_f32(const DevView& v, int mode, const float* XP, const fl
                            float* out, double shift, int64_t begin, int64_t end, hipStream_t st);
 hipError_t launch_diag(const DevView& v, double* d, double shift,
                        int64_t begin, int64_t end, hipStream_t st);
+// Neumann face terms added by the node gather: nfidx maps a node to its
+// index in the Neumann-node list (-1 for other nodes), foff/finc list that
+// node's incident (face, vertex) pairs in ascending face order, fy holds
+// -(rho beta / 2)(area / 3) |A_n|_- u per face point (launch_face_point) and,
+// for the residual (resid != 0), fh the traction modes.  nfidx == nullptr: no
+// face terms.
+struct FaceSum {
+  const int32_t* nfidx = nullptr;
+  const int32_t* foff = nullptr;
+  const int32_t* finc = nullptr;
+  const double* fy = nullptr;
+  const double* fgeo = nullptr;
+  const double* fh = nullptr;
+  int resid = 0;
+};
 // out[node][4][S] = sum over incident (element, local node) of the ebuf rows
-// mapped from positions to slots, in ascending element order (deterministic).
-// Velocity rows of Dirichlet nodes (nflag bit 0) are written as zero.
+// mapped from positions to slots, in ascending element order (deterministic),
+// then the node's face terms (fs).  Velocity rows of Dirichlet nodes (nflag
+// bit 0) are written as zero.
 hipError_t launch_gather(int K, const int32_t* noff, const int32_t* ninc,
                          const uint8_t* nflag, const double* ebuf, double* out,
-                         int64_t n_nodes, hipStream_t st);
+                         int64_t n_nodes, hipStream_t st, const FaceSum& fs = FaceSum());
 // The same from FP32 element rows (accumulated in FP64).
 hipError_t launch_gather_f32(int K, const int32_t* noff, const int32_t* ninc,
                              const uint8_t* nflag, const float* ebuf, double* out,
-                             int64_t n_nodes, hipStream_t st);
+                             int64_t n_nodes, hipStream_t st, const FaceSum& fs = FaceSum());
 hipError_t launch_face_lin(const DevView& v, const double* Y, double* aneg,
                            hipStream_t st);
-hipError_t launch_face_apply(const DevView& v, const double* Y, const double* Ys, int resid,
-                             const double* aneg, double* out, hipStream_t st);
+// Per Neumann face point: fy = -(rho beta / 2)(area / 3) |A_n|_- u with u the
+// input (Y, times Ys when not null) at the point; Dirichlet velocity rows of
+// a direction (resid == 0) are masked.  The node sums are taken by the gather.
+hipError_t launch_face_point(const DevView& v, const double* Y, const double* Ys, int resid,
+                             const double* aneg, hipStream_t st);
 hipError_t launch_face_diag(const DevView& v, double* d, hipStream_t st);
 hipError_t launch_diag_finish(int K, const uint8_t* nflag, double* d,
                               int64_t n_nodes, hipStream_t st);
