@@ -68,6 +68,8 @@ struct tsgls_ctx {
                                 // [0, 2048) device->host, [2560, 3584) least-squares
                                 // solution (the Gram-Schmidt coefficients of the delayed
                                 // GMRES go as kernel arguments)
+  double* hpd = nullptr;        // device address of hp (the delayed GMRES's reductions
+                                // are written there by the GPU directly)
   bool linearized = false;
   // tracer mode (convection-diffusion of a scalar in field 0 by the frozen
   // velocity of yvel): residual, tangent and solve use the tracer operator
@@ -428,7 +430,10 @@ int ensure_krylov(tsgls_ctx* c, int m) {
     CHK(dalloc(c, &c->minv, n));
     CHK(dalloc(c, &c->partial, (size_t)multidot_blocks(n) * 1024));
     CHK(dalloc(c, &c->dh, 4096));
-    if (!c->hp) HIPCHK(c, hipHostMalloc((void**)&c->hp, 4096 * sizeof(double), hipHostMallocDefault));
+    if (!c->hp) {
+      HIPCHK(c, hipHostMalloc((void**)&c->hp, 4096 * sizeof(double), hipHostMallocDefault));
+      HIPCHK(c, hipHostGetDevicePointer((void**)&c->hpd, c->hp, 0));
+    }
   }
   c->m_alloc = m;
   return TSGLS_OK;
@@ -483,8 +488,9 @@ int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, i
   auto reduce = [&](int J, const double* u, const double* w) -> int {
     ProfScope ps(c, TSGLS_PROF_ORTHO);
     HIPCHK(c, launch_gs_reduce(c->V, n, J, u, w, c->partial, nb, n, c->st));
-    HIPCHK(c, launch_reduce_partials(c->partial, nb, 2 * J + 3, c->dh, c->st));
-    HIPCHK(c, hipMemcpyAsync(c->hp, c->dh, (2 * J + 3) * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    // the second stage writes the sums straight into pinned host memory (no
+    // copy launch); they are read after the stream synchronization
+    HIPCHK(c, launch_reduce_partials(c->partial, nb, 2 * J + 3, c->hpd, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
     std::copy(c->hp, c->hp + 2 * J + 3, red.begin());
     return TSGLS_OK;
