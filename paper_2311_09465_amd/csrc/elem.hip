@@ -12,6 +12,7 @@
 // conjugate-symmetric mode vectors.  Products are formed on M = 3K+1 time
 // samples, which reproduces the truncated convolution exactly.
 #include "common.cuh"
+#include "face_point.cuh"
 #include "internal.h"
 
 namespace tsgls {
@@ -66,16 +67,24 @@ hipError_t launch_geometry(const double* xyz, const int32_t* conn, double* geo, 
 // (field f, position p) writes XP[node][f][p] = mode pos_mode(p) of field f
 // in the orthonormal basis; then lane (j, s) forms XT[node][j][s] = u_j(t_s)
 // from the modes staged in LDS.  masked != 0 zeroes Dirichlet velocity rows;
-// Ys, when given, scales the input entrywise (input = Y * Ys).
+// Ys, when given, scales the input entrywise (input = Y * Ys).  Blocks from
+// nbp on each form one Neumann face point of the same input (no separate
+// launch for the face points of a tangent product).
 template <int K, typename TO>
 __global__ void __launch_bounds__(256)
 k_prep_time(const double* __restrict__ Y, const double* __restrict__ Ys,
             const uint8_t* __restrict__ nflag, int masked, const double* __restrict__ F,
-            TO* __restrict__ XT, TO* __restrict__ XP, int64_t nn) {
+            TO* __restrict__ XT, TO* __restrict__ XP, int64_t nn, int64_t nbp, DevView fv,
+            const double* __restrict__ aneg, int fresid) {
   constexpr int n = Dim<K>::n, S = Dim<K>::S, M = Dim<K>::M, PW = (n + 15) / 16 * 16;
   constexpr int NPT = PW / 16, NR = (3 * M + 63) / 64;
   constexpr bool HOIST = NR == 1;          // the lane's column of F stays in registers
   __shared__ double sx[4][4 * PW];
+  if (blockIdx.x >= nbp) {                 // a face point (uniform per block)
+    static_assert(3 * n <= 256 && 3 * n <= 16 * PW, "face point lanes and LDS");
+    face_point_block<K>(fv, Y, Ys, fresid, aneg, (int64_t)blockIdx.x - nbp, threadIdx.x, &sx[0][0]);
+    return;
+  }
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int sj[NR], ss[NR];
 #pragma unroll
@@ -89,7 +98,7 @@ k_prep_time(const double* __restrict__ Y, const double* __restrict__ Ys,
 #pragma unroll
     for (int a = 0; a < n; ++a) Fl[HOIST ? a : 0] = F[a * M + ss[0]];
   }
-  const int64_t stride = (int64_t)gridDim.x * 4;
+  const int64_t stride = nbp * 4;
   // the trip count is the same for the four waves of a block (barriers below)
   for (int64_t base = (int64_t)blockIdx.x * 4; base < nn; base += stride) {
     const int64_t node = base + wv;
@@ -598,15 +607,22 @@ int supported_K_list(int* out, int cap) {
   return cnt;
 }
 
-hipError_t launch_prep_time(int K, const double* Y, const double* Ys, const uint8_t* nflag,
-                            int masked, const double* F, double* XT, double* XP, int64_t nn,
-                            hipStream_t st) {
+template <typename TO>
+static hipError_t prep_launch(int K, const double* Y, const double* Ys, const uint8_t* nflag,
+                              int masked, const double* F, TO* XT, TO* XP, int64_t nn,
+                              hipStream_t st, const DevView* fv, const double* aneg, int fresid) {
   if (nn == 0) return hipSuccess;
   int64_t nb = (nn + 3) / 4;
   if (nb > 8192) nb = 8192;
-  const unsigned grid = (unsigned)nb;
+  const int64_t nfq = (fv && fv->n_faces > 0 && fv->n_fnodes > 0) ? fv->n_faces * 3 : 0;
+  const DevView dv = fv ? *fv : DevView{};
+  const unsigned grid = (unsigned)(nb + nfq);
   switch (K) {
-#define CASE(k) case k: k_prep_time<k, double><<<grid, 256, 0, st>>>(Y, Ys, nflag, masked, F, XT, XP, nn); break;
+#define CASE(k)                                                                                  \
+  case k:                                                                                        \
+    k_prep_time<k, TO><<<grid, 256, 0, st>>>(Y, Ys, nflag, masked, F, XT, XP, nn, nb, dv, aneg,   \
+                                             fresid);                                            \
+    break;
     TSGLS_FOR_EACH_K(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -614,20 +630,16 @@ hipError_t launch_prep_time(int K, const double* Y, const double* Ys, const uint
   return hipGetLastError();
 }
 
+hipError_t launch_prep_time(int K, const double* Y, const double* Ys, const uint8_t* nflag,
+                            int masked, const double* F, double* XT, double* XP, int64_t nn,
+                            hipStream_t st, const DevView* fv, const double* aneg, int fresid) {
+  return prep_launch<double>(K, Y, Ys, nflag, masked, F, XT, XP, nn, st, fv, aneg, fresid);
+}
+
 hipError_t launch_prep_time_f32(int K, const double* Y, const double* Ys, const uint8_t* nflag,
                                 int masked, const double* F, float* XT, float* XP, int64_t nn,
-                                hipStream_t st) {
-  if (nn == 0) return hipSuccess;
-  int64_t nb = (nn + 3) / 4;
-  if (nb > 8192) nb = 8192;
-  const unsigned grid = (unsigned)nb;
-  switch (K) {
-#define CASE(k) case k: k_prep_time<k, float><<<grid, 256, 0, st>>>(Y, Ys, nflag, masked, F, XT, XP, nn); break;
-    TSGLS_FOR_EACH_K(CASE)
-#undef CASE
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+                                hipStream_t st, const DevView* fv, const double* aneg, int fresid) {
+  return prep_launch<float>(K, Y, Ys, nflag, masked, F, XT, XP, nn, st, fv, aneg, fresid);
 }
 
 hipError_t launch_tau(const DevView& v, const double* Y, double* tau, hipStream_t st) {

@@ -3,6 +3,7 @@
 // (section "Stabilizing simulations in the presence of backflow") and the
 // traction term -(w, h n)_Gamma_h of eq. Rmc.  3-point degree-2 rule per face.
 #include "common.cuh"
+#include "face_point.cuh"
 #include "internal.h"
 
 namespace tsgls {
@@ -100,37 +101,8 @@ template <int K>
 __global__ void __launch_bounds__(128)
 k_face_point(DevView v, const double* __restrict__ Y, const double* __restrict__ Ys, int resid,
              const double* __restrict__ an) {
-  constexpr int n = Dim<K>::n, S = Dim<K>::S, P = Dim<K>::P;
-  __shared__ double su[3 * n];
-  const int64_t fq = blockIdx.x;           // face * 3 + point
-  const int64_t f = fq / 3;
-  const int q = (int)(fq % 3);
-  const int t = threadIdx.x;
-  const int i = t / n, m = t % n;
-  if (t < 3 * n) {
-    double acc = 0.0;
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const int64_t nb = v.fconn[f * 3 + b];
-      const bool z = !resid && (v.nflag[nb] & 1);
-      const int64_t o = (nb * 4 + i) * S + (m == 0 ? 0 : m + 1);
-      const double x = (m == 0 ? 1.0 : TS_SQ2) * (Ys ? Y[o] * Ys[o] : Y[o]);
-      acc += z ? 0.0 : flam(q, b) * x;
-    }
-    su[i * n + m] = acc;
-  }
-  __syncthreads();
-  if (t < 3 * n) {
-    const double* ap = an + fq * P;
-    double acc = 0.0;
-#pragma unroll
-    for (int cc = 0; cc < n; ++cc) {
-      const int lo = m < cc ? m : cc, hi = m < cc ? cc : m;
-      acc = fma(ap[lo * n - (lo * (lo - 1)) / 2 + (hi - lo)], su[i * n + cc], acc);
-    }
-    const double coef = -0.5 * v.rho * v.beta * v.fgeo[f * 4 + 3] / 3.0;
-    v.fy[fq * (3 * n) + i * n + m] = coef * acc;
-  }
+  __shared__ double su[3 * Dim<K>::n];
+  face_point_block<K>(v, Y, Ys, resid, an, blockIdx.x, threadIdx.x, su);
 }
 
 template <int K>

@@ -251,11 +251,13 @@ FaceSum face_sum(const tsgls_ctx* c, int resid) {
   return fs;
 }
 
+// faces_ready: the face points of Y were formed with its nodal samples
+// (launch_prep_time with the face view), so they are not launched here.
 int apply_operator(tsgls_ctx* c, const DevView& v, int mode, const double* Y, const double* VTp,
                    double* Zout, double* out, double shift, const double* an, int resid,
-                   const double* Ys = nullptr) {
+                   const double* Ys = nullptr, bool faces_ready = false) {
   const int which = (mode & MODE_RESID) ? TSGLS_PROF_ELEM_RESIDUAL : TSGLS_PROF_ELEM_TANGENT;
-  if (c->nf) {   // face points first (they need only the input); the gather adds them
+  if (c->nf && !faces_ready) {   // face points first (they need only the input); the gather adds them
     ProfScope ps(c, TSGLS_PROF_FACE);
     HIPCHK(c, launch_face_point(v, Y, Ys, resid, an, c->st));
   }
@@ -350,20 +352,19 @@ int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt, cons
   DevView v = view(c);
   const int mode = jac == TSGLS_JAC_PICARD ? 0 : jac == TSGLS_JAC_PICARD_NOLS ? MODE_NOLS : MODE_NEWTON;
   const double shift = dt > 0 ? 1.5 * c->p.rho / dt : 0.0;
+  const DevView* fv = c->nf ? &v : nullptr;   // face points in the same launch as the samples
   if (prec == TSGLS_PREC_F64) {
-    HIPCHK(c, launch_prep_time(c->K, x, xs, c->nflag, 1, c->F, c->VT, c->XP, c->nn, c->st));
-    return apply_operator(c, v, mode, x, c->VT, nullptr, out, shift, c->aneg, 0, xs);
+    HIPCHK(c, launch_prep_time(c->K, x, xs, c->nflag, 1, c->F, c->VT, c->XP, c->nn, c->st, fv,
+                               c->aneg, 0));
+    return apply_operator(c, v, mode, x, c->VT, nullptr, out, shift, c->aneg, 0, xs, true);
   }
   CHK(ensure_lin32(c));
   v = view(c);
   float* XP32 = reinterpret_cast<float*>(c->XP);
   float* VT32 = reinterpret_cast<float*>(c->VT);
   float* eb32 = reinterpret_cast<float*>(c->ebuf);
-  HIPCHK(c, launch_prep_time_f32(c->K, x, xs, c->nflag, 1, c->F, VT32, XP32, c->nn, c->st));
-  if (c->nf) {
-    ProfScope ps(c, TSGLS_PROF_FACE);
-    HIPCHK(c, launch_face_point(v, x, xs, 0, c->aneg, c->st));
-  }
+  HIPCHK(c, launch_prep_time_f32(c->K, x, xs, c->nflag, 1, c->F, VT32, XP32, c->nn, c->st,
+                                 c->nf ? &v : nullptr, c->aneg, 0));
   {
     ProfScope ps(c, TSGLS_PROF_ELEM_TANGENT);
     HIPCHK(c, launch_elem_f32(v, mode, XP32, VT32, eb32, shift, 0, c->E, c->st));

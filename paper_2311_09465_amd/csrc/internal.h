@@ -74,13 +74,19 @@ hipError_t launch_geometry(const double* xyz, const int32_t* conn, double* geo,
 // XP[node][4][PW]: the four fields' modes in the orthonormal basis at their
 // positions (zero padding).  masked != 0 zeroes Dirichlet velocity rows.  The
 // input is Y, or Y * Ys entrywise when Ys is not null.
+// When fv is not null, the same launch also forms the Neumann face points of
+// the input (as launch_face_point(*fv, Y, Ys, fresid, aneg)) in extra blocks.
 hipError_t launch_prep_time(int K, const double* Y, const double* Ys,
                             const uint8_t* nflag, int masked, const double* F,
-                            double* XT, double* XP, int64_t n_nodes, hipStream_t st);
+                            double* XT, double* XP, int64_t n_nodes, hipStream_t st,
+                            const DevView* fv = nullptr, const double* aneg = nullptr,
+                            int fresid = 0);
 // The same with FP32 outputs (the sums are formed in FP64).
 hipError_t launch_prep_time_f32(int K, const double* Y, const double* Ys,
                                 const uint8_t* nflag, int masked, const double* F,
-                                float* XT, float* XP, int64_t n_nodes, hipStream_t st);
+                                float* XT, float* XP, int64_t n_nodes, hipStream_t st,
+                                const DevView* fv = nullptr, const double* aneg = nullptr,
+                                int fresid = 0);
 // Positions per field row of XP (16 or 32).
 int pos_width(int K);
 hipError_t launch_tau(const DevView& v, const double* Y, double* tau,
