@@ -288,9 +288,12 @@ int tsgls_info(const tsgls_ctx* ctx, int64_t* n_colors, int64_t* n_tets,
 #define TSGLS_PROF_ELEM_RESIDUAL 1  /* element kernel in residual / linearize */
 #define TSGLS_PROF_TAU 2            /* tau kernel (one launch per linearize) */
 #define TSGLS_PROF_DIAG 3           /* Jacobi-diagonal element kernel */
-#define TSGLS_PROF_FACE 4           /* face-term kernel */
+#define TSGLS_PROF_FACE 4           /* face-point kernel of the residual (a tangent
+                                       product forms its face points in the launch
+                                       of its nodal time samples, which is not timed) */
 #define TSGLS_PROF_ORTHO 5          /* Gram-Schmidt block of one GMRES iteration */
-#define TSGLS_PROF_GATHER 6         /* node-wise sum of element contributions */
+#define TSGLS_PROF_GATHER 6         /* node-wise sum of element contributions and
+                                       of the Neumann face terms */
 int tsgls_profile(tsgls_ctx* ctx, int enable);
 int tsgls_profile_get(tsgls_ctx* ctx, int which, int64_t* launches, double* total_ms);
 
