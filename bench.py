@@ -714,6 +714,20 @@ def main():
         jv_ms = (time.perf_counter() - a) / reps * 1e3
         out["jv_ms"] = round(jv_ms, 3)
         out["jv_only_gdof_modes_s"] = round(dof / jv_ms / 1e6, 4)
+        # linearize (nodal samples, tau, face |A_n|_-, residual with z stored)
+        # and the residual alone, in the same unit, 10 calls each after one
+        r = torch.zeros_like(y)
+        for name, call in (("linearize", lambda: s.linearize(y, r)), ("residual", lambda: s.residual(y, r))):
+            call()
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            for _ in range(10):
+                call()
+            torch.cuda.synchronize()
+            t_ms = (time.perf_counter() - a) / 10 * 1e3
+            out[f"{name}_ms"] = round(t_ms, 3)
+            out[f"{name}_gdof_modes_s"] = round(dof / t_ms / 1e6, 4)
+        s.linearize(y)   # the state the products below were measured at
         # mixed precision: the same steps, from the same state, with the FP32
         # element operator in the tangent (residual, tau, diagonal and Krylov
         # stay FP64); one FP32 product first allocates the FP32 copies
