@@ -14,7 +14,8 @@ import numpy as np
 import scipy.sparse as sps
 import scipy.sparse.linalg as spla
 
-from .tsref import QP_BARY, geometry, toeplitz, tau_from_velocity, omega_diag
+from .tsref import (FACE_QP_BARY, QP_BARY, _face_geometry, _negpart, geometry, omega_diag,
+                    tau_from_velocity, toeplitz)
 
 
 def element_matrices(xyz, tets, uq, kappa, omega, C_I=3.0, stabilized=True):
@@ -41,6 +42,24 @@ def element_matrices(xyz, tets, uq, kappa, omega, C_I=3.0, stabilized=True):
          + kappa * np.einsum("e,eak,ebk,mn->eabmn", vol, grads, grads, I, optimize=True)
          + np.einsum("e,eqamk,eqkl,eqbln->eabmn", w, P, tau, T, optimize=True))
     return B, tau, P, w
+
+
+def face_matrices(xyz, tris, C, beta):
+    """Backflow term of the convection-diffusion equation on Neumann faces
+    (remarks after the backflow stabilization of the Navier-Stokes equations):
+    -(w, (beta / 2) |A_n|_- phi)_Gamma is added to b(w, phi), with
+    |A_n|_- = (A_n - |A_n|) / 2 and A_n the mode-coupling matrix of the
+    normal velocity u.n, on the 3-point degree-2 face rule (weights area/3).
+
+    tris: (F, 3) face nodes; C: (n_nodes, 3, N) complex velocity modes.
+    Returns Bf[f, a, b] (N x N complex), assembled like element blocks.
+    """
+    nhat, area = _face_geometry(xyz, tris)
+    uf = np.einsum("qa,fain->fqin", FACE_QP_BARY, C[tris][:, :, :3])
+    un = np.einsum("fi,fqin->fqn", nhat, uf)
+    Aneg = _negpart(toeplitz(un))                                  # (F, 3, N, N)
+    return -0.5 * beta * np.einsum("f,qa,qb,fqmn->fabmn", area / 3.0, FACE_QP_BARY,
+                                   FACE_QP_BARY, Aneg, optimize=True)
 
 
 def assemble(xyz, tets, B):

@@ -110,3 +110,58 @@ def test_lemma1_identity(kappa):
     ls = np.sum(vol[:, None] / 4 * np.einsum("eqm,eqmn,eqn->eq", np.conj(L), tau, L).real)
     assert abs(q.imag) < 1e-12 * abs(q)
     assert np.isclose(q.real, kappa * grad2 + ls, rtol=1e-12)
+
+
+# ---- backflow term on Neumann faces (cd.face_matrices) ----
+# One face, the right triangle (0,0,0), (2,0,0), (0,1,0): area 1, outward
+# normal +z.  Velocity uniform in space, so |A_n|_- is the same at the three
+# face points and the face integrals of N_a N_b are exact: area/12 (1 + d_ab).
+_FXYZ = np.array([[0.0, 0.0, 0.0], [2.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
+_FTRI = np.array([[0, 1, 2]])
+
+
+def _uniform_velocity(umodes):
+    return np.broadcast_to(umodes, (3,) + umodes.shape).copy()
+
+
+def test_face_backflow_steady_closed_form():
+    """K = 0: |A_n|_- = min(u.n, 0), so the block is
+    -(beta/2) min(u.n, 0) area/12 (1 + d_ab) (textbook backflow term)."""
+    beta = 0.7
+    for un in (-1.3, 0.4):
+        um = np.zeros((3, 1), complex)
+        um[2, 0] = un
+        Bf = cd.face_matrices(_FXYZ, _FTRI, _uniform_velocity(um), beta)
+        exact = -0.5 * beta * min(un, 0.0) * (1.0 / 12.0) * (np.ones((3, 3)) + np.eye(3))
+        assert np.allclose(Bf[0, :, :, 0, 0], exact, rtol=0, atol=1e-15)
+
+
+def test_face_backflow_vanishes_without_inflow():
+    """u.n(t) > 0 at all times: every eigenvalue of A_n is positive and the
+    term is exactly zero (it only acts where flow enters)."""
+    K2 = 2
+    um = np.zeros((3, 2 * K2 + 1), complex)
+    um[2, K2] = 1.0                            # u.n = 1 + 0.4 cos t + 0.2 sin 2t > 0
+    um[2, K2 + 1] = um[2, K2 - 1] = 0.2
+    um[2, K2 + 2], um[2, K2 - 2] = -0.1j, 0.1j
+    Bf = cd.face_matrices(_FXYZ, _FTRI, _uniform_velocity(um), 1.0)
+    assert np.abs(Bf).max() == 0.0
+
+
+def test_face_backflow_one_harmonic_trace():
+    """K = 1, u.n = a0 + a1 cos t: A_n is tridiagonal Toeplitz (diagonal a0,
+    off-diagonals a1/2) with eigenvalues a0 + a1 cos(k pi / 4), k = 1..3, so
+    trace(Bf[a, a]) = -(beta/2) (area/6) sum_k min(lambda_k, 0)."""
+    a0, a1, beta = -0.3, 1.0, 0.5
+    um = np.zeros((3, 3), complex)
+    um[2, 1] = a0
+    um[2, 0] = um[2, 2] = a1 / 2
+    Bf = cd.face_matrices(_FXYZ, _FTRI, _uniform_velocity(um), beta)
+    lam = a0 + a1 * np.cos(np.arange(1, 4) * np.pi / 4)
+    exact = -0.5 * beta * (1.0 / 6.0) * np.minimum(lam, 0.0).sum()
+    for a in range(3):
+        assert abs(np.trace(Bf[0, a, a]) - exact) <= 1e-14
+    # Hermitian negative part: the block is Hermitian and positive semidefinite
+    blk = Bf[0, 0, 0]
+    assert np.allclose(blk, blk.conj().T, atol=1e-15)
+    assert np.linalg.eigvalsh(blk).min() >= -1e-15
