@@ -145,7 +145,8 @@ int tsgls_set_dirichlet(tsgls_ctx* ctx, const int32_t* nodes, int64_t n);
 
 /* Neumann (outflow) faces: host tris [nf][3] node ids, ordered so that
  * (x1-x0) x (x2-x0) points out of the domain; h: host [nf][2K+2] traction
- * modes per face (slot layout, constant over the face) or NULL for h = 0.
+ * modes per face (slot layout, constant over the face) or NULL for h = 0
+ * (a context in tracer mode takes no traction: TSGLS_EINVAL).
  * Replaces any earlier set. */
 int tsgls_set_neumann(tsgls_ctx* ctx, const int32_t* tris, int64_t nf,
                       const double* h);
@@ -157,8 +158,12 @@ int tsgls_set_neumann(tsgls_ctx* ctx, const int32_t* tris, int64_t nf,
  * fields are copied).  States and residuals keep the [n_nodes][4][2K+2]
  * layout with the tracer in field 0 (fields 1..3 are zero in every
  * residual and product).  tsgls_set_dirichlet gives the tracer's Dirichlet
- * nodes (their values are those of the state passed to tsgls_solve); the
- * context must have no Neumann faces (zero diffusive flux elsewhere).
+ * nodes (their values are those of the state passed to tsgls_solve); on
+ * the faces given by tsgls_set_neumann (which must carry no traction, h =
+ * NULL) the operator includes the backflow term -(w, (beta/2)|A_n|_- phi)
+ * of the remark on backflow for the convection-diffusion equation (beta of
+ * tsgls_params, A_n from the frozen velocity); elsewhere the diffusive flux
+ * is zero.  Returns TSGLS_EINVAL if a traction has been set.
  * stabilized = 0 drops the least-squares term (tau = 0): the Galerkin
  * method.  In tracer mode tsgls_jv ignores the variant and dt_pseudo (the
  * operator is linear), tsgls_jacobi_diag returns ones (GMRES runs without a

@@ -555,7 +555,7 @@ k_gather(const int32_t* __restrict__ noff, const int32_t* __restrict__ ninc,
 #pragma unroll
     for (int r = 0; r < NJ; ++r) {
       const int j = lane + 64 * r, i = j / S, sl = j % S;
-      if (j < 3 * S && sl != 1) {
+      if (j < fs.nfield * S && sl != 1) {
         const int m = sl == 0 ? 0 : sl - 1;
         double o = 0.0;
         for (int kf = f0; kf < f1; ++kf) {

@@ -246,8 +246,9 @@ FaceSum face_sum(const tsgls_ctx* c, int resid) {
   fs.finc = c->finc;
   fs.fy = c->fy;
   fs.fgeo = c->fgeo;
-  fs.fh = c->fh;
+  fs.fh = c->tracer ? nullptr : c->fh;
   fs.resid = resid;
+  fs.nfield = c->tracer ? 1 : 3;   // the tracer is field 0 and has no traction
   return fs;
 }
 
@@ -273,15 +274,24 @@ int apply_operator(tsgls_ctx* c, const DevView& v, int mode, const double* Y, co
   return TSGLS_OK;
 }
 
-// Tracer operator applied to the modes in c->XP (element kernel + node sums).
-int apply_tracer(tsgls_ctx* c, double* out) {
+// Tracer operator applied to the modes in c->XP (element kernel + node sums)
+// and, on Neumann faces, its backflow term -(w, (beta/2)|A_n|_- phi) for the
+// input Y (times Ys when given; resid: Dirichlet entries of Y not masked).
+int apply_tracer(tsgls_ctx* c, double* out, const double* Y, const double* Ys, int resid) {
   DevView v = view(c);
+  if (c->nf) {
+    DevView vf = v;
+    vf.rho = 1.0;   // the tracer's backflow term carries no density
+    ProfScope ps(c, TSGLS_PROF_FACE);
+    HIPCHK(c, launch_face_point(vf, Y, Ys, resid, c->aneg, c->st));
+  }
   {
     ProfScope ps(c, TSGLS_PROF_ELEM_TANGENT);
     HIPCHK(c, launch_cd(v, c->XP, c->kappa, c->ebuf, 0, c->E, c->st));
   }
   ProfScope ps(c, TSGLS_PROF_GATHER);
-  HIPCHK(c, launch_gather(c->K, c->noff, c->ninc, c->nflag, c->ebuf, out, c->nn, c->st));
+  HIPCHK(c, launch_gather(c->K, c->noff, c->ninc, c->nflag, c->ebuf, out, c->nn, c->st,
+                          face_sum(c, resid)));
   return TSGLS_OK;
 }
 
@@ -299,11 +309,12 @@ int linearize_tracer(tsgls_ctx* c, const double* y, double* r) {
   } else {
     HIPCHK(c, launch_zero(c->tau, c->E * 4 * c->P, c->st));
   }
+  if (c->nf) HIPCHK(c, launch_face_lin(v, c->UT, c->aneg, c->st));   // |A_n|_- of the velocity
   c->linearized = true;
   c->lin32 = false;
   if (!r) return TSGLS_OK;
   HIPCHK(c, launch_prep_time(c->K, y, nullptr, c->nflag, 0, c->F, c->VT, c->XP, c->nn, c->st));
-  return apply_tracer(c, r);
+  return apply_tracer(c, r, y, nullptr, 1);
 }
 
 int linearize_impl(tsgls_ctx* c, const double* y, double* r) {
@@ -347,7 +358,7 @@ int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt, cons
   if (c->tracer) {   // the tracer operator is linear: its tangent is itself
     if (prec != TSGLS_PREC_F64) return fail(c, TSGLS_EINVAL, "the tracer operator runs in FP64 only");
     HIPCHK(c, launch_prep_time(c->K, x, xs, c->nflag, 1, c->F, c->VT, c->XP, c->nn, c->st));
-    return apply_tracer(c, out);
+    return apply_tracer(c, out, x, xs, 0);
   }
   DevView v = view(c);
   const int mode = jac == TSGLS_JAC_PICARD ? 0 : jac == TSGLS_JAC_PICARD_NOLS ? MODE_NOLS : MODE_NEWTON;
@@ -1004,6 +1015,7 @@ int tsgls_set_dirichlet(tsgls_ctx* c, const int32_t* nodes, int64_t n) {
 int tsgls_set_neumann(tsgls_ctx* c, const int32_t* tris, int64_t nf, const double* h) {
   if (!c) return TSGLS_EINVAL;
   if (nf < 0 || (nf > 0 && !tris)) return fail(c, TSGLS_EINVAL, "bad Neumann arguments");
+  if (c->tracer && h) return fail(c, TSGLS_EINVAL, "the tracer takes no Neumann traction");
   dfree(c, c->fconn);
   dfree(c, c->fgeo);
   dfree(c, c->fh);
@@ -1125,7 +1137,7 @@ int tsgls_set_tracer(tsgls_ctx* c, const double* y_velocity, double kappa, int s
   if (!c) return TSGLS_EINVAL;
   if (!y_velocity || !(kappa > 0) || !std::isfinite(kappa) || (stabilized != 0 && stabilized != 1))
     return fail(c, TSGLS_EINVAL, "bad tracer arguments");
-  if (c->nf) return fail(c, TSGLS_EINVAL, "the tracer context must have no Neumann faces");
+  if (c->fh) return fail(c, TSGLS_EINVAL, "the tracer context must have no Neumann traction");
   const int64_t n = ndof(c);
   if (!c->yvel) CHK(dalloc(c, &c->yvel, n));
   HIPCHK(c, launch_copy(y_velocity, c->yvel, n, c->st));

@@ -118,6 +118,7 @@ struct FaceSum {
   const double* fgeo = nullptr;
   const double* fh = nullptr;
   int resid = 0;
+  int nfield = 3;   // leading fields that receive face terms (3 velocity; 1 for the tracer)
 };
 // out[node][4][S] = sum over incident (element, local node) of the ebuf rows
 // mapped from positions to slots, in ascending element order (deterministic),
