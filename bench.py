@@ -562,11 +562,52 @@ def tracer(args):
                              phi_min=float("%.3e" % vals.min()), phi_max=float("%.3e" % vals.max())))
             print(runs[-1], file=sys.stderr, flush=True)
             del s
+    # Backflow: a reversing inflow Q(t) = Qbar (1 + 1.6 sin wt) makes fluid re-enter through the
+    # outlet for part of the period; the outlet is a natural boundary of the tracer
+    # (phi = 1 + 0.5 cos wt at the inlet only), with the backflow term at beta = 0.5 and without
+    # it (beta = 0), for two diffusivities.
+    pb = womersley_problem(4, 16, K=3, amp=1.6)
+    nsb = T.Solver.from_problem(pb)
+    yb = torch.from_numpy(initial_guess(pb)).cuda()
+    stb = nsb.solve(yb, rtol=1e-8, restart=30, max_newton=60)
+    outl = nodes(pb.mesh.faces["outlet"])
+    ub = yb.cpu().numpy()[outl, 2]                       # axial velocity = u.n on the outlet
+    cu = ub[:, 0::2] + 1j * ub[:, 1::2]
+    cu[:, 0] = ub[:, 0]
+    uz = cu[:, :1].real + 2 * np.real(sum(cu[:, k:k + 1] * np.exp(1j * k * t)[None, :]
+                                          for k in range(1, K + 1)))
+    dnb = np.setdiff1d(nodes(pb.mesh.faces["inlet"]), nodes(pb.mesh.faces["wall"]))
+    back = []
+    for kappa, beta in ((0.005, 0.5), (0.005, 0.0), (0.001, 0.5), (0.001, 0.0)):
+        s = T.Solver(pb.mesh.xyz, pb.mesh.tets, K, pb.rho, pb.mu, pb.omega, backflow_beta=beta)
+        s.set_dirichlet(dnb.astype(np.int32))
+        s.set_neumann(np.asarray(pb.mesh.faces["outlet"], dtype=np.int32))
+        s.set_tracer(yb, kappa, True)
+        y0 = np.zeros((pb.mesh.n_nodes, 4, 2 * K + 2))
+        y0[dnb, 0, 0] = 1.0
+        y0[dnb, 0, 2] = 0.25                            # Re c_1: 0.5 cos wt
+        y = torch.from_numpy(y0).cuda()
+        st = s.solve(y, rtol=1e-8, lin_rtol=1e-8, restart=100, max_newton=1, max_matvec=20000)
+        ph = y.cpu().numpy()[:, 0]
+        c = ph[:, 0::2] + 1j * ph[:, 1::2]
+        c[:, 0] = ph[:, 0]
+        vals = c[:, :1].real + 2 * np.real(sum(c[:, k:k + 1] * np.exp(1j * k * t)[None, :]
+                                               for k in range(1, K + 1)))
+        back.append(dict(kappa=kappa, beta=beta, converged=st["status"] == 0, gmres_products=st["matvecs"],
+                         rel_residual=float("%.2e" % st["rel_residual"]),
+                         phi_min=float("%.3e" % vals.min()), phi_max=float("%.3e" % vals.max())))
+        print(back[-1], file=sys.stderr, flush=True)
+        del s
     print(json.dumps({"metric": "tracer: GLS vs Galerkin, GMRES products to 1e-8 and range of phi",
                       "n_gpus": 1, "data": "synthetic (converged pipe flow)",
                       "config": dict(workload="womersley_6k_K3_tracer", n_tets=prob.mesh.n_tets, K=K,
                                      restart=100, preconditioner="none"),
-                      "runs": runs}), flush=True)
+                      "runs": runs,
+                      "backflow": dict(flow="Q(t) = Qbar (1 + 1.6 sin wt)", method="GLS",
+                                       inlet_phi="1 + 0.5 cos wt",
+                                       ns_converged=stb["status"] == 0,
+                                       outlet_min_axial_velocity=float("%.3e" % uz.min()),
+                                       runs=back)}), flush=True)
 
 
 def main():
