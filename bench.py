@@ -392,19 +392,26 @@ def learned(args):
     probs, feats = pipe_family(ntr + nte, K=3, seed=11)
     opts = dict(lin_rtol=0.05, restart=30, max_newton=60)
     t0 = time.perf_counter()
-    solvers = [T.Solver.from_problem(probs[i], stream=torch.cuda.Stream()) for i in range(ntr)]
-    ys = [torch.from_numpy(initial_guess(probs[i])).cuda() for i in range(ntr)]
-    torch.cuda.synchronize()
     print(f"solving {ntr} training members", file=sys.stderr, flush=True)
-    rc, st, _ = T.solve_batch(solvers, ys, rtol=1e-9, max_concurrent=8, **opts)
+    ys, rcs, chunk = [], [], 512     # contexts made and freed per chunk (device memory)
+    for c0 in range(0, ntr, chunk):
+        idx = range(c0, min(ntr, c0 + chunk))
+        solvers = [T.Solver.from_problem(probs[i], stream=torch.cuda.Stream()) for i in idx]
+        yc = [torch.from_numpy(initial_guess(probs[i])).cuda() for i in idx]
+        torch.cuda.synchronize()
+        rc, st, _ = T.solve_batch(solvers, yc, rtol=1e-9, max_concurrent=8, **opts)
+        rcs.append(rc)
+        ys += yc
+        del solvers
+        print(f"  {len(ys)} solved", file=sys.stderr, flush=True)
+    rc = next((x for x in rcs if x != 0), 0)
     t_data = time.perf_counter() - t0
     print(f"training data in {t_data:.1f} s", file=sys.stderr, flush=True)
-    del solvers
     Y = torch.stack([y.view(-1) for y in ys]).contiguous()
     del ys
     t0 = time.perf_counter()
-    ws = WarmStart.fit(feats[:ntr], Y, r=r, steps=args.learned_steps, lr=1e-3, seed=1,
-                       precision=args.learned_precision)
+    ws = WarmStart.fit(feats[:ntr], Y, r=r, n_hidden=args.learned_hidden, steps=args.learned_steps,
+                       lr=1e-3, seed=1, precision=args.learned_precision)
     torch.cuda.synchronize()
     t_fit = time.perf_counter() - t0
     rows = []
@@ -455,7 +462,7 @@ def learned(args):
         "metric": "learned warm start: Newton steps and time to 1e-8 vs the plain initial guess",
         "n_gpus": 1, "data": "synthetic (seeded pipe inflow waveforms, Re, Wo)",
         "config": dict(workload="womersley_6k_K3_family", n_tets=probs[0].mesh.n_tets, K=3,
-                       n_train=ntr, n_test=nte, basis=int(ws.Phi.shape[0]), net="8-512x3-r tanh",
+                       n_train=ntr, n_test=nte, basis=int(ws.Phi.shape[0]), net=f"8-512x{args.learned_hidden}-r tanh",
                        precision=("bf16 MFMA, FP32 master weights" if args.learned_precision == "bf16"
                                   else "FP32 MFMA"), steps=args.learned_steps),
         "train": dict(data_s=round(t_data, 3), all_converged=rc == 0, fit_s=round(t_fit, 3),
@@ -641,6 +648,7 @@ def main():
     ap.add_argument("--learned-test", type=int, default=32)
     ap.add_argument("--learned-basis", type=int, default=64)
     ap.add_argument("--learned-steps", type=int, default=3000)
+    ap.add_argument("--learned-hidden", type=int, default=4, help="hidden layers of width 512")
     ap.add_argument("--learned-precision", default="bf16", choices=["bf16", "f32"])
     args = ap.parse_args()
     if args.summarize_issue:

@@ -233,7 +233,8 @@ int tsgls_solve_batch(tsgls_ctx* const* ctxs, double* const* ys, int nb,
  * network's training data are solutions of the method itself.
  *
  * Reduced basis (all arrays device FP64, vectors of length D, row-major):
- * tsgls_rb_greedy picks, r times, the snapshot of Y [N][D] (N <= 1024)
+ * tsgls_rb_greedy picks, r times, the snapshot of Y [N][D] (N <= 65536,
+ * r <= min(N, 1024))
  * worst represented by the basis so far (largest |y - mean - P(y - mean)|),
  * orthonormalizes it against the basis (classical Gram-Schmidt, two passes)
  * and stores it in Phi [r][D]; picked (host [r]) receives the snapshot

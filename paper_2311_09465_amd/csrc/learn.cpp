@@ -260,7 +260,7 @@ void tsgls_mlp_destroy(tsgls_mlp* m) {
 // ------------------------------------------------------------ reduced basis
 int tsgls_rb_greedy(const double* Y, int64_t N, int64_t D, const double* mean, int r, double* Phi,
                     int32_t* picked, void* hip_stream) {
-  if (!Y || !mean || !Phi || !picked || N < 1 || N > 1024 || D < 1 || r < 1 || r > N)
+  if (!Y || !mean || !Phi || !picked || N < 1 || N > 65536 || D < 1 || r < 1 || r > N || r > 1024)
     return TSGLS_EINVAL;
   hipStream_t st = (hipStream_t)hip_stream;
   const int nb = multidot_blocks(D);
@@ -270,7 +270,7 @@ int tsgls_rb_greedy(const double* Y, int64_t N, int64_t D, const double* mean, i
   std::vector<char> used(N, 0);
   RHIP(hipMalloc(&Yc, sizeof(double) * (size_t)N * D));
   RHIP(hipMalloc(&partial, sizeof(double) * (size_t)nb * 1024));
-  RHIP(hipMalloc(&dd, sizeof(double) * 2048));
+  RHIP(hipMalloc(&dd, sizeof(double) * (size_t)std::max<int64_t>(2048, N)));
   // centered snapshots and their squared norms
   RHIP(launch_copy(Y, Yc, N * D, st));
   for (int64_t i = 0; i < N; ++i) RHIP(launch_axpy(-1.0, mean, Yc + i * D, D, st));
@@ -306,9 +306,12 @@ int tsgls_rb_greedy(const double* Y, int64_t N, int64_t D, const double* mean, i
       RHIP(hipStreamSynchronize(st));
       if (!(h[0] > 1e-24 * top)) break;
       RHIP(launch_scal_copy(1.0 / std::sqrt(h[0]), phi, phi, D, st));
-      // coefficients of every snapshot on the new basis vector
-      RHIP(launch_multidot(Yc, D, (int)N, phi, partial, nb, D, st));
-      RHIP(launch_reduce_partials(partial, nb, (int)N, dd, st));
+      // coefficients of every snapshot on the new basis vector (1,024 rows per pass)
+      for (int64_t i0 = 0; i0 < N; i0 += 1024) {
+        const int J = (int)std::min<int64_t>(1024, N - i0);
+        RHIP(launch_multidot(Yc + i0 * D, D, J, phi, partial, nb, D, st));
+        RHIP(launch_reduce_partials(partial, nb, J, dd + i0, st));
+      }
       RHIP(hipMemcpyAsync(c.data(), dd, sizeof(double) * N, hipMemcpyDeviceToHost, st));
       RHIP(hipStreamSynchronize(st));
       for (int64_t i = 0; i < N; ++i) proj[i] += c[i] * c[i];

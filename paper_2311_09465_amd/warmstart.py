@@ -32,10 +32,13 @@ class WarmStart:
         """features: host [N][F]; Y: solutions, float64 CUDA [N][D]."""
         import torch
         N, D = Y.shape
-        ones = torch.full((N,), 1.0 / N, dtype=torch.float64, device=Y.device)
-        zero = torch.zeros(D, dtype=torch.float64, device=Y.device)
+        w = torch.full((min(N, 1024),), 1.0 / N, dtype=torch.float64, device=Y.device)
+        acc = torch.zeros(D, dtype=torch.float64, device=Y.device)
         mean = torch.empty(D, dtype=torch.float64, device=Y.device)
-        rb_expand(Y, ones, zero, mean)                      # mean = sum_i Y_i / N
+        for i0 in range(0, N, 1024):                        # mean = sum_i Y_i / N, 1,024 rows a pass
+            i1 = min(N, i0 + 1024)
+            rb_expand(Y[i0:i1], w[:i1 - i0], acc, mean)
+            acc.copy_(mean)
         Phi, _ = rb_greedy(Y, mean, r)
         coef = rb_project(Phi, Y, mean).cpu().numpy()
         F = np.asarray(features, dtype=np.float64)

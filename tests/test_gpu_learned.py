@@ -104,6 +104,23 @@ def test_reduced_basis_matches_oracle():
     assert np.abs(to_host(y) - (mean + coef[3] @ Po)).max() <= 1e-10 * np.abs(mean).max()
 
 
+def test_reduced_basis_more_snapshots_than_one_pass():
+    """N = 1,100 snapshots: the coefficients of the snapshots on each new basis
+    vector are formed 1,024 rows at a time; same result as the reference."""
+    log("[gpu] reduced basis, 1,100 snapshots")
+    import paper_2311_09465_amd as T
+    rng = np.random.default_rng(12)
+    D, N = 400, 1100
+    Q, _ = np.linalg.qr(rng.standard_normal((D, 5)))
+    mean = rng.standard_normal(D)
+    C = rng.standard_normal((N, 5)) * np.array([7.0, 4.0, 2.5, 1.5, 1.0])
+    Y = mean + C @ Q.T + 1e-3 * rng.standard_normal((N, D))
+    Phi, picked = T.rb_greedy(to_dev(Y), to_dev(mean), 4)
+    Po, pk = OM.greedy_basis(Y, mean, 4)
+    assert picked == pk
+    assert np.abs(to_host(Phi) - Po).max() <= 1e-10
+
+
 def test_learned_warm_start_on_pipe_family():
     import torch
     import paper_2311_09465_amd as T
