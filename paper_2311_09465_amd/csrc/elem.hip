@@ -546,9 +546,10 @@ k_gather(const int32_t* __restrict__ noff, const int32_t* __restrict__ ninc,
     for (int r = 0; r < NJ; ++r)
       if (src[r] >= 0) acc[r] += ebuf[i0 + src[r]];
   }
-  // face terms of a Neumann node: per velocity slot, the sum over its
-  // incident faces (ascending) of the three face points weighted by the
-  // vertex's P1 value there, minus the traction term for the residual
+  // face terms of a Neumann node: per slot of the leading fs.nfield fields
+  // (velocity, or the tracer), the sum over its incident faces (ascending) of
+  // the three face points weighted by the vertex's P1 value there, minus the
+  // traction term for the residual
   const int u = (fs.nfidx && !dir) ? fs.nfidx[node] : -1;
   if (u >= 0) {
     const int f0 = fs.foff[u], f1 = fs.foff[u + 1];

@@ -234,9 +234,6 @@ struct ProfScope {
   }
 };
 
-// Volume + face terms of the operator into out (overwritten).  The input's
-// modes must already be in c->XP (launch_prep_time); Y is the input vector
-// itself (face terms).
 // Face terms for the node gather (none without Neumann faces).
 FaceSum face_sum(const tsgls_ctx* c, int resid) {
   FaceSum fs;
@@ -252,8 +249,11 @@ FaceSum face_sum(const tsgls_ctx* c, int resid) {
   return fs;
 }
 
-// faces_ready: the face points of Y were formed with its nodal samples
-// (launch_prep_time with the face view), so they are not launched here.
+// Volume + face terms of the operator into out (overwritten).  The input's
+// modes must already be in c->XP (launch_prep_time); Y is the input vector
+// itself (face terms).  faces_ready: the face points of Y were formed with
+// its nodal samples (launch_prep_time with the face view), so they are not
+// launched here.
 int apply_operator(tsgls_ctx* c, const DevView& v, int mode, const double* Y, const double* VTp,
                    double* Zout, double* out, double shift, const double* an, int resid,
                    const double* Ys = nullptr, bool faces_ready = false) {
