@@ -113,7 +113,8 @@ typedef struct {
                         first use of a (restart, tangent, dt_pseudo, precision)
                         and replayed; one host synchronization per cycle, cycles
                         always make restart products (whole cycles count against
-                        max_matvec, the first cycle always runs) */
+                        max_matvec, the first cycle always runs); with
+                        restart > 32 the flag is ignored */
 } tsgls_solve_opts;
 
 typedef struct {
