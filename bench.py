@@ -261,7 +261,7 @@ def summarize_issue(csvs):
         "# Commands (repository root, one MI355X), one rocprofv3 run per counter pass:",
     ]
     for i, ctr in enumerate(ISSUE_PASSES):
-        lines.append(f"#   rocprofv3 --pmc {ctr} --output-format csv -d gpurun_out/issue{'ABC'[i]} "
+        lines.append(f"#   rocprofv3 --pmc {ctr} --output-format csv -d rocprof_out/issue{'ABC'[i]} "
                      f"-o {'abc'[i]} -- python -u bench.py --probe")
     lines.append("#   python bench.py --summarize-issue <issueA csv> <issueB csv> <issueC csv>")
     lines.append("# Values are per dispatch (averaged over the probe's dispatches of the kernel);")
@@ -656,11 +656,11 @@ def main():
         return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc,
-                      "rocprofv3 --pmc {counter} --output-format csv -d gpurun_out/{d} -o p -- "
+                      "rocprofv3 --pmc {counter} --output-format csv -d rocprof_out/{d} -o p -- "
                       "python bench.py --probe")
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it "
+        print(json.dumps({"error": "the library runs on one GPU; multi-GPU runs are not implemented "
                           "(mesh-partition sharding is described in the design notes)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
