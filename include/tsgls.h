@@ -22,7 +22,9 @@
  *                "Pseudo-time stepping");
  *   solve     -- Newton-Raphson (eq. NR) with right-Jacobi-preconditioned
  *                restarted GMRES, stopped at ||r|| <= rtol ||r^0|| (remarks
- *                after eq. K_mat).
+ *                after eq. K_mat); or pseudo-time stepping with one Newton
+ *                iteration per pseudo-time step and an adaptive step size
+ *                (section "Pseudo-time stepping").
  *
  * Conventions shared by every entry point
  *   Mode count   K = number of harmonics (the paper's N is K+1).
@@ -84,6 +86,27 @@ extern "C" {
 #define TSGLS_PREC_F64 0
 #define TSGLS_PREC_F32 1
 
+/* Pseudo-time schedule of tsgls_solve (section "Pseudo-time stepping": one
+ * Newton iteration per pseudo-time step, the tangent shifted by
+ * 1.5 rho / dt (N_A, N_B); the converged solution does not depend on it).
+ *   TSGLS_DT_FIXED  every step uses dt_pseudo (<= 0: no shift, plain Newton).
+ *   TSGLS_DT_SER    the first step uses dt_pseudo > 0; after each step the
+ *                   size is multiplied by ||r_old|| / ||r_new|| clipped to
+ *                   [0.1, 10] (switched evolution relaxation), and bounded
+ *                   by dt_max if dt_max > 0 (else it grows without bound and
+ *                   the shift is dropped once dt exceeds 1e12).
+ *   TSGLS_DT_AUTO   plain Newton steps while the residual falls; after three
+ *                   consecutive steps whose residual ratio exceeds 0.99 (a
+ *                   stall) or one rejected step, continues as TSGLS_DT_SER
+ *                   from dt_pseudo > 0.
+ * Under SER and AUTO a step whose residual is non-finite or grows by more
+ * than 1e3 is rejected: y returns to the previous iterate and the next step
+ * size is a tenth of the rejected one (a rejected step counts as a Newton
+ * iteration). */
+#define TSGLS_DT_FIXED 0
+#define TSGLS_DT_SER 1
+#define TSGLS_DT_AUTO 2
+
 typedef struct tsgls_ctx tsgls_ctx;
 
 typedef struct {
@@ -115,6 +138,8 @@ typedef struct {
                         always make restart products (whole cycles count against
                         max_matvec, the first cycle always runs); with
                         restart > 32 the flag is ignored */
+  int dt_schedule;   /* TSGLS_DT_FIXED (0, default), TSGLS_DT_SER, TSGLS_DT_AUTO */
+  double dt_max;     /* SER / AUTO: upper bound of the pseudo-time step (<= 0: none) */
 } tsgls_solve_opts;
 
 typedef struct {
@@ -125,6 +150,9 @@ typedef struct {
   double r0_norm;         /* ||r^0|| (Euclidean norm of the masked slot vector) */
   double seconds;         /* wall time of the solve */
   double history[64];     /* ||r||/||r^0|| after each Newton step (first 64) */
+  int rejected;           /* pseudo-time steps rejected (SER / AUTO) */
+  int switched_at;        /* AUTO: Newton iteration at which pseudo-time began, -1 if never */
+  double dt_last;         /* pseudo-time step of the last iteration (0: no shift) */
 } tsgls_solve_stats;
 
 /* Harmonic counts compiled into this library: writes up to cap values into

@@ -19,6 +19,7 @@ TSGLS_OK = 0
 TSGLS_NOT_CONVERGED = 1
 JAC = {"picard": 0, "picard_nols": 1, "newton": 2}
 PREC = {"f64": 0, "f32": 1}
+DT_SCHEDULE = {"fixed": 0, "ser": 1, "auto": 2}
 ERRORS = {-1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "EMESH", -5: "ENONFINITE", -6: "ESTATE"}
 
 
@@ -31,13 +32,14 @@ class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("lin_rtol", C.c_double), ("restart", C.c_int),
                 ("max_newton", C.c_int), ("max_matvec", C.c_int), ("jacobian", C.c_int),
                 ("dt_pseudo", C.c_double), ("verbose", C.c_int), ("tangent_precision", C.c_int),
-                ("gmres_graph", C.c_int)]
+                ("gmres_graph", C.c_int), ("dt_schedule", C.c_int), ("dt_max", C.c_double)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("newton_iters", C.c_int), ("matvecs", C.c_int), ("status", C.c_int),
                 ("rel_residual", C.c_double), ("r0_norm", C.c_double), ("seconds", C.c_double),
-                ("history", C.c_double * 64)]
+                ("history", C.c_double * 64), ("rejected", C.c_int), ("switched_at", C.c_int),
+                ("dt_last", C.c_double)]
 
 
 class TsglsError(RuntimeError):
@@ -110,21 +112,23 @@ def _host(a, dtype):
 
 
 def _opts(rtol, lin_rtol, restart, max_newton, max_matvec, jacobian, dt_pseudo, verbose,
-          tangent_precision, gmres_graph=False):
+          tangent_precision, gmres_graph=False, dt_schedule="fixed", dt_max=0.0):
     return SolveOpts(rtol, lin_rtol, restart, max_newton, max_matvec, JAC[jacobian],
                      float(dt_pseudo or 0.0), int(verbose), PREC[tangent_precision],
-                     int(bool(gmres_graph)))
+                     int(bool(gmres_graph)), DT_SCHEDULE[dt_schedule], float(dt_max or 0.0))
 
 
 def _stats_dict(rc, st):
     return dict(status=rc, newton_iters=st.newton_iters, matvecs=st.matvecs,
                 rel_residual=st.rel_residual, r0_norm=st.r0_norm, seconds=st.seconds,
-                history=list(st.history[:min(64, st.newton_iters)]))
+                history=list(st.history[:min(64, st.newton_iters)]), rejected=st.rejected,
+                switched_at=st.switched_at, dt_last=st.dt_last)
 
 
 def solve_batch(solvers, ys, rtol=1e-8, lin_rtol=0.05, restart=100, max_newton=50,
                 max_matvec=10000, jacobian="picard", dt_pseudo=0.0, verbose=False,
-                tangent_precision="f64", max_concurrent=8, gmres_graph=False):
+                tangent_precision="f64", max_concurrent=8, gmres_graph=False,
+                dt_schedule="fixed", dt_max=0.0):
     """tsgls_solve_batch: solve every (solver, y) pair with the same options,
     up to max_concurrent at a time.  Returns (status, per-solve stats dicts,
     per-solve finish times in seconds from the call's start)."""
@@ -134,7 +138,7 @@ def solve_batch(solvers, ys, rtol=1e-8, lin_rtol=0.05, restart=100, max_newton=5
     hs = (C.c_void_p * max(nb, 1))(*[s._h.value for s in solvers])
     yp = (C.c_void_p * max(nb, 1))(*[s._vec(y, "y").value for s, y in zip(solvers, ys)])
     o = _opts(rtol, lin_rtol, restart, max_newton, max_matvec, jacobian, dt_pseudo, verbose,
-              tangent_precision, gmres_graph)
+              tangent_precision, gmres_graph, dt_schedule, dt_max)
     st = (SolveStats * max(nb, 1))()
     fin = (C.c_double * max(nb, 1))()
     rc = lib().tsgls_solve_batch(hs, yp, nb, C.byref(o), C.cast(st, C.c_void_p),
@@ -237,9 +241,9 @@ class Solver:
 
     def solve(self, y, rtol=1e-8, lin_rtol=0.05, restart=100, max_newton=50, max_matvec=10000,
               jacobian="picard", dt_pseudo=0.0, verbose=False, tangent_precision="f64",
-              gmres_graph=False):
+              gmres_graph=False, dt_schedule="fixed", dt_max=0.0):
         o = _opts(rtol, lin_rtol, restart, max_newton, max_matvec, jacobian, dt_pseudo, verbose,
-                  tangent_precision, gmres_graph)
+                  tangent_precision, gmres_graph, dt_schedule, dt_max)
         st = SolveStats()
         rc = self._check(lib().tsgls_solve(self._h, self._vec(y, "y"), C.byref(o), C.byref(st)), "solve")
         return _stats_dict(rc, st)

@@ -61,6 +61,7 @@ struct tsgls_ctx {
   double* kx = nullptr;
   double* kt = nullptr;
   double* kt2 = nullptr;
+  double* ybak = nullptr;       // previous iterate (rejected pseudo-time steps)
   double* minv = nullptr;
   double* partial = nullptr;
   double* dh = nullptr;
@@ -429,8 +430,22 @@ int norm2(tsgls_ctx* c, const double* x, double* nrm) {
   return TSGLS_OK;
 }
 
+// A captured GMRES cycle holds the device addresses of the Krylov basis, of
+// the face arrays and of the operator it was captured with.  Every call that
+// frees or replaces one of them, or switches the operator, drops the graph,
+// so that the next graph solve captures a fresh one.
+void drop_graph(tsgls_ctx* c) {
+  if (c->gexec) {
+    if (c->gst) (void)hipStreamSynchronize(c->gst);
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  c->gkey = tsgls_ctx::GraphKey{};
+}
+
 int ensure_krylov(tsgls_ctx* c, int m) {
   if (c->m_alloc >= m) return TSGLS_OK;
+  drop_graph(c);
   dfree(c, c->V);
   c->V = nullptr;
   const int64_t n = ndof(c);
@@ -439,6 +454,7 @@ int ensure_krylov(tsgls_ctx* c, int m) {
     CHK(dalloc(c, &c->kx, n));
     CHK(dalloc(c, &c->kt, n));
     CHK(dalloc(c, &c->kt2, n));
+    CHK(dalloc(c, &c->ybak, n));
     CHK(dalloc(c, &c->minv, n));
     CHK(dalloc(c, &c->partial, (size_t)multidot_blocks(n) * 1024));
     CHK(dalloc(c, &c->dh, 4096));
@@ -546,8 +562,10 @@ int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, i
         bbq += bq[i] * bq[i];
       }
       const double nu = std::sqrt(std::max(uu - aa, 0.0));
-      if (!(nu > 0.0)) {   // u_j in span(Q): column j-1 ends the Krylov space
+      if (!(nu > 0.0)) {   // u_j = Q a lies in span(Q): column j-1 ends the Krylov space
         if (j >= 1) {
+          const double sj = H(j, j - 1);
+          for (int i = 0; i < j; ++i) H(i, j - 1) += sj * a[i];
           H(j, j - 1) = 0.0;
           commit(j - 1);
         }
@@ -1016,6 +1034,7 @@ int tsgls_set_neumann(tsgls_ctx* c, const int32_t* tris, int64_t nf, const doubl
   if (!c) return TSGLS_EINVAL;
   if (nf < 0 || (nf > 0 && !tris)) return fail(c, TSGLS_EINVAL, "bad Neumann arguments");
   if (c->tracer && h) return fail(c, TSGLS_EINVAL, "the tracer takes no Neumann traction");
+  drop_graph(c);
   dfree(c, c->fconn);
   dfree(c, c->fgeo);
   dfree(c, c->fh);
@@ -1139,6 +1158,7 @@ int tsgls_set_tracer(tsgls_ctx* c, const double* y_velocity, double kappa, int s
     return fail(c, TSGLS_EINVAL, "bad tracer arguments");
   if (c->fh) return fail(c, TSGLS_EINVAL, "the tracer context must have no Neumann traction");
   const int64_t n = ndof(c);
+  drop_graph(c);
   if (!c->yvel) CHK(dalloc(c, &c->yvel, n));
   HIPCHK(c, launch_copy(y_velocity, c->yvel, n, c->st));
   c->tracer = true;
@@ -1203,10 +1223,15 @@ int tsgls_solve(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_
   if (!y || !o) return fail(c, TSGLS_EINVAL, "null argument");
   if (o->restart < 1 || o->restart > 1000 || o->max_newton < 0 || o->max_matvec < 1 || !(o->rtol > 0) ||
       !(o->lin_rtol > 0) || o->jacobian < 0 || o->jacobian > 2 ||
-      (o->tangent_precision != TSGLS_PREC_F64 && o->tangent_precision != TSGLS_PREC_F32))
+      (o->tangent_precision != TSGLS_PREC_F64 && o->tangent_precision != TSGLS_PREC_F32) ||
+      o->dt_schedule < TSGLS_DT_FIXED || o->dt_schedule > TSGLS_DT_AUTO || !std::isfinite(o->dt_max) ||
+      !std::isfinite(o->dt_pseudo))
     return fail(c, TSGLS_EINVAL, "bad solve options");
+  if (o->dt_schedule != TSGLS_DT_FIXED && !(o->dt_pseudo > 0))
+    return fail(c, TSGLS_EINVAL, "an adaptive pseudo-time schedule needs dt_pseudo > 0");
   const auto t0 = std::chrono::steady_clock::now();
   tsgls_solve_stats st{};
+  st.switched_at = -1;
   CHK(ensure_krylov(c, o->restart));
   const int64_t n = ndof(c);
   double* r = c->rs;
@@ -1218,6 +1243,12 @@ int tsgls_solve(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_
   double rn = r0;
   int it = 0;
   int status = TSGLS_NOT_CONVERGED;
+  // pseudo-time state: dt of the next step (0 = no shift), whether the
+  // schedule adapts it, and the stall counter of the AUTO schedule
+  const bool adaptive = o->dt_schedule != TSGLS_DT_FIXED;
+  bool ser = o->dt_schedule == TSGLS_DT_SER;
+  double dt = o->dt_schedule == TSGLS_DT_AUTO ? 0.0 : o->dt_pseudo;
+  int slow = 0;
   for (;;) {
     const double rel = r0 > 0 ? rn / r0 : 0.0;
     st.rel_residual = rel;
@@ -1227,27 +1258,64 @@ int tsgls_solve(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_
       break;
     }
     if (it >= o->max_newton) break;
-    CHK(diag_impl(c, c->minv, o->dt_pseudo));
+    CHK(diag_impl(c, c->minv, dt));
     HIPCHK(c, launch_recip(c->minv, n, c->st));
-    // b = -r in kt2 is overwritten inside gmres; keep it in the last Krylov slot-free buffer
+    // b = -r in place (r is recomputed after the update)
     HIPCHK(c, launch_scal_copy(-1.0, r, r, n, c->st));
     int mv = 0;
     if (o->restart <= 32 && o->gmres_graph)
-      CHK(gmres_graph(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, o->dt_pseudo,
+      CHK(gmres_graph(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, dt,
                       o->tangent_precision, &mv));
     else if (o->restart <= GS_DELAYED_MAX)
-      CHK(gmres_delayed(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, o->dt_pseudo,
+      CHK(gmres_delayed(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, dt,
                         o->tangent_precision, &mv));
     else
-      CHK(gmres(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, o->dt_pseudo,
+      CHK(gmres(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, dt,
                 o->tangent_precision, &mv));
     st.matvecs += mv;
+    if (adaptive) HIPCHK(c, launch_copy(y, c->ybak, n, c->st));
     HIPCHK(c, launch_axpy(1.0, c->kx, y, n, c->st));
     CHK(linearize_impl(c, y, r));
-    CHK(norm2(c, r, &rn));
-    if (!std::isfinite(rn)) return fail(c, TSGLS_ENONFINITE, "non-finite residual at Newton step %d", it + 1);
+    double rnew;
+    CHK(norm2(c, r, &rnew));
     ++it;
-    if (o->verbose) fprintf(stderr, "tsgls newton %d: |r|/|r0| = %.3e  gmres %d\n", it, rn / r0, mv);
+    st.dt_last = dt;
+    if (adaptive && (!std::isfinite(rnew) || rnew > 1e3 * rn)) {
+      // rejected: back to the previous iterate, a tenth of the step (a
+      // rejected plain Newton step starts the pseudo-time schedule)
+      HIPCHK(c, launch_copy(c->ybak, y, n, c->st));
+      CHK(linearize_impl(c, y, r));
+      ++st.rejected;
+      if (!ser) {
+        ser = true;
+        st.switched_at = it;
+        dt = o->dt_pseudo;
+      } else {
+        dt = (dt > 0 ? dt : o->dt_pseudo) * 0.1;
+      }
+      if (o->verbose)
+        fprintf(stderr, "tsgls step %d rejected (|r|/|r0| %.3e), next dt %.3g\n", it, rnew / r0, dt);
+      continue;
+    }
+    if (!std::isfinite(rnew)) return fail(c, TSGLS_ENONFINITE, "non-finite residual at Newton step %d", it);
+    if (o->verbose)
+      fprintf(stderr, "tsgls newton %d: |r|/|r0| = %.3e  gmres %d  dt %.3g\n", it, rnew / r0, mv, dt);
+    if (ser) {
+      // switched evolution relaxation: dt grows as the residual falls
+      if (dt > 0) {
+        dt *= std::min(10.0, std::max(0.1, rn / rnew));
+        if (o->dt_max > 0) dt = std::min(dt, o->dt_max);
+        else if (dt > 1e12) dt = 0.0;
+      }
+    } else if (o->dt_schedule == TSGLS_DT_AUTO) {
+      slow = rnew > 0.99 * rn ? slow + 1 : 0;
+      if (slow >= 3) {   // plain Newton has stalled: continue in pseudo-time
+        ser = true;
+        st.switched_at = it;
+        dt = o->dt_pseudo;
+      }
+    }
+    rn = rnew;
   }
   HIPCHK(c, hipStreamSynchronize(c->st));
   st.newton_iters = it;

@@ -60,3 +60,34 @@ def test_graph_solve_cross_evaluated_by_oracle(prec):
     r = np.linalg.norm(O.residual(par, prob.mesh.xyz, prob.mesh.tets, to_host(y)))
     log(f"[gpu]   newton {st['newton_iters']} matvecs {st['matvecs']} oracle rel {r / r0:.2e}")
     assert r <= 1e-8 * r0
+
+
+def test_graph_recaptured_after_basis_and_faces_change():
+    """A captured cycle holds the addresses of the Krylov basis and the face
+    arrays.  A larger host-driven restart reallocates the basis and a new
+    Neumann set replaces the face arrays; the next graph solve must capture
+    afresh and match the host-driven GMRES (restart 16 each time)."""
+    import torch
+    import paper_2311_09465_amd as T
+    prob = cube_problem(3, K=2)
+    log("[gpu] graph GMRES after the basis and the face arrays are replaced")
+    kw = dict(rtol=1e-300, lin_rtol=1e-300, max_newton=1, max_matvec=16)
+    s = T.Solver.from_problem(prob)
+    y0 = initial_guess(prob)
+
+    def pair(tag):
+        ya, yb = to_dev(y0), to_dev(y0)
+        torch.cuda.synchronize()
+        s.solve(ya, restart=16, **kw)
+        s.solve(yb, restart=16, gmres_graph=True, **kw)
+        a, b = to_host(ya), to_host(yb)
+        err = np.abs(a - b).max() / np.abs(a).max()
+        log(f"[gpu]   {tag}: rel diff {err:.2e}")
+        assert err <= 1e-10
+
+    pair("first capture")
+    yc = to_dev(y0)
+    s.solve(yc, restart=100, **kw)          # host-driven, grows the basis
+    pair("after the basis grew")
+    s.set_neumann(prob.neumann_tris, prob.neumann_h)
+    pair("after a new Neumann set")
