@@ -69,6 +69,8 @@ extern "C" {
 #define TSGLS_EMESH (-4)       /* non-positive tet volume, bad index, degenerate face */
 #define TSGLS_ENONFINITE (-5)  /* NaN/Inf in the residual or a Krylov quantity */
 #define TSGLS_ESTATE (-6)      /* jv / jacobi_diag before linearize */
+#define TSGLS_ESCRATCH (-7)    /* request larger than the fixed scratch of an
+                                  allocation-free entry point */
 
 /* Tangent variants (jv, jacobi_diag, solve). */
 #define TSGLS_JAC_PICARD 0       /* eq. K_mat: A_i and tau frozen (paper's tangent) */
@@ -278,6 +280,22 @@ int tsgls_rb_project(const double* Phi, int r, int64_t D, const double* Y, int64
                      const double* mean, double* coef, void* hip_stream);
 int tsgls_rb_expand(const double* Phi, int r, int64_t D, const double* coef,
                     const double* mean, double* y, void* hip_stream);
+
+/* tsgls_rb_project for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, same kernels and the same result bit for bit,
+ * but it calls no allocator.  Its block partial sums and the projected mean
+ * live in a fixed device array of 1024 * 1024 + 1024 doubles (8.0 MiB) per
+ * GPU, held until the process ends, whose address is looked up on the first
+ * call made with that GPU current.  r > 1024 returns TSGLS_ESCRATCH; bad
+ * pointers or sizes TSGLS_EINVAL.  Returns without synchronizing (the work
+ * is ordered on hip_stream).  Every call on one GPU uses that GPU's array:
+ * calls that overlap on one GPU (other streams or host threads) race, so a
+ * caller serializes them.  Nothing in the array needs to start at zero; each
+ * call overwrites what it reads. */
+int tsgls_rb_project_noalloc(const double* Phi, int r, int64_t D, const double* Y,
+                             int64_t N, const double* mean, double* coef,
+                             void* hip_stream);
 
 /* Network: n_in -> n_hidden layers of width (tanh) -> n_out (linear).
  * Weights W_l [d_{l+1}][d_l] and biases b_l, l = 0..n_hidden, stored as one

@@ -20,7 +20,8 @@ TSGLS_NOT_CONVERGED = 1
 JAC = {"picard": 0, "picard_nols": 1, "newton": 2}
 PREC = {"f64": 0, "f32": 1}
 DT_SCHEDULE = {"fixed": 0, "ser": 1, "auto": 2}
-ERRORS = {-1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "EMESH", -5: "ENONFINITE", -6: "ESTATE"}
+ERRORS = {-1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "EMESH", -5: "ENONFINITE", -6: "ESTATE",
+          -7: "ESCRATCH"}
 
 
 class Params(C.Structure):
@@ -77,6 +78,7 @@ def lib():
         L.tsgls_rb_greedy.argtypes = [P, I64, I64, P, I32, P, P, P]
         L.tsgls_rb_project.argtypes = [P, I32, I64, P, I64, P, P, P]
         L.tsgls_rb_expand.argtypes = [P, I32, I64, P, P, P, P]
+        L.tsgls_rb_project_noalloc.argtypes = [P, I32, I64, P, I64, P, P, P]
         L.tsgls_mlp_create.argtypes = [I32, I32, I32, I32, I32, C.c_uint64, P, C.POINTER(P)]
         L.tsgls_mlp_num_params.argtypes = [P, C.POINTER(I64)]
         L.tsgls_mlp_get_params.argtypes = [P, P, P]
@@ -320,6 +322,20 @@ def rb_project(Phi, Y, mean, stream=None):
     if rc < 0:
         raise TsglsError(f"rb_project: {ERRORS.get(rc, rc)}")
     return coef
+
+
+def rb_project_noalloc(Phi, Y, mean, coef, stream=None):
+    """coef [N][r] = Phi (Y_i - mean) into the caller's coef, with no device
+    allocation (tsgls_rb_project_noalloc; calls on one GPU must not overlap)."""
+    r, D = Phi.shape
+    N = Y.shape[0]
+    if tuple(coef.shape) != (N, r):
+        raise TsglsError("rb_project_noalloc: coef must be [N][r]")
+    rc = lib().tsgls_rb_project_noalloc(_dev(Phi, "f64", "Phi", 2), r, D, _dev(Y, "f64", "Y"), N,
+                                        _dev(mean, "f64", "mean"), _dev(coef, "f64", "coef"),
+                                        _cur_stream(stream))
+    if rc < 0:
+        raise TsglsError(f"rb_project_noalloc: {ERRORS.get(rc, rc)}")
 
 
 def rb_expand(Phi, coef, mean, out, stream=None):

@@ -19,8 +19,8 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(HERE, "..", "include")]
-UNITS = ["elem.hip", "elemop.hip", "face.hip", "krylov.hip", "mlp.hip", "tracer.hip", "host.cpp",
-         "learn.cpp"]
+UNITS = ["elem.hip", "elemop.hip", "face.hip", "krylov.hip", "mlp.hip", "tracer.hip", "noalloc.hip",
+         "host.cpp", "learn.cpp"]
 
 
 def _compile(unit: str) -> str:
