@@ -69,42 +69,77 @@ def _workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(prob, jv_per_step, n_sample=3000):
-    """Oracle Newton-step work (linearize + Jacobi diagonal + jv_per_step
-    tangent products) on the first n_sample elements (Morton order, so a
-    contiguous patch), scaled to the full mesh."""
+def _oracle_patch(prob, first, n_sample):
+    """Elements [first, first + n_sample) (Morton order: a contiguous patch)
+    as a stand-alone oracle problem with its seeded state and direction."""
     import numpy as np
     import oracle as O
-    tets = prob.mesh.tets[:n_sample]
+    tets = prob.mesh.tets[first:first + n_sample]
     used = np.unique(tets)
     remap = -np.ones(prob.mesh.n_nodes, dtype=np.int64)
     remap[used] = np.arange(used.size)
-    xyz = prob.mesh.xyz[used]
-    t = remap[tets].astype(np.int32)
     dn = remap[prob.dirichlet_nodes]
     par = O.Params(K=prob.K, rho=prob.rho, mu=prob.mu, omega=prob.omega, C_I=prob.C_I,
                    backflow_beta=prob.backflow_beta, dirichlet_nodes=dn[dn >= 0],
                    neumann_tris=np.zeros((0, 3), np.int32))
-    rng = np.random.default_rng(0)
+    rng = np.random.default_rng(first)
     y = rng.standard_normal((used.size, 4, 2 * prob.K + 2)) * 0.1
     v = rng.standard_normal(y.shape)
-    c0 = time.process_time()
-    w0 = time.perf_counter()
-    lin = O.linearize(par, xyz, t, y)
-    O.jacobian_diagonal(par, xyz, t, lin)
-    for _ in range(jv_per_step):
-        O.jv(par, xyz, t, lin, v, "picard")
-    wall = time.perf_counter() - w0
-    cpu = time.process_time() - c0
+    return par, prob.mesh.xyz[used], remap[tets].astype(np.int32), y, v
+
+
+def _oracle_step_seconds(task):
+    """Wall time of one oracle Newton step's work (linearize, Jacobi diagonal,
+    jv_per_step Picard products) on one patch, BLAS limited to one thread;
+    a first untimed run absorbs start-up (process pool worker)."""
+    par, xyz, t, y, v, jv_per_step, runs = task
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+
+    def one():
+        w0 = time.perf_counter()
+        lin = O.linearize(par, xyz, t, y)
+        O.jacobian_diagonal(par, xyz, t, lin)
+        for _ in range(jv_per_step):
+            O.jv(par, xyz, t, lin, v, "picard")
+        return time.perf_counter() - w0
+
+    with threadpool_limits(limits=1):
+        return [one() for _ in range(runs)]
+
+
+def cpu_baseline(prob, jv_per_step, n_sample=1200, repeats=3):
+    """The oracle (as it stands: NumPy, effectively one thread per process)
+    on bounded samples of the same workload, scaled to the full mesh.
+
+    * 1 core: one process, `repeats` runs on one patch of n_sample elements
+      (median).
+    * all cores: one worker process per core the process may use (CPU
+      affinity mask, at most 16), each on its own patch, `repeats` timed runs
+      after an untimed one; the rate is total elements / the slowest
+      worker's median run."""
+    import multiprocessing as mp
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    patches = [_oracle_patch(prob, i * n_sample, n_sample) for i in range(cores)]
+    one = sorted(_oracle_step_seconds(patches[0] + (jv_per_step, repeats + 1))[1:])
+    med_one = one[repeats // 2]
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_oracle_step_seconds, [pt + (jv_per_step, repeats + 1) for pt in patches])
+    med_workers = [sorted(r[1:])[repeats // 2] for r in res]
+    wall_all = max(med_workers)
     scale = prob.mesh.n_tets / n_sample
-    step_s = wall * scale
     dof = prob.mesh.n_nodes * 4 * (2 * prob.K + 1)
-    return dict(value=jv_per_step * dof / step_s / 1e9, unit="GDOF-modes/s",
-                cores=max(1, int(round(cpu / wall))), kind="oracle",
+    rate_one = jv_per_step * dof / (med_one * scale) / 1e9
+    rate_all = rate_one * med_one / wall_all * cores
+    return dict(value=rate_all, unit="GDOF-modes/s", cores=cores, kind="oracle",
+                value_1core=rate_one,
                 sample=f"oracle Newton-step work (linearize, Jacobi diagonal, {jv_per_step} Picard "
-                       f"tangent products) on {n_sample} of {prob.mesh.n_tets} elements, "
-                       f"{wall:.1f} s wall, scaled by {scale:.0f}x to the full mesh",
-                seconds=wall)
+                       f"tangent products) on patches of {n_sample} of {prob.mesh.n_tets} elements, "
+                       f"scaled by {scale:.0f}x to the full mesh; 1 core: median of {repeats} runs "
+                       f"({med_one:.2f} s); {cores} cores: {cores} worker processes on their own "
+                       f"patches, slowest median {wall_all:.2f} s",
+                seconds_1core=[round(w, 3) for w in one],
+                seconds_per_worker=[round(w, 3) for w in med_workers])
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_op_junction_1M_K6_traffic.txt")
@@ -303,22 +338,24 @@ def summarize_issue(csvs):
 
 
 def batched(args):
+    print(json.dumps(batched_run(args.batched, args.batch_concurrency, args.batch_graph)), flush=True)
+
+
+def batched_run(N, concurrency=8, graph=False):
     """Batched solves: N inflow waveforms of uneven harmonic count on the
     Womersley pipe (R = 1, L = 4, 6,144 tets), K drawn from {3, 5, 7, 11},
     waveform Q(t)/Qbar = 1 + sum_k a k^-2 cos(k omega t + phi_k) with
     a ~ U[0.1, 1] and seeded phases, each solved to 1e-8 from the initial
     guess.  Runs them one at a time, then all through tsgls_solve_batch, and
-    prints one JSON line with throughput and per-solve latency percentiles of
-    both.  (On the 200k-tet junction the Jacobi-preconditioned GMRES needs
-    thousands of products per Newton step, so solves to 1e-8 there are not a
-    batch-latency workload.)"""
+    returns throughput and per-solve latency percentiles of both.  (On the
+    200k-tet junction a solve to 1e-8 takes tens of thousands of products,
+    so it is not a batch-latency workload.)"""
     import numpy as np
     import torch
     import paper_2311_09465_amd as T
     from workloads import womersley_problem, initial_guess
     from workloads.problems import inlet_waveforms
     from workloads.meshgen import pipe
-    N = args.batched
     rng = np.random.default_rng(2311)
     mesh = pipe(4, 16)
     Ks = rng.choice([3, 5, 7, 11], size=N)
@@ -327,7 +364,7 @@ def batched(args):
                                waveform=inlet_waveforms(int(Ks[i]), 1000 + i, amps[i], n_inlets=1)[0])
              for i in range(N)]
     solvers = [T.Solver.from_problem(p, stream=torch.cuda.Stream()) for p in probs]
-    opts = dict(rtol=1e-8, lin_rtol=0.05, restart=30, max_newton=40, gmres_graph=args.batch_graph)
+    opts = dict(rtol=1e-8, lin_rtol=0.05, restart=30, max_newton=40, gmres_graph=graph)
     # one short solve per K first (first-use setup of each kernel family)
     for K in sorted(set(int(k) for k in Ks)):
         i = int(np.argmax(Ks == K))
@@ -353,7 +390,7 @@ def batched(args):
     ys = [torch.from_numpy(initial_guess(p)).cuda() for p in probs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rc, stats, fin = T.solve_batch(solvers, ys, max_concurrent=args.batch_concurrency, **opts)
+    rc, stats, fin = T.solve_batch(solvers, ys, max_concurrent=concurrency, **opts)
     bat_wall = time.perf_counter() - t0
     out = {
         "metric": "batched solves to 1e-8: throughput and per-solve latency",
@@ -361,8 +398,8 @@ def batched(args):
         "config": dict(workload="womersley_6k_batched", n_tets=mesh.n_tets,
                        n_nodes=mesh.n_nodes, K_choices=[3, 5, 7, 11],
                        K_counts={int(k): int((Ks == k).sum()) for k in sorted(set(Ks.tolist()))},
-                       restart=30, lin_rtol=0.05, concurrency=args.batch_concurrency,
-                       gmres_graph=bool(args.batch_graph)),
+                       restart=30, lin_rtol=0.05, concurrency=concurrency,
+                       gmres_graph=bool(graph)),
         "sequential": dict(wall_s=round(seq_wall, 3), solves_per_s=round(N / seq_wall, 3),
                            own_p50_s=round(pct(seq_own, 50), 4), own_p99_s=round(pct(seq_own, 99), 4),
                            converged=int(seq_ok), newton_iters_mean=round(float(np.mean(seq_it)), 2)),
@@ -373,22 +410,28 @@ def batched(args):
                         converged=int(sum(s_["status"] == 0 for s_ in stats)), status=rc),
         "throughput_gain": round(seq_wall / bat_wall, 3),
     }
-    print(json.dumps(out), flush=True)
+    del solvers
+    return out
 
 
 def learned(args):
+    print(json.dumps(learned_run(args.learned, args.learned_test, args.learned_basis,
+                                 args.learned_hidden, args.learned_steps, args.learned_precision)),
+          flush=True)
+
+
+def learned_run(ntr, nte, r, hidden=4, steps=3000, precision="bf16"):
     """Learned warm start on the pipe family (6,144 tets, K = 3; inflow
     waveform amplitude, phases, Re and Wo drawn per member): solves the
     training members (batched), builds the reduced basis, trains the
     network, then solves held-out members from the plain initial guess and
     from the prediction to the same absolute residual (1e-8 of the initial
-    guess's).  Prints one JSON line."""
+    guess's).  Returns the measurements."""
     import numpy as np
     import torch
     import paper_2311_09465_amd as T
     from paper_2311_09465_amd.warmstart import WarmStart, fix_dirichlet
     from workloads import pipe_family, initial_guess
-    ntr, nte, r = args.learned, args.learned_test, args.learned_basis
     probs, feats = pipe_family(ntr + nte, K=3, seed=11)
     opts = dict(lin_rtol=0.05, restart=30, max_newton=60)
     t0 = time.perf_counter()
@@ -410,8 +453,8 @@ def learned(args):
     Y = torch.stack([y.view(-1) for y in ys]).contiguous()
     del ys
     t0 = time.perf_counter()
-    ws = WarmStart.fit(feats[:ntr], Y, r=r, n_hidden=args.learned_hidden, steps=args.learned_steps,
-                       lr=1e-3, seed=1, precision=args.learned_precision)
+    ws = WarmStart.fit(feats[:ntr], Y, r=r, n_hidden=hidden, steps=steps,
+                       lr=1e-3, seed=1, precision=precision)
     torch.cuda.synchronize()
     t_fit = time.perf_counter() - t0
     rows = []
@@ -462,9 +505,9 @@ def learned(args):
         "metric": "learned warm start: Newton steps and time to 1e-8 vs the plain initial guess",
         "n_gpus": 1, "data": "synthetic (seeded pipe inflow waveforms, Re, Wo)",
         "config": dict(workload="womersley_6k_K3_family", n_tets=probs[0].mesh.n_tets, K=3,
-                       n_train=ntr, n_test=nte, basis=int(ws.Phi.shape[0]), net=f"8-512x{args.learned_hidden}-r tanh",
-                       precision=("bf16 MFMA, FP32 master weights" if args.learned_precision == "bf16"
-                                  else "FP32 MFMA"), steps=args.learned_steps),
+                       n_train=ntr, n_test=nte, basis=int(ws.Phi.shape[0]), net=f"8-512x{hidden}-r tanh",
+                       precision=("bf16 MFMA, FP32 master weights" if precision == "bf16"
+                                  else "FP32 MFMA"), steps=steps),
         "train": dict(data_s=round(t_data, 3), all_converged=rc == 0, fit_s=round(t_fit, 3),
                       final_loss=ws.train_loss),
         "cold": dict(newton_mean=round(col("cold_it").mean(), 3), s_mean=round(col("cold_s").mean(), 4),
@@ -484,7 +527,57 @@ def learned(args):
         "speedup_time_to_1e8": round(col("cold_s").mean() / col("warm_s").mean(), 3),
         "speedup_time_to_1e8_warm_newton": round(col("cold_s").mean() / col("wn_s").mean(), 3),
     }
-    print(json.dumps(out), flush=True)
+    return out
+
+
+JUNCTION_SOLVE = dict(rtol=1e-8, lin_rtol=0.1, restart=100, max_newton=150, max_matvec=10000,
+                      jacobian="newton", dt_pseudo=0.1, dt_schedule="ser", dt_max=2.0)
+
+
+def junction_time_to_1e8():
+    """Time to 1e-8 on the 200k-tet junction (h = 0.081, K = 3, Re = 100,
+    Wo = 10) from the initial guess: pseudo-time stepping with one Newton
+    iteration per step (Newton tangent, tau frozen), switched-evolution step
+    size from 0.1 bounded by 2, GMRES(100) to 0.1; FP64 tangent and FP32
+    tangent (FP64 residual and Krylov)."""
+    import torch
+    import paper_2311_09465_amd as T
+    from workloads import junction_problem, initial_guess
+    prob = junction_problem(h=0.081, K=3, Re=100.0)
+    s = T.Solver.from_problem(prob)
+    out = dict(workload="junction_200k_K3_Re100", n_tets=prob.mesh.n_tets, n_nodes=prob.mesh.n_nodes,
+               solver={k: v for k, v in JUNCTION_SOLVE.items()})
+    for prec in ("f64", "f32"):
+        y = torch.from_numpy(initial_guess(prob)).cuda()
+        torch.cuda.synchronize()
+        st = s.solve(y, tangent_precision=prec, **JUNCTION_SOLVE)
+        out[prec] = dict(seconds=round(st["seconds"], 3), status="converged" if st["status"] == 0
+                         else "not converged", newton_iters=st["newton_iters"], matvecs=st["matvecs"],
+                         rel_residual=float("%.3e" % st["rel_residual"]), rejected=st["rejected"])
+        print(f"junction 200k time to 1e-8 ({prec}): {out[prec]}", file=sys.stderr, flush=True)
+    out["f32_speedup"] = round(out["f64"]["seconds"] / out["f32"]["seconds"], 3)
+    s.close()
+    return out
+
+
+def junction_re500_attempt(prob, steps=25):
+    """The headline junction (Re = 500) under the same pseudo-time schedule,
+    bounded to `steps` pseudo-time steps of at most 300 products: the relative
+    residual does not settle (no attractor of the pseudo-time iteration), so
+    only its trace is reported."""
+    import torch
+    import paper_2311_09465_amd as T
+    from workloads import initial_guess
+    s = T.Solver.from_problem(prob)
+    y = torch.from_numpy(initial_guess(prob)).cuda()
+    torch.cuda.synchronize()
+    st = s.solve(y, **dict(JUNCTION_SOLVE, max_newton=steps, max_matvec=300, dt_pseudo=0.05))
+    h = st["history"]
+    s.close()
+    return dict(workload="junction_1M_K6_Re500", pseudo_time_steps=st["newton_iters"],
+                matvecs=st["matvecs"], seconds=round(st["seconds"], 3),
+                rel_residual_min=float("%.3e" % min(h)), rel_residual_last=float("%.3e" % h[-1]),
+                history=[float("%.2e" % x) for x in h])
 
 
 def dt_sweep(args):
@@ -627,6 +720,8 @@ def main():
     ap.add_argument("--jacobian", default="picard")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-solves", action="store_true",
+                    help="skip the solve measurements (junction time to 1e-8, batched, learned)")
     ap.add_argument("--probe", action="store_true",
                     help="counter-collection workload (linearize, 3 tangent products, a 512 MiB copy)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -831,6 +926,14 @@ def main():
             time_to_1e8_womersley_6k_K3_newton_iters=stw["newton_iters"],
             time_to_1e8_womersley_6k_K3_matvecs=stw["matvecs"],
             time_to_1e8_womersley_6k_K3_status=stw["status"])
+        del sw
+        if not args.no_solves:
+            out["time_to_1e8_junction"] = junction_time_to_1e8()
+            out["junction_re500_pseudo_time"] = junction_re500_attempt(prob)
+            print("batched solves", file=sys.stderr, flush=True)
+            out["batched"] = batched_run(64)
+            print("learned warm start", file=sys.stderr, flush=True)
+            out["learned"] = learned_run(512, 16, 64)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, m)
     print(json.dumps(out), flush=True)
