@@ -122,9 +122,14 @@ k_prep_time(const double* __restrict__ Y, const double* __restrict__ Ys,
       if (act && lane + 64 * r < 3 * M) {
         const double* xr = sx[wv] + sj[r] * PW;
         double acc = 0.0;
+        if constexpr (n > 32) {   // large K: bounded unrolling keeps the loads in registers
+#pragma unroll 4
+          for (int a = 0; a < n; ++a) acc = fma(xr[mode_pos(a, K)], F[a * M + ss[r]], acc);
+        } else {
 #pragma unroll
-        for (int a = 0; a < n; ++a)
-          acc = fma(xr[mode_pos(a, K)], HOIST ? Fl[HOIST ? a : 0] : F[a * M + ss[r]], acc);
+          for (int a = 0; a < n; ++a)
+            acc = fma(xr[mode_pos(a, K)], HOIST ? Fl[HOIST ? a : 0] : F[a * M + ss[r]], acc);
+        }
         XT[(node * 3 + sj[r]) * M + ss[r]] = TO(acc);
       }
     }
@@ -587,6 +592,231 @@ __global__ void k_diag_finish(const uint8_t* __restrict__ nflag, double* __restr
   if (s == 1 || (f < 3 && (nflag[node] & 1)) || d[idx] == 0.0) d[idx] = 1.0;
 }
 
+// ------------------------------------------------------ tau, large K
+// tau for n = 2K+1 > 32: one wave per (element, quadrature point).  Lane c
+// forms column c of S = sum_i A(u_i) A(v_i) + C_I nu^2 (G:G) I as
+// A(u_i) (A(v_i) e_c), each product applied on the M = 3K+1 samples:
+// A(x) y = (1/M) sum_s phi(t_s) x(t_s) y(t_s), exact for band-limited x and
+// y (the integrand has degree <= 3K).  The sample table is read with
+// wave-uniform indices (scalar loads).  Then the one-sided Jacobi on the
+// columns and tau = Q^T Q on MFMA, as in k_tau.
+template <int K>
+__global__ void __launch_bounds__(64)
+k_tau_big(DevView v, const double* __restrict__ Y, double* __restrict__ tau) {
+  constexpr int n = Dim<K>::n, M = Dim<K>::M, S = Dim<K>::S, P = Dim<K>::P;
+  constexpr int PW = (n + 15) / 16 * 16, QS = PW + 1;
+  static_assert(n <= 64 && PW <= 64, "one lane per column");
+  __shared__ double sX[6 * M];          // u_j(t_s), then v_i(t_s)
+  __shared__ double sQ[PW * QS];        // modes of u_j, v_i; then Q
+  const double* __restrict__ F = v.F;
+  const int c = threadIdx.x;
+  const int64_t gq = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t e = gq >> 2;
+  const int q = (int)(gq & 3);
+  if (e >= v.n_tets) return;                      // uniform over the block
+  double dN[4][3];
+  int nodes[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    nodes[b] = v.conn[e * 4 + b];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dN[b][i] = v.geo[e * 16 + b * 3 + i];
+  }
+  double Gm[3][3];
+  double GG = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Gm[i][j] = dN[1][i] * dN[1][j] + dN[2][i] * dN[2][j] + dN[3][i] * dN[3][j];
+      GG += Gm[i][j] * Gm[i][j];
+    }
+  const double nu = v.mu / v.rho;
+  const double kap = v.C_I * nu * nu * GG;
+  double* sUm = sQ;            // [3][n]
+  double* sVm = sQ + 3 * n;    // [3][n]
+  if (c < n) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc += lamq(q, b) * slot_x(Y + ((int64_t)nodes[b] * 4 + j) * S, c);
+      sUm[j * n + c] = acc;
+    }
+  }
+  __syncthreads();
+  if (c < n) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      sVm[i * n + c] = Gm[i][0] * sUm[c] + Gm[i][1] * sUm[n + c] + Gm[i][2] * sUm[2 * n + c];
+  }
+  __syncthreads();
+  for (int s = c; s < M; s += 64) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double au = 0.0, av = 0.0;
+      for (int a = 0; a < n; ++a) {
+        au = fma(sUm[j * n + a], F[a * M + s], au);
+        av = fma(sVm[j * n + a], F[a * M + s], av);
+      }
+      sX[j * M + s] = au;
+      sX[(3 + j) * M + s] = av;
+    }
+  }
+  __syncthreads();
+  const double invM = 1.0 / M;
+  double w[n];
+#pragma unroll
+  for (int a = 0; a < n; ++a) w[a] = 0.0;
+  if (c < n) {
+#pragma unroll 1
+    for (int i = 0; i < 3; ++i) {
+      double y[n];                       // A(v_i) e_c
+#pragma unroll
+      for (int a = 0; a < n; ++a) y[a] = 0.0;
+#pragma unroll 1
+      for (int s = 0; s < M; ++s) {
+        const double t = sX[(3 + i) * M + s] * F[c * M + s] * invM;
+#pragma unroll
+        for (int a = 0; a < n; ++a) y[a] = fma(t, F[a * M + s], y[a]);
+      }
+#pragma unroll 1
+      for (int s = 0; s < M; ++s) {      // w += A(u_i) y
+        double ys = 0.0;
+#pragma unroll
+        for (int a = 0; a < n; ++a) ys = fma(y[a], F[a * M + s], ys);
+        const double t = sX[i * M + s] * ys * invM;
+#pragma unroll
+        for (int a = 0; a < n; ++a) w[a] = fma(t, F[a * M + s], w[a]);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < n; ++a)
+      if (a == c) w[a] += kap;
+  }
+  jacobi_columns<n, 64>(w, c);
+  double l2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < n; ++a) l2 = fma(w[a], w[a], l2);
+  const double sc = l2 > 0.0 ? pow(l2, -0.625) : 0.0;   // lambda^(-5/4), lambda = |w|
+  __syncthreads();
+  // Q[k][p] = w_k[pos_mode(p)] lambda_k^(-5/4); tau over positions = Q^T Q
+  for (int i = c; i < PW * QS; i += 64) sQ[i] = 0.0;
+  __syncthreads();
+  if (c < n) {
+#pragma unroll
+    for (int a = 0; a < n; ++a) sQ[c * QS + mode_pos(a, K)] = w[a] * sc;
+  }
+  __syncthreads();
+  const int gl = c >> 4, cl = c & 15;
+  double* tj = tau + gq * P;
+#pragma unroll 1
+  for (int tr = 0; tr < PW / 16; ++tr)
+#pragma unroll 1
+    for (int tc = tr; tc < PW / 16; ++tc) {
+      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < PW / 4; ++ks) {
+        const double* qr = sQ + (ks * 4 + gl) * QS;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(qr[cl + 16 * tr], qr[cl + 16 * tc], acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = gl + 4 * r + 16 * tr, col = cl + 16 * tc;
+        if (row <= col && col < n) tj[pk_index(row, col, n)] = acc[r];
+      }
+    }
+}
+
+// ------------------------------------------- Jacobi diagonal, large K
+// One wave per (element, node b); lane a < n forms, per point,
+// b_a = A(g) e_a + lam Omega e_a with g = grad N_b . u(q, t) on the samples
+// (A(g) e_a = (1/M) sum_s phi(t_s) g(t_s) phi_a(t_s)) and the quadratic form
+// b_a^T tau b_a with tau's packed entries read by wave-uniform index.
+template <int K>
+__global__ void __launch_bounds__(64)
+k_diag_big(DevView v, double* __restrict__ d, double shift, int64_t begin, int64_t end) {
+  constexpr int n = Dim<K>::n, M = Dim<K>::M, P = Dim<K>::P;
+  static_assert(n <= 64, "one lane per mode");
+  __shared__ double sg[M];
+  const int64_t idx = begin * 4 + xcd_block(blockIdx.x, gridDim.x);
+  if (idx >= end * 4) return;                       // uniform over the block
+  const int64_t e = idx >> 2;
+  const int b = (int)(idx & 3);
+  const int a = threadIdx.x;
+  const double dNb[3] = {v.geo[e * 16 + b * 3 + 0], v.geo[e * 16 + b * 3 + 1], v.geo[e * 16 + b * 3 + 2]};
+  const double wgt = v.geo[e * 16 + 12];
+  const double gn2 = dNb[0] * dNb[0] + dNb[1] * dNb[1] + dNb[2] * dNb[2];
+  int nodes[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) nodes[c] = v.conn[e * 4 + c];
+  const double* __restrict__ F = v.F;
+  const double invM = 1.0 / M;
+  double dm = 0.0, dc = 0.0;
+#pragma unroll 1
+  for (int q = 0; q < 4; ++q) {
+    const double lam = lamq(q, b);
+    for (int s = a; s < M; s += 64) {
+      double gsum = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double* ut = v.UT + (int64_t)nodes[c] * 3 * M + s;
+        gsum += lamq(q, c) * (dNb[0] * ut[0] + dNb[1] * ut[M] + dNb[2] * ut[2 * M]);
+      }
+      sg[s] = gsum;
+    }
+    __syncthreads();
+    if (a < n) {
+      double bc[n];
+#pragma unroll
+      for (int r = 0; r < n; ++r) bc[r] = 0.0;
+#pragma unroll 1
+      for (int s = 0; s < M; ++s) {
+        const double t = sg[s] * F[a * M + s] * invM;
+#pragma unroll
+        for (int r = 0; r < n; ++r) bc[r] = fma(t, F[r * M + s], bc[r]);
+      }
+      double Aaa = 0.0;
+#pragma unroll
+      for (int r = 0; r < n; ++r)
+        if (r == a) Aaa = bc[r];
+      if (a > 0) {   // + lam Omega e_a
+        const int k = (a + 1) >> 1;
+        const double om = k * v.omega * lam;
+#pragma unroll
+        for (int r = 0; r < n; ++r) {
+          if ((a & 1) && r == a + 1) bc[r] += om;        // Omega e_{2k-1} = k w e_{2k}
+          if (!(a & 1) && r == a - 1) bc[r] -= om;       // Omega e_{2k} = -k w e_{2k-1}
+        }
+      }
+      const double* tq = v.tau + (e * 4 + q) * P;
+      double quad = 0.0;
+#pragma unroll
+      for (int r = 0; r < n; ++r) {
+        double off = 0.0;
+#pragma unroll
+        for (int c = r + 1; c < n; ++c) {
+          const int pr = mode_pos(r, K), pc = mode_pos(c, K);
+          off = fma(tq[pr < pc ? pk_index(pr, pc, n) : pk_index(pc, pr, n)], bc[c], off);
+        }
+        const int pp = mode_pos(r, K);
+        quad = fma(bc[r], fma(2.0, off, tq[pk_index(pp, pp, n)] * bc[r]), quad);
+      }
+      const int pa = mode_pos(a, K);
+      const double taa = tq[pk_index(pa, pa, n)];
+      dm += wgt * (v.rho * lam * Aaa + v.mu * gn2 + v.rho * quad + shift * lam * lam);
+      dc += (wgt / v.rho) * gn2 * taa;
+    }
+    __syncthreads();
+  }
+  if (a < n) {
+    double* op = d + (e * 4 + b) * 4 * n;      // node b's rows [field][position]
+    const int pa = mode_pos(a, K);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) op[f * n + pa] = f < 3 ? dm : dc;
+  }
+}
+
 // --------------------------------------------------------------- dispatch
 
 int pos_width(int K) { return (2 * K + 1 + 15) / 16 * 16; }
@@ -653,7 +883,10 @@ hipError_t launch_tau(const DevView& v, const double* Y, double* tau, hipStream_
     k_tau<k><<<grid, TauCfg<k>::BLOCK, 0, st>>>(v, Y, tau);                              \
     break;                                                                               \
   }
-    TSGLS_FOR_EACH_K(CASE)
+    TSGLS_FOR_EACH_K_SMALL(CASE)
+#undef CASE
+#define CASE(k) case k: k_tau_big<k><<<(unsigned)(v.n_tets * 4), 64, 0, st>>>(v, Y, tau); break;
+    TSGLS_FOR_EACH_K_LARGE(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
   }
@@ -666,7 +899,10 @@ hipError_t launch_diag(const DevView& v, double* d, double shift, int64_t begin,
   const unsigned grid = (unsigned)(((end - begin) * 4 + 127) / 128);
   switch (v.K) {
 #define CASE(k) case k: k_diag<k><<<grid, 128, 0, st>>>(v, d, shift, begin, end); break;
-    TSGLS_FOR_EACH_K(CASE)
+    TSGLS_FOR_EACH_K_SMALL(CASE)
+#undef CASE
+#define CASE(k) case k: k_diag_big<k><<<(unsigned)((end - begin) * 4), 64, 0, st>>>(v, d, shift, begin, end); break;
+    TSGLS_FOR_EACH_K_LARGE(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
   }

@@ -576,6 +576,349 @@ k_op(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
   }
 }
 
+// ------------------------------------------- element operator, large K
+// The same operator for K with n = 2K+1 > 32 modes per field (the
+// register-blocked kernel above keeps a tile of DFT weights and a packed tau
+// block per lane, which does not fit at n = 63).  One block of four waves per
+// element (persistent over a contiguous Morton range per XCD); the sample
+// table phi_a(t_s) sits in LDS for the whole launch, and every phase uses a
+// layout in which one LDS operand is the same for the whole wave:
+//   products    thread s < M: conv_{q,i}(t_s) for all (q, i) (+ Newton
+//               term), u_q(t_s) and the direction at the points kept in
+//               registers for the least-squares products
+//   to modes    wave q, lane p: conv modes of point q, then L_i (LDS)
+//   z           wave q, lane p: z_i = tau_q L_i, tau_q row p read from the
+//               packed block (L1/L2); G = gal - Omega z with the pair
+//               partner's z from the neighbouring lane
+//   to samples  thread s: z_{q,i}(t_s) in registers
+//   LS          thread s: W_ji(t_s) = w sum_q u_{q,j} z_{q,i} -> LDS
+//   to modes    wave i, lane p: W modes in registers
+//   assembly    wave f, lane p: Galerkin, viscous, pressure, LS and PSPG
+//               terms of the four node rows (same element-buffer layout).
+template <int K, typename T>
+struct BigCfg {
+  static constexpr int n = 2 * K + 1, M = 3 * K + 1, P = n * (n + 1) / 2;
+  static constexpr int PW = (n + 63) / 64 * 64;   // positions: one per lane of a wave
+  static constexpr int RP = PW + 1;               // LDS row stride over positions
+  static constexpr int RS = M | 1;                // LDS row stride over samples
+  static_assert(PW == 64, "large-K operator: one wave spans the positions");
+  static_assert(M <= 256, "large-K operator: one thread per sample");
+};
+
+template <int K, int MODE, typename T>
+__global__ void __launch_bounds__(256)
+k_op_big(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
+         double* __restrict__ Zout, T* __restrict__ out, T shift, int64_t begin, int64_t end) {
+  using C = BigCfg<K, T>;
+  constexpr int n = C::n, M = C::M, P = C::P, PW = C::PW, RP = C::RP, RS = C::RS;
+  constexpr bool RESID = (MODE & MODE_RESID) != 0;
+  constexpr bool NEWTON = (MODE & MODE_NEWTON) != 0;
+  constexpr bool NOLS = (MODE & MODE_NOLS) != 0;
+  constexpr bool STOREZ = (MODE & MODE_STOREZ) != 0;
+  const Frozen<T> fz = frozen<T>(v);
+  const T* __restrict__ UT = fz.UT;
+  const T QB = T(TS_QB), QAB = T(TS_QA - TS_QB);
+  constexpr T MD = TS_QA * TS_QA + 3.0 * TS_QB * TS_QB;      // sum_q lam_qb^2
+  constexpr T MO = 2.0 * TS_QA * TS_QB + 2.0 * TS_QB * TS_QB;  // sum_q lam_qb lam_qc
+
+  __shared__ T sPhi[M * RP];                 // phi_{mode(p)}(t_s) at [s][p], 0 for p >= n
+  __shared__ T sV[16 * RP];                  // input modes [node][field][position]
+  __shared__ T sC[12 * RS];                  // conv(t) [q*3+i][s], then W(t) [i*3+j][s]
+  __shared__ T sL[(NOLS ? 24 : 12) * RP];    // L [q*3+i][p] (+ grad p part), then G
+  __shared__ T sZ[(NOLS ? 32 : 16) * RP];    // z [i*4+q][p] (+ tau grad p)
+  __shared__ T sZf[NEWTON ? 16 * RP : 1];    // stored tau L(u) [i*4+q][p]
+
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const T rho = T(v.rho), mu = T(v.mu), omega = T(v.omega), irho = T(1.0 / v.rho);
+  const T invM = T(1.0 / M);
+  for (int i = tid; i < M * RP; i += 256) {
+    const int s = i / RP, p = i % RP;
+    const int a = p < PW ? pos_mode(p, K) : -1;
+    sPhi[i] = a >= 0 ? T(v.F[a * M + s]) : T(0);
+  }
+  for (int i = tid; i < 16 * RP; i += 256) {
+    if (NEWTON) sZf[i] = T(0);
+  }
+  // per-lane constants of the position layouts
+  const int p = lane;
+  const T om = p < 2 * K ? ((p & 1) ? T((p + 1) >> 1) * omega : -T((p >> 1) + 1) * omega) : T(0);
+  const T oscale = p < 2 * K ? T(TS_RS2) : T(1);
+  __syncthreads();
+
+  const int64_t nbx = gridDim.x >> 3, xcd = blockIdx.x & 7, jx = blockIdx.x >> 3;
+  const int64_t cnt = end - begin;
+  const int64_t lo = begin + cnt * xcd / 8, hi = begin + cnt * (xcd + 1) / 8;
+
+  for (int64_t e = lo + jx; e < hi; e += nbx) {
+    int nd[4];
+    T dN[4][3];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      nd[b] = v.conn[e * 4 + b];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) dN[b][j] = T(v.geo[e * 16 + b * 3 + j]);
+    }
+    const T wgt = T(v.geo[e * 16 + 12]);
+
+    // ---- modal input
+    for (int i = tid; i < 16 * PW; i += 256) {
+      const int b = i / (4 * PW), fp = i % (4 * PW);
+      sV[(b * 4 + fp / PW) * RP + fp % PW] = XP[(int64_t)nd[b] * (4 * PW) + fp];
+    }
+
+    // ---- products at the samples, thread s
+    const int s = tid;
+    const bool samp = s < M;
+    T u[4][3], wq[NEWTON ? 4 : 1][3];
+    if (samp) {
+      T U[4][3], Wd[4][3];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          U[b][j] = UT[(int64_t)nd[b] * (3 * M) + j * M + s];
+          Wd[b][j] = RESID ? U[b][j] : VT[(int64_t)nd[b] * (3 * M) + j * M + s];
+        }
+      T su[3], sw[3], gW[3][3], gU[3][3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        su[j] = U[0][j] + U[1][j] + U[2][j] + U[3][j];
+        sw[j] = Wd[0][j] + Wd[1][j] + Wd[2][j] + Wd[3][j];
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          gW[i][j] = dN[0][j] * Wd[0][i] + dN[1][j] * Wd[1][i] + dN[2][j] * Wd[2][i] + dN[3][j] * Wd[3][i];
+          gU[i][j] = dN[0][j] * U[0][i] + dN[1][j] * U[1][i] + dN[2][j] * U[2][i] + dN[3][j] * U[3][i];
+        }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          u[q][j] = QB * su[j] + QAB * U[q][j];
+          if (NEWTON) wq[NEWTON ? q : 0][j] = QB * sw[j] + QAB * Wd[q][j];
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          T cv = u[q][0] * gW[i][0] + u[q][1] * gW[i][1] + u[q][2] * gW[i][2];
+          if (NEWTON)
+            cv += wq[NEWTON ? q : 0][0] * gU[i][0] + wq[NEWTON ? q : 0][1] * gU[i][1] +
+                  wq[NEWTON ? q : 0][2] * gU[i][2];
+          sC[(q * 3 + i) * RS + s] = cv;
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- conv -> modes and L, wave q, lane p
+    const int q = wv;
+    T gal[3];
+    {
+      T cm[3] = {T(0), T(0), T(0)};
+      const T* c0 = sC + (q * 3) * RS;
+#pragma unroll 2
+      for (int t = 0; t < M; ++t) {
+        const T ph = sPhi[t * RP + p];
+        cm[0] = tfma(c0[t], ph, cm[0]);
+        cm[1] = tfma(c0[RS + t], ph, cm[1]);
+        cm[2] = tfma(c0[2 * RS + t], ph, cm[2]);
+      }
+      const int p1 = p ^ 1;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const T du1 = QB * (sV[(0 * 4 + i) * RP + p1] + sV[(1 * 4 + i) * RP + p1] + sV[(2 * 4 + i) * RP + p1] +
+                            sV[(3 * 4 + i) * RP + p1]) + QAB * sV[(q * 4 + i) * RP + p1];
+        const T dp = dN[0][i] * sV[(0 * 4 + 3) * RP + p] + dN[1][i] * sV[(1 * 4 + 3) * RP + p] +
+                     dN[2][i] * sV[(2 * 4 + 3) * RP + p] + dN[3][i] * sV[(3 * 4 + 3) * RP + p];
+        gal[i] = rho * tfma(om, du1, cm[i] * invM);
+        sL[(q * 3 + i) * RP + p] = NOLS ? gal[i] : gal[i] + dp;
+        if (NOLS) sL[(12 + q * 3 + i) * RP + p] = dp;
+      }
+    }
+    __syncthreads();
+
+    // ---- z = tau_q L (and tau_q grad p without LS coupling), G = gal - Omega z
+    T z[3] = {T(0), T(0), T(0)}, zc[3] = {T(0), T(0), T(0)};
+    if (p < n) {
+      const T* tq = fz.tau + (e * 4 + q) * P;
+      const T* l0 = sL + (q * 3) * RP;
+#pragma unroll 2
+      for (int k = 0; k < n; ++k) {
+        const int lo_ = p < k ? p : k, hi_ = p < k ? k : p;
+        const T t = tq[pk_index(lo_, hi_, n)];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          z[i] = tfma(t, l0[i * RP + k], z[i]);
+          if (NOLS) zc[i] = tfma(t, l0[(12 + i) * RP + k], zc[i]);
+        }
+      }
+    }
+    T G[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) G[i] = gal[i] - om * swap_pair(z[i]);
+    __syncthreads();   // every lane has read L
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      sL[(q * 3 + i) * RP + p] = G[i];
+      sZ[(i * 4 + q) * RP + p] = z[i];
+      if (NOLS) sZ[(16 + i * 4 + q) * RP + p] = zc[i];
+      if (p < n) {
+        const int64_t zi = ((e * 4 + q) * 3 + i) * n + p;
+        if (STOREZ) Zout[zi] = double(z[i]);
+        if (NEWTON) sZf[(i * 4 + q) * RP + p] = fz.Z[zi];
+      }
+    }
+    __syncthreads();
+
+    // ---- z (and the stored tau L(u)) at the samples, then the LS products, thread s
+    if (samp) {
+      T zt[12], zft[NEWTON ? 12 : 1];
+#pragma unroll
+      for (int r = 0; r < 12; ++r) {
+        zt[r] = T(0);
+        if (NEWTON) zft[NEWTON ? r : 0] = T(0);
+      }
+#pragma unroll 1
+      for (int k = 0; k < n; ++k) {
+        const T ph = sPhi[s * RP + k];
+#pragma unroll
+        for (int r = 0; r < 12; ++r) {
+          zt[r] = tfma(sZ[r * RP + k], ph, zt[r]);
+          if (NEWTON) zft[NEWTON ? r : 0] = tfma(sZf[r * RP + k], ph, zft[NEWTON ? r : 0]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          T acc = T(0);
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            acc = tfma(u[qq][j], zt[i * 4 + qq], acc);
+            if (NEWTON) acc = tfma(wq[NEWTON ? qq : 0][j], zft[NEWTON ? i * 4 + qq : 0], acc);
+          }
+          sC[(i * 3 + j) * RS + s] = wgt * acc;   // conv(t) was consumed before the last barriers
+        }
+    }
+    __syncthreads();
+
+    // ---- W -> modes (wave i) and assembly (wave f = field), lane p
+    const int f = wv;
+    T o[4];
+    if (f < 3) {
+      const int i = f;
+      T wm[3] = {T(0), T(0), T(0)};
+      const T* w0 = sC + (i * 3) * RS;
+#pragma unroll 2
+      for (int t = 0; t < M; ++t) {
+        const T ph = sPhi[t * RP + p];
+        wm[0] = tfma(w0[t], ph, wm[0]);
+        wm[1] = tfma(w0[RS + t], ph, wm[1]);
+        wm[2] = tfma(w0[2 * RS + t], ph, wm[2]);
+      }
+      T Gq[4], Vf[4], Vp[4];
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) Gq[qq] = sL[(qq * 3 + i) * RP + p];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        Vf[b] = sV[(b * 4 + i) * RP + p];
+        Vp[b] = sV[(b * 4 + 3) * RP + p];
+      }
+      const T Gs = Gq[0] + Gq[1] + Gq[2] + Gq[3];
+      const T ps = Vp[0] + Vp[1] + Vp[2] + Vp[3];
+      const T Vs = Vf[0] + Vf[1] + Vf[2] + Vf[3];
+      const T kv = T(4) * wgt * mu, ks = shift * wgt;
+      T t3[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        t3[j] = tfma(kv, dN[0][j] * Vf[0] + dN[1][j] * Vf[1] + dN[2][j] * Vf[2] + dN[3][j] * Vf[3],
+                     wm[j] * invM);
+      const T wq_ = wgt * QAB, km = ks * (MD - MO), wps = -wgt * ps;
+      const T base = tfma(wgt * QB, Gs, ks * MO * Vs);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const T dNi = i == 0 ? dN[b][0] : (i == 1 ? dN[b][1] : dN[b][2]);
+        T acc = tfma(wq_, Gq[b], base);
+        acc = tfma(km, Vf[b], acc);
+        acc = tfma(wps, dNi, acc);
+        acc = tfma(dN[b][0], t3[0], acc);
+        acc = tfma(dN[b][1], t3[1], acc);
+        o[b] = tfma(dN[b][2], t3[2], acc);
+      }
+    } else {
+      T div = T(0);
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) div = tfma(dN[b][j], sV[(b * 4 + j) * RP + p], div);
+      T zs[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const T* zr = sZ + ((NOLS ? 16 : 0) + i * 4) * RP + p;
+        zs[i] = zr[0] + zr[RP] + zr[2 * RP] + zr[3 * RP];
+      }
+      const T wr = wgt * irho, wd = wgt * div;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        o[b] = tfma(wr, dN[b][0] * zs[0] + dN[b][1] * zs[1] + dN[b][2] * zs[2], wd);
+    }
+    if (p < n) {
+      T* oe = out + e * (16 * n);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) oe[(b * 4 + f) * n + p] = o[b] * oscale;
+    }
+    __syncthreads();   // LDS of this element fully consumed before the next one
+  }
+}
+
+template <int K, int MD, typename T>
+static hipError_t op_big_launch(const DevView& v, const T* XP, const T* VT, double* Zout, T* out,
+                                double shift, int64_t begin, int64_t end, hipStream_t st) {
+  static std::atomic<int> max_blocks_cache{0};
+  int max_blocks = max_blocks_cache.load(std::memory_order_relaxed);
+  if (max_blocks == 0) {
+    int dev = 0, ncu = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_op_big<K, MD, T>, 256, 0);
+    if (e != hipSuccess) return e;
+    const int mb = ncu * (per_cu > 0 ? per_cu : 1);
+    max_blocks = mb < 8 ? 8 : mb / 8 * 8;
+    max_blocks_cache.store(max_blocks, std::memory_order_relaxed);
+  }
+  int64_t nb = (end - begin + 7) / 8 * 8;
+  if (nb > max_blocks) nb = max_blocks;
+  k_op_big<K, MD, T><<<(unsigned)nb, 256, 0, st>>>(v, XP, VT, Zout, out, T(shift), begin, end);
+  return hipGetLastError();
+}
+
+template <int K>
+static hipError_t op_big_dispatch(const DevView& v, int mode, const double* XP, const double* VT,
+                                  double* Zout, double* out, double shift, int64_t begin, int64_t end,
+                                  hipStream_t st) {
+  switch (mode) {
+    case MODE_RESID: return op_big_launch<K, MODE_RESID>(v, XP, VT, Zout, out, shift, begin, end, st);
+    case MODE_RESID | MODE_STOREZ:
+      return op_big_launch<K, MODE_RESID | MODE_STOREZ>(v, XP, VT, Zout, out, shift, begin, end, st);
+    case 0: return op_big_launch<K, 0>(v, XP, VT, Zout, out, shift, begin, end, st);
+    case MODE_NOLS: return op_big_launch<K, MODE_NOLS>(v, XP, VT, Zout, out, shift, begin, end, st);
+    case MODE_NEWTON: return op_big_launch<K, MODE_NEWTON>(v, XP, VT, Zout, out, shift, begin, end, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int K>
+static hipError_t op_big_dispatch(const DevView& v, int mode, const float* XP, const float* VT,
+                                  float* out, double shift, int64_t begin, int64_t end, hipStream_t st) {
+  switch (mode) {
+    case 0: return op_big_launch<K, 0>(v, XP, VT, nullptr, out, shift, begin, end, st);
+    case MODE_NOLS: return op_big_launch<K, MODE_NOLS>(v, XP, VT, nullptr, out, shift, begin, end, st);
+    case MODE_NEWTON: return op_big_launch<K, MODE_NEWTON>(v, XP, VT, nullptr, out, shift, begin, end, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // ------------------------------------------------------------- dispatch
 template <typename T>
 struct OpArgs {
@@ -642,7 +985,10 @@ hipError_t launch_elem(const DevView& v, int mode, const double* XP, const doubl
   const OpArgs<double> a{XP, VT, out, Zout};
   switch (v.K) {
 #define CASE(k) case k: return op_dispatch<k>(v, mode, a, shift, begin, end, st);
-    TSGLS_FOR_EACH_K(CASE)
+    TSGLS_FOR_EACH_K_SMALL(CASE)
+#undef CASE
+#define CASE(k) case k: return op_big_dispatch<k>(v, mode, XP, VT, Zout, out, shift, begin, end, st);
+    TSGLS_FOR_EACH_K_LARGE(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
   }
@@ -656,7 +1002,10 @@ hipError_t launch_elem_f32(const DevView& v, int mode, const float* XP, const fl
   const OpArgs<float> a{XP, VT, out, nullptr};
   switch (v.K) {
 #define CASE(k) case k: return op_dispatch<k>(v, mode, a, shift, begin, end, st);
-    TSGLS_FOR_EACH_K(CASE)
+    TSGLS_FOR_EACH_K_SMALL(CASE)
+#undef CASE
+#define CASE(k) case k: return op_big_dispatch<k>(v, mode, XP, VT, out, shift, begin, end, st);
+    TSGLS_FOR_EACH_K_LARGE(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
   }

@@ -98,7 +98,7 @@ k_face_lin(DevView v, const double* __restrict__ UTs, double* __restrict__ aneg)
 // sums, per Neumann node, lam_q(node) y over its incident faces and points in
 // a fixed order (deterministic), and for the residual subtracts the traction.
 template <int K>
-__global__ void __launch_bounds__(128)
+__global__ void __launch_bounds__(256)   // 3n lanes rounded up to a wave: 192 at K = 31
 k_face_point(DevView v, const double* __restrict__ Y, const double* __restrict__ Ys, int resid,
              const double* __restrict__ an) {
   __shared__ double su[3 * Dim<K>::n];
@@ -159,6 +159,7 @@ hipError_t launch_face_lin(const DevView& v, const double* UTs, double* aneg, hi
 hipError_t launch_face_point(const DevView& v, const double* Y, const double* Ys, int resid,
                              const double* an, hipStream_t st) {
   if (v.n_fnodes == 0 || v.n_faces == 0) return hipSuccess;
+  static_assert(3 * Dim<31>::n <= 256, "face point lanes within the launch bound");
   switch (v.K) {
 #define CASE(k)                                                                                   \
   case k:                                                                                         \

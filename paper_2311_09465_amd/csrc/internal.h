@@ -6,8 +6,14 @@
 
 namespace tsgls {
 
-// Harmonic counts K the kernels are instantiated for.
-#define TSGLS_FOR_EACH_K(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(11) X(15)
+// Harmonic counts K the kernels are instantiated for.  The element operator,
+// tau, the Jacobi diagonal and the tracer have register-blocked kernels for
+// the small set and LDS-staged kernels for the large set (n = 63 modes per
+// field does not fit the register-blocked lane layouts); the other kernels
+// are instantiated for both.
+#define TSGLS_FOR_EACH_K_SMALL(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(11) X(15)
+#define TSGLS_FOR_EACH_K_LARGE(X) X(31)
+#define TSGLS_FOR_EACH_K(X) TSGLS_FOR_EACH_K_SMALL(X) TSGLS_FOR_EACH_K_LARGE(X)
 
 // Mode positions.  Inside the element operator the n = 2K+1 real modes of a
 // field sit at "positions" p: mode 2k-1 (cos k wt) at p = 2k-2, mode 2k

@@ -1,10 +1,10 @@
-"""Mode sweep on the 200k-tet junction (h = 0.081): for K = 3, 7, 15 the
+"""Mode sweep on the 200k-tet junction (h = 0.081): for K = 3, 7, 15, 31 the
 library's residual and tangent product (FP64 and the FP32 element operator)
 are compared with the oracle on sampled nodes, whose rows the oracle gives
 exactly from the elements and Neumann faces around them.  The errors against
 the oracle are printed per K; tolerances as in the small-mesh parity tests
 (FP64 1e-11, FP32 tangent 16 units of FP32 roundoff = 1e-6, relative to the
-largest sampled entry).  K = 31 (63 modes) is outside the compiled set.
+largest sampled entry).  K = 31 runs the LDS-staged large-K kernels.
 """
 import numpy as np
 import pytest
@@ -19,7 +19,7 @@ TOL = 1e-11
 TOL32 = 1e-6
 
 
-@pytest.mark.parametrize("K", [3, 7, 15])
+@pytest.mark.parametrize("K", [3, 7, 15, 31])
 def test_mode_sweep_junction_200k(K):
     import paper_2311_09465_amd as T
     log(f"[gpu] mode sweep junction h=0.081 K={K}: building mesh")
