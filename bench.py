@@ -560,6 +560,59 @@ def junction_time_to_1e8():
     return out
 
 
+def mode_sweep_200k(ks=(3, 7, 15, 31), reps=20):
+    """Per-K cost on the 200k-tet junction (h = 0.081, Re = 500, Wo = 10) at
+    a seeded state (initial guess + 0.05 noise): linearize (tau at every
+    point, residual) and the tangent product in FP64 and with the FP32
+    element operator, back to back after warm-ups, with the product rate in
+    the metric's unit and the FP32 product's max-norm difference from the
+    FP64 one relative to its largest entry."""
+    import numpy as np
+    import torch
+    import paper_2311_09465_amd as T
+    from workloads import junction_problem, initial_guess
+    out = {}
+    for K in ks:
+        prob = junction_problem(h=0.081, K=K, Re=500.0, Wo=10.0, seed=1)
+        rng = np.random.default_rng(100 + K)
+        y0 = initial_guess(prob)
+        noise = 0.05 * rng.standard_normal(y0.shape)
+        noise[..., 1] = 0.0
+        noise[prob.dirichlet_nodes, :3] = 0.0
+        y = torch.from_numpy(y0 + noise).cuda()
+        v = torch.from_numpy(rng.standard_normal(y0.shape)).cuda()
+        s = T.Solver.from_problem(prob)
+        r = torch.zeros_like(y)
+        o64, o32 = torch.zeros_like(y), torch.zeros_like(y)
+
+        def timed(call, n):
+            call()
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            for _ in range(n):
+                call()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - a) / n * 1e3
+
+        lin_ms = timed(lambda: s.linearize(y, r), 3)
+        s.jv(v, o32, "picard", precision="f32")
+        jv64 = timed(lambda: s.jv(v, o64, "picard"), reps)
+        jv32 = timed(lambda: s.jv(v, o32, "picard", precision="f32"), reps)
+        torch.cuda.synchronize()
+        diff = float((o32 - o64).abs().max() / o64.abs().max())
+        dof = prob.mesh.n_nodes * 4 * (2 * K + 1)
+        out[f"K{K}"] = dict(n=2 * K + 1, M=3 * K + 1, linearize_ms=round(lin_ms, 3),
+                            jv_f64_ms=round(jv64, 3), jv_f32_ms=round(jv32, 3),
+                            jv_f64_gdof_modes_s=round(dof / jv64 / 1e6, 4),
+                            jv_f32_gdof_modes_s=round(dof / jv32 / 1e6, 4),
+                            f32_vs_f64_rel_maxdiff=float("%.2e" % diff))
+        print(f"mode sweep K={K}: {out[f'K{K}']}", file=sys.stderr, flush=True)
+        s.close()
+        del s, y, v, r, o64, o32
+        torch.cuda.empty_cache()
+    return dict(workload="junction_200k", n_tets=prob.mesh.n_tets, n_nodes=prob.mesh.n_nodes, **out)
+
+
 def junction_re500_attempt(prob, steps=25):
     """The headline junction (Re = 500) under the same pseudo-time schedule,
     bounded to `steps` pseudo-time steps of at most 300 products: the relative
@@ -930,6 +983,7 @@ def main():
         if not args.no_solves:
             out["time_to_1e8_junction"] = junction_time_to_1e8()
             out["junction_re500_pseudo_time"] = junction_re500_attempt(prob)
+            out["mode_sweep"] = mode_sweep_200k()
             print("batched solves", file=sys.stderr, flush=True)
             out["batched"] = batched_run(64)
             print("learned warm start", file=sys.stderr, flush=True)

@@ -162,9 +162,18 @@ struct TauCfg {
   static constexpr int PG = PH1 > PH2 ? PH1 : PH2;
 };
 
+//
+// Warm start (Vin not null): Vin holds orthonormal eigenvectors of S from an
+// earlier linearization, [point][a][c] with column c the eigenvector of lane
+// c.  The Jacobi then runs on the columns of W = S V instead of S: for any
+// orthonormal V its rotations J make W J orthogonal, so V J diagonalizes S^2
+// and hence S, and the same tau follows; when S changed little since V was
+// taken, W is nearly orthogonal already and few sweeps remain.  Vout (not
+// null) receives the new eigenvectors w_c / |w_c| in the same layout.
 template <int K>
 __global__ void __launch_bounds__(TauCfg<K>::BLOCK)
-k_tau(DevView v, const double* __restrict__ Y, double* __restrict__ tau) {
+k_tau(DevView v, const double* __restrict__ Y, double* __restrict__ tau,
+      const double* Vin, double* Vout) {   // Vin and Vout may be the same array
   using C = TauCfg<K>;
   constexpr int n = C::n, M = C::M, S = Dim<K>::S, NP = C::NP, P = Dim<K>::P, GB = C::GB;
   constexpr int PW = C::PW, QS = C::QS, QW = C::QW;
@@ -269,11 +278,40 @@ k_tau(DevView v, const double* __restrict__ Y, double* __restrict__ tau) {
       w[a] = a == c ? acc + kap : acc;
     }
   }
+  if (Vin) {   // w = S v_c (uniform branch)
+    double* sS = lds + g * C::PG;          // S [row][col], over the first-phase arrays
+    static_assert(n * n <= C::PG, "S fits the point's LDS");
+    __syncthreads();
+    if (valid && c < n) {
+#pragma unroll
+      for (int a = 0; a < n; ++a) sS[a * n + c] = w[a];
+    }
+    __syncthreads();
+    if (valid && c < n) {
+      const double* vp = Vin + gq * (n * n) + c;
+      double vc[n];
+#pragma unroll
+      for (int b = 0; b < n; ++b) vc[b] = vp[b * n];
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < n; ++b) acc = fma(sS[a * n + b], vc[b], acc);
+        w[a] = acc;
+      }
+    }
+  }
   jacobi_columns<n, NP>(w, c);
   double l2 = 0.0;
 #pragma unroll
   for (int a = 0; a < n; ++a) l2 = fma(w[a], w[a], l2);
   const double sc = l2 > 0.0 ? pow(l2, -0.625) : 0.0;   // lambda^(-5/4), lambda = |w|
+  if (Vout && valid && c < n) {
+    double* vp = Vout + gq * (n * n) + c;
+    const double inv = l2 > 0.0 ? rsq_nr(l2) : 0.0;
+#pragma unroll
+    for (int a = 0; a < n; ++a) vp[a * n] = w[a] * inv;
+  }
   __syncthreads();   // the first-phase arrays are reused below
   if constexpr (C::MFMA_OUT) {
     // Q[k][p] = w_k[pos_mode(p)] lambda_k^(-5/4); tau over positions = Q^T Q
@@ -873,14 +911,15 @@ hipError_t launch_prep_time_f32(int K, const double* Y, const double* Ys, const 
   return prep_launch<float>(K, Y, Ys, nflag, masked, F, XT, XP, nn, st, fv, aneg, fresid);
 }
 
-hipError_t launch_tau(const DevView& v, const double* Y, double* tau, hipStream_t st) {
+hipError_t launch_tau(const DevView& v, const double* Y, double* tau, hipStream_t st,
+                      const double* Vin, double* Vout) {
   if (v.n_tets == 0) return hipSuccess;
   switch (v.K) {
 #define CASE(k)                                                                          \
   case k: {                                                                              \
     const int64_t groups = v.n_tets * 4;                                                 \
     const unsigned grid = (unsigned)((groups + TauCfg<k>::GB - 1) / TauCfg<k>::GB);      \
-    k_tau<k><<<grid, TauCfg<k>::BLOCK, 0, st>>>(v, Y, tau);                              \
+    k_tau<k><<<grid, TauCfg<k>::BLOCK, 0, st>>>(v, Y, tau, Vin, Vout);                  \
     break;                                                                               \
   }
     TSGLS_FOR_EACH_K_SMALL(CASE)

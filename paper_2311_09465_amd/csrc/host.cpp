@@ -39,6 +39,9 @@ struct tsgls_ctx {
   double* VT = nullptr;
   double* XP = nullptr;         // [n_nodes][4][PW] modes at their positions (operator input)
   double* tau = nullptr;
+  double* tauV = nullptr;       // [E][4][n][n] eigenvectors of S at the last linearization
+                                // (warm start of the next one; K <= 15), or null
+  bool tauV_ok = false;         // tauV holds orthonormal eigenvectors
   double* Z = nullptr;
   double* rs = nullptr;         // scratch residual for linearize
   int32_t* fconn = nullptr;
@@ -318,14 +321,33 @@ int linearize_tracer(tsgls_ctx* c, const double* y, double* r) {
   return apply_tracer(c, r, y, nullptr, 1);
 }
 
+// Eigenvectors of S kept between linearizations (the Jacobi iteration of tau
+// starts from them); allocated on the first linearization for K <= 15.  A
+// failed allocation only means cold starts.
+void ensure_tauV(tsgls_ctx* c) {
+  if (c->tauV || c->K > 15) return;
+  const size_t cnt = (size_t)c->E * 4 * c->n * c->n;
+  void* q = nullptr;
+  if (hipMalloc(&q, cnt * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  c->allocs.push_back(q);
+  c->dev_bytes += cnt * sizeof(double);
+  c->tauV = static_cast<double*>(q);
+  c->tauV_ok = false;
+}
+
 int linearize_impl(tsgls_ctx* c, const double* y, double* r) {
   if (c->tracer) return linearize_tracer(c, y, r ? r : c->rs);
   DevView v = view(c);
   c->lin32 = false;
+  ensure_tauV(c);
   HIPCHK(c, launch_prep_time(c->K, y, nullptr, c->nflag, 0, c->F, c->UT, c->XP, c->nn, c->st));
   {
     ProfScope ps(c, TSGLS_PROF_TAU);
-    HIPCHK(c, launch_tau(v, y, c->tau, c->st));
+    HIPCHK(c, launch_tau(v, y, c->tau, c->st, c->tauV_ok ? c->tauV : nullptr, c->tauV));
+    c->tauV_ok = c->tauV != nullptr;
   }
   HIPCHK(c, launch_face_lin(v, c->UT, c->aneg, c->st));
   double* rr = r ? r : c->rs;
@@ -1147,7 +1169,7 @@ int tsgls_residual(tsgls_ctx* c, const double* y, double* r) {
   v.tau = c->taur;
   v.aneg = c->anegr;
   HIPCHK(c, launch_prep_time(c->K, y, nullptr, c->nflag, 0, c->F, c->UTr, c->XP, c->nn, c->st));
-  HIPCHK(c, launch_tau(v, y, c->taur, c->st));
+  HIPCHK(c, launch_tau(v, y, c->taur, c->st, c->tauV_ok ? c->tauV : nullptr, nullptr));
   HIPCHK(c, launch_face_lin(v, c->UTr, c->anegr, c->st));
   return apply_operator(c, v, MODE_RESID, y, nullptr, nullptr, r, 0.0, c->anegr, 1);
 }

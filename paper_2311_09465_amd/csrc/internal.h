@@ -95,8 +95,13 @@ hipError_t launch_prep_time_f32(int K, const double* Y, const double* Ys,
                                 int fresid = 0);
 // Positions per field row of XP (16 or 32).
 int pos_width(int K);
+// tau at every quadrature point.  Vin / Vout (optional, K <= 15 only):
+// eigenvectors of S from an earlier linearization as the starting basis of
+// the Jacobi iteration / the new eigenvectors, [E][4][n][n] (row a, column
+// c).  The result does not depend on Vin beyond rounding (any orthonormal
+// basis converges to the same tau).
 hipError_t launch_tau(const DevView& v, const double* Y, double* tau,
-                      hipStream_t st);
+                      hipStream_t st, const double* Vin = nullptr, double* Vout = nullptr);
 // Element operator over elements [begin, end) (processing order); input
 // modes from XP, direction samples VT (tangent modes), writes the per-element
 // contributions out[E][4][4][n] over positions.  Zout (mode & MODE_STOREZ)

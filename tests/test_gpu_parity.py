@@ -189,3 +189,33 @@ def test_error_codes():
         s.solve(to_dev(y))
     st = s.solve(to_dev(rand_state(prob, 1)), max_newton=1, rtol=1e-14)
     assert st["status"] == 1 and st["newton_iters"] == 1
+
+
+@pytest.mark.parametrize("name", ["cube3_K1", "cube4_K3", "cube3_K6", "junction_K3", "cube2_K11"])
+def test_tau_warm_start_parity(name):
+    """tau's Jacobi iteration starts from the eigenvectors of the previous
+    linearization: linearize at y1, then at y2 (warm start from y1's basis),
+    then at y2 again (from its own basis); tau and the residual of each match
+    the oracle at that state, and a residual evaluation between them (which
+    reads the stored basis) does too."""
+    log(f"[gpu] tau warm start {name}")
+    prob = _case(name)
+    s = _solver(prob)
+    par = O.Params.from_problem(prob)
+    xyz, tets = prob.mesh.xyz, prob.mesh.tets
+    y1 = rand_state(prob, 21)
+    y2 = y1 + 0.05 * rand_state(prob, 22)
+    y2[..., 1] = 0.0
+    y2[prob.dirichlet_nodes, :3] = prob.dirichlet_values
+    r = to_dev(np.zeros_like(y1))
+    for y in (y1, y2, y2):
+        s.linearize(to_dev(y), r)
+        tg = unpack(s.get_tau(), 2 * prob.K + 1)
+        tr = tau_complex_to_real(O.linearize(par, xyz, tets, y)["tau"], prob.K)
+        rr = O.residual(par, xyz, tets, y)
+        et = np.abs(tg - tr).max() / np.abs(tr).max()
+        er = np.abs(to_host(r) - rr).max() / np.abs(rr).max()
+        s.residual(to_dev(y1), r)
+        er1 = np.abs(to_host(r) - O.residual(par, xyz, tets, y1)).max() / np.abs(rr).max()
+        log(f"[gpu]   tau {et:.2e} residual {er:.2e} residual(y1) {er1:.2e}")
+        assert et <= TOL and er <= TOL and er1 <= TOL
