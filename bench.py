@@ -538,8 +538,8 @@ def junction_time_to_1e8():
     """Time to 1e-8 on the 200k-tet junction (h = 0.081, K = 3, Re = 100,
     Wo = 10) from the initial guess: pseudo-time stepping with one Newton
     iteration per step (Newton tangent, tau frozen), switched-evolution step
-    size from 0.1 bounded by 2, GMRES(100) to 0.1; FP64 tangent and FP32
-    tangent (FP64 residual and Krylov)."""
+    size from 0.1 bounded by 2, GMRES(100) to 0.1; FP64 tangent, FP32
+    tangent and FP32 tangent with tau in bf16 (FP64 residual and Krylov)."""
     import torch
     import paper_2311_09465_amd as T
     from workloads import junction_problem, initial_guess
@@ -547,7 +547,7 @@ def junction_time_to_1e8():
     s = T.Solver.from_problem(prob)
     out = dict(workload="junction_200k_K3_Re100", n_tets=prob.mesh.n_tets, n_nodes=prob.mesh.n_nodes,
                solver={k: v for k, v in JUNCTION_SOLVE.items()})
-    for prec in ("f64", "f32"):
+    for prec in ("f64", "f32", "bf16"):
         y = torch.from_numpy(initial_guess(prob)).cuda()
         torch.cuda.synchronize()
         st = s.solve(y, tangent_precision=prec, **JUNCTION_SOLVE)
@@ -556,6 +556,7 @@ def junction_time_to_1e8():
                          rel_residual=float("%.3e" % st["rel_residual"]), rejected=st["rejected"])
         print(f"junction 200k time to 1e-8 ({prec}): {out[prec]}", file=sys.stderr, flush=True)
     out["f32_speedup"] = round(out["f64"]["seconds"] / out["f32"]["seconds"], 3)
+    out["bf16_speedup"] = round(out["f64"]["seconds"] / out["bf16"]["seconds"], 3)
     s.close()
     return out
 
@@ -927,40 +928,50 @@ def main():
         s.linearize(y)   # the state the products below were measured at
         # mixed precision: the same steps, from the same state, with the FP32
         # element operator in the tangent (residual, tau, diagonal and Krylov
-        # stay FP64); one FP32 product first allocates the FP32 copies
-        s.jv(v, o, args.jacobian, precision="f32")
-        y.copy_(y_start)
-        torch.cuda.synchronize()
-        s.profile(True)
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        s.solve(y, max_newton=args.steps, tangent_precision="f32", **step_kw)
-        torch.cuda.synchronize()
-        secs32 = time.perf_counter() - a
-        prof32 = {k: s.profile_get(k) for k in s.PROF}
-        s.profile(False)
-        l32, t32 = prof32["elem_tangent"]
-        avg32 = t32 / max(l32, 1) / 1e3
-        s.jv(v, o, args.jacobian, precision="f32")
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        for _ in range(reps):
-            s.jv(v, o, args.jacobian, precision="f32")
-        torch.cuda.synchronize()
-        jv32 = (time.perf_counter() - a) / reps * 1e3
-        out["mixed_f32_tangent"] = dict(
-            value=round(args.steps * m * dof / secs32 / 1e9, 4),
-            ms_per_step=round(secs32 / args.steps * 1e3, 3),
-            breakdown_ms_per_step={k: round(v_[1] / args.steps, 3) for k, v_ in prof32.items()},
-            elem_tangent_avg_launch_us=round(avg32 * 1e6, 2),
-            elem_tangent_tflops_fp32=round(fl / avg32 / 1e12, 3),
-            elem_tangent_algorithmic_bytes=round(jv_bytes(K, E, nn, args.jacobian, word=4)),
-            elem_tangent_traffic=None if tr is None else round(tr["f32_bytes_per_launch"]),
-            elem_tangent_hbm_frac_algorithmic=round(jv_bytes(K, E, nn, args.jacobian, word=4) / avg32
-                                                    / 1e9 / HBM_PEAK_GBS, 4),
-            elem_tangent_hbm_frac_measured=None if tr is None else round(
-                tr["f32_bytes_per_launch"] / avg32 / 1e9 / HBM_PEAK_GBS, 4),
-            jv_ms=round(jv32, 3))
+        # stay FP64), then the same with tau in bf16; one product of each kind
+        # first allocates its copies
+        def lower_precision(prec):
+            s.jv(v, o, args.jacobian, precision=prec)
+            y.copy_(y_start)
+            torch.cuda.synchronize()
+            s.profile(True)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            s.solve(y, max_newton=args.steps, tangent_precision=prec, **step_kw)
+            torch.cuda.synchronize()
+            secs_p = time.perf_counter() - a
+            prof_p = {k: s.profile_get(k) for k in s.PROF}
+            s.profile(False)
+            lp, tp = prof_p["elem_tangent"]
+            avg_p = tp / max(lp, 1) / 1e3
+            s.jv(v, o, args.jacobian, precision=prec)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            for _ in range(reps):
+                s.jv(v, o, args.jacobian, precision=prec)
+            torch.cuda.synchronize()
+            jv_p = (time.perf_counter() - a) / reps * 1e3
+            tau_word = 2 if prec == "bf16" else 4
+            n_, P_ = 2 * K + 1, (2 * K + 1) * (2 * K + 2) // 2
+            alg = jv_bytes(K, E, nn, args.jacobian, word=4) - E * 4.0 * (4 - tau_word) * P_
+            res = dict(
+                value=round(args.steps * m * dof / secs_p / 1e9, 4),
+                ms_per_step=round(secs_p / args.steps * 1e3, 3),
+                breakdown_ms_per_step={k: round(v_[1] / args.steps, 3) for k, v_ in prof_p.items()},
+                elem_tangent_avg_launch_us=round(avg_p * 1e6, 2),
+                elem_tangent_tflops_fp32=round(fl / avg_p / 1e12, 3),
+                elem_tangent_algorithmic_bytes=round(alg),
+                elem_tangent_hbm_frac_algorithmic=round(alg / avg_p / 1e9 / HBM_PEAK_GBS, 4),
+                jv_ms=round(jv_p, 3))
+            return res
+
+        out["mixed_f32_tangent"] = lower_precision("f32")
+        out["mixed_f32_tangent"]["elem_tangent_traffic"] = None if tr is None else round(
+            tr["f32_bytes_per_launch"])
+        out["mixed_f32_tangent"]["elem_tangent_hbm_frac_measured"] = None if tr is None else round(
+            tr["f32_bytes_per_launch"] / (out["mixed_f32_tangent"]["elem_tangent_avg_launch_us"] / 1e6)
+            / 1e9 / HBM_PEAK_GBS, 4)
+        out["bf16_tau_tangent"] = lower_precision("bf16")
         # time to 1e-8 on the small Womersley case (full solve, FP64, Picard)
         del s
         torch.cuda.empty_cache()

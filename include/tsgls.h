@@ -87,6 +87,12 @@ extern "C" {
  * solves (iterative refinement).  Face terms stay FP64. */
 #define TSGLS_PREC_F64 0
 #define TSGLS_PREC_F32 1
+/* TSGLS_PREC_F32 with tau stored and applied in bf16 (8-bit significand,
+ * round to nearest even, made from the FP64 tau once per linearization):
+ * the dominant operand stream of the product at half the FP32 bytes; the
+ * relative error of the product grows to order 1e-3, still far below the
+ * GMRES tolerance, and the FP64 residual of each Newton step corrects it. */
+#define TSGLS_PREC_BF16 2
 
 /* Pseudo-time schedule of tsgls_solve (section "Pseudo-time stepping": one
  * Newton iteration per pseudo-time step, the tangent shifted by
@@ -132,7 +138,7 @@ typedef struct {
   int jacobian;      /* TSGLS_JAC_* */
   double dt_pseudo;  /* pseudo-time step; <= 0 disables the mass shift */
   int verbose;       /* 1: one line per Newton step on stderr */
-  int tangent_precision;  /* TSGLS_PREC_F64 (0, default) or TSGLS_PREC_F32 */
+  int tangent_precision;  /* TSGLS_PREC_F64 (0, default), TSGLS_PREC_F32 or TSGLS_PREC_BF16 */
   int gmres_graph;   /* 1 (restart <= 32): each GMRES cycle is one HIP graph with
                         the least-squares update on the device, captured on the
                         first use of a (restart, tangent, dt_pseudo, precision)
@@ -220,7 +226,9 @@ int tsgls_jv(tsgls_ctx* ctx, const double* v, double* Jv, int jacobian,
  * (4 P E + 12 n E + 3 M n_nodes floats), allocated on the first such call
  * (TSGLS_ENOMEM if that fails) and refreshed once after each linearize.  The
  * result is within FP32 rounding of the FP64 product (relative error of
- * order 1e-6 of the largest entry). */
+ * order 1e-6 of the largest entry).  TSGLS_PREC_BF16 needs the same copies
+ * plus a bf16 copy of tau (4 P E 16-bit words); its result carries the bf16
+ * rounding of tau (relative error of order 1e-3). */
 int tsgls_jv_prec(tsgls_ctx* ctx, const double* v, double* Jv, int jacobian,
                   double dt_pseudo, int precision);
 

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libtsgls.so")
 TSGLS_OK = 0
 TSGLS_NOT_CONVERGED = 1
 JAC = {"picard": 0, "picard_nols": 1, "newton": 2}
-PREC = {"f64": 0, "f32": 1}
+PREC = {"f64": 0, "f32": 1, "bf16": 2}
 DT_SCHEDULE = {"fixed": 0, "ser": 1, "auto": 2}
 ERRORS = {-1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "EMESH", -5: "ENONFINITE", -6: "ESTATE",
           -7: "ESCRATCH"}

@@ -89,7 +89,17 @@ __device__ __forceinline__ float swap_pair(float x) {
 // (the launch repeated inside GMRES) fits three without spilling in FP64,
 // four in FP32.
 template <int MODE, typename T>
-constexpr int op_waves() { return MODE == 0 ? (sizeof(T) == 4 ? 4 : 3) : 1; }
+constexpr int op_waves() { return (MODE & ~MODE_TAU16) == 0 ? (sizeof(T) == 4 ? 4 : 3) : 1; }
+
+// bf16 bit pattern -> FP32 (bf16 is the top half of an FP32 word)
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Entry idx of the packed tau of the operator's arithmetic (bf16 copy for MODE_TAU16).
+template <int MODE, typename T>
+__device__ __forceinline__ T tau_entry(const DevView& v, const T* tau, int64_t idx) {
+  if constexpr ((MODE & MODE_TAU16) != 0) return T(bf16_to_f32(v.tau16[idx]));
+  else return tau[idx];
+}
 
 // Frozen fields of the linearization in the kernel's arithmetic type.
 template <typename T>
@@ -219,7 +229,8 @@ k_op(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int j = 0; j < NTL; ++j) tv[q][j] = tok[j] ? TAU[(e0 * 4 + q) * P + lane + 64 * j] : T(0);
+      for (int j = 0; j < NTL; ++j)
+        tv[q][j] = tok[j] ? tau_entry<MODE, T>(v, TAU, (e0 * 4 + q) * P + lane + 64 * j) : T(0);
   }
 
   for (int64_t e = lo + jx; e < hi; e += nbx) {
@@ -322,7 +333,8 @@ k_op(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int j = 0; j < NTL; ++j) tv[q][j] = tok[j] ? TAU[(en * 4 + q) * P + lane + 64 * j] : T(0);
+        for (int j = 0; j < NTL; ++j)
+          tv[q][j] = tok[j] ? tau_entry<MODE, T>(v, TAU, (en * 4 + q) * P + lane + 64 * j) : T(0);
     }
     __syncthreads();
 
@@ -741,12 +753,12 @@ k_op_big(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
     // ---- z = tau_q L (and tau_q grad p without LS coupling), G = gal - Omega z
     T z[3] = {T(0), T(0), T(0)}, zc[3] = {T(0), T(0), T(0)};
     if (p < n) {
-      const T* tq = fz.tau + (e * 4 + q) * P;
+      const int64_t tq = (e * 4 + q) * P;
       const T* l0 = sL + (q * 3) * RP;
 #pragma unroll 2
       for (int k = 0; k < n; ++k) {
         const int lo_ = p < k ? p : k, hi_ = p < k ? k : p;
-        const T t = tq[pk_index(lo_, hi_, n)];
+        const T t = tau_entry<MODE, T>(v, fz.tau, tq + pk_index(lo_, hi_, n));
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
           z[i] = tfma(t, l0[i * RP + k], z[i]);
@@ -912,9 +924,10 @@ template <int K>
 static hipError_t op_big_dispatch(const DevView& v, int mode, const float* XP, const float* VT,
                                   float* out, double shift, int64_t begin, int64_t end, hipStream_t st) {
   switch (mode) {
-    case 0: return op_big_launch<K, 0>(v, XP, VT, nullptr, out, shift, begin, end, st);
-    case MODE_NOLS: return op_big_launch<K, MODE_NOLS>(v, XP, VT, nullptr, out, shift, begin, end, st);
-    case MODE_NEWTON: return op_big_launch<K, MODE_NEWTON>(v, XP, VT, nullptr, out, shift, begin, end, st);
+#define CASE(md) case md: return op_big_launch<K, md>(v, XP, VT, nullptr, out, shift, begin, end, st);
+    CASE(0) CASE(MODE_NOLS) CASE(MODE_NEWTON)
+    CASE(MODE_TAU16) CASE(MODE_TAU16 | MODE_NOLS) CASE(MODE_TAU16 | MODE_NEWTON)
+#undef CASE
     default: return hipErrorInvalidValue;
   }
 }
@@ -971,9 +984,10 @@ template <int K>
 static hipError_t op_dispatch(const DevView& v, int mode, const OpArgs<float>& a, double shift,
                               int64_t begin, int64_t end, hipStream_t st) {
   switch (mode) {
-    case 0: return op_launch<K, 0>(v, a, shift, begin, end, st);
-    case MODE_NOLS: return op_launch<K, MODE_NOLS>(v, a, shift, begin, end, st);
-    case MODE_NEWTON: return op_launch<K, MODE_NEWTON>(v, a, shift, begin, end, st);
+#define CASE(md) case md: return op_launch<K, md>(v, a, shift, begin, end, st);
+    CASE(0) CASE(MODE_NOLS) CASE(MODE_NEWTON)
+    CASE(MODE_TAU16) CASE(MODE_TAU16 | MODE_NOLS) CASE(MODE_TAU16 | MODE_NEWTON)
+#undef CASE
     default: return hipErrorInvalidValue;
   }
 }
@@ -999,6 +1013,7 @@ hipError_t launch_elem_f32(const DevView& v, int mode, const float* XP, const fl
   if (end <= begin) return hipSuccess;
   if (mode & (MODE_RESID | MODE_STOREZ)) return hipErrorInvalidValue;
   if (!v.UT32 || !v.tau32 || (!v.Z32 && (mode & MODE_NEWTON))) return hipErrorInvalidValue;
+  if ((mode & MODE_TAU16) && !v.tau16) return hipErrorInvalidValue;
   const OpArgs<float> a{XP, VT, out, nullptr};
   switch (v.K) {
 #define CASE(k) case k: return op_dispatch<k>(v, mode, a, shift, begin, end, st);

@@ -100,6 +100,8 @@ struct tsgls_ctx {
   float* UT32 = nullptr;
   float* Z32 = nullptr;
   bool lin32 = false;     // the copies match the last linearize
+  uint16_t* tau16 = nullptr;   // tau rounded to bf16 (TSGLS_PREC_BF16), allocated on first use
+  bool lin16 = false;          // tau16 matches the last linearize
   // optional per-launch timing with HIP events (benchmark support)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -186,6 +188,7 @@ DevView view(const tsgls_ctx* c) {
   v.UT32 = c->UT32;
   v.tau32 = c->tau32;
   v.Z32 = c->Z32;
+  v.tau16 = c->tau16;
   v.noff = c->noff;
   v.ninc = c->ninc;
   v.fconn = c->fconn;
@@ -316,6 +319,7 @@ int linearize_tracer(tsgls_ctx* c, const double* y, double* r) {
   if (c->nf) HIPCHK(c, launch_face_lin(v, c->UT, c->aneg, c->st));   // |A_n|_- of the velocity
   c->linearized = true;
   c->lin32 = false;
+  c->lin16 = false;
   if (!r) return TSGLS_OK;
   HIPCHK(c, launch_prep_time(c->K, y, nullptr, c->nflag, 0, c->F, c->VT, c->XP, c->nn, c->st));
   return apply_tracer(c, r, y, nullptr, 1);
@@ -342,6 +346,7 @@ int linearize_impl(tsgls_ctx* c, const double* y, double* r) {
   if (c->tracer) return linearize_tracer(c, y, r ? r : c->rs);
   DevView v = view(c);
   c->lin32 = false;
+  c->lin16 = false;
   ensure_tauV(c);
   HIPCHK(c, launch_prep_time(c->K, y, nullptr, c->nflag, 0, c->F, c->UT, c->XP, c->nn, c->st));
   {
@@ -372,8 +377,18 @@ int ensure_lin32(tsgls_ctx* c) {
   return TSGLS_OK;
 }
 
+// bf16 copy of tau for TSGLS_PREC_BF16 (made once per linearization).
+int ensure_tau16(tsgls_ctx* c) {
+  if (c->lin16) return TSGLS_OK;
+  if (!c->tau16) CHK(dalloc(c, &c->tau16, (size_t)c->E * 4 * c->P));
+  HIPCHK(c, launch_to_bf16(c->tau, c->tau16, c->E * 4 * c->P, c->st));
+  c->lin16 = true;
+  return TSGLS_OK;
+}
+
 // out = J (x * xs) (xs: optional entrywise scale of the input, e.g. the
-// right preconditioner inside GMRES).  prec TSGLS_PREC_F32 runs the element
+// right preconditioner inside GMRES).  prec TSGLS_PREC_F32 (or _BF16, tau in
+// bf16) runs the element
 // operator in FP32; the node sums and the face terms stay FP64.
 int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt, const double* xs = nullptr,
             int prec = TSGLS_PREC_F64) {
@@ -393,7 +408,9 @@ int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt, cons
     return apply_operator(c, v, mode, x, c->VT, nullptr, out, shift, c->aneg, 0, xs, true);
   }
   CHK(ensure_lin32(c));
+  if (prec == TSGLS_PREC_BF16) CHK(ensure_tau16(c));
   v = view(c);
+  const int mode32 = prec == TSGLS_PREC_BF16 ? (mode | MODE_TAU16) : mode;
   float* XP32 = reinterpret_cast<float*>(c->XP);
   float* VT32 = reinterpret_cast<float*>(c->VT);
   float* eb32 = reinterpret_cast<float*>(c->ebuf);
@@ -401,7 +418,7 @@ int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt, cons
                                  c->nf ? &v : nullptr, c->aneg, 0));
   {
     ProfScope ps(c, TSGLS_PROF_ELEM_TANGENT);
-    HIPCHK(c, launch_elem_f32(v, mode, XP32, VT32, eb32, shift, 0, c->E, c->st));
+    HIPCHK(c, launch_elem_f32(v, mode32, XP32, VT32, eb32, shift, 0, c->E, c->st));
   }
   {
     ProfScope ps(c, TSGLS_PROF_GATHER);
@@ -700,7 +717,8 @@ int gmres_graph(tsgls_ctx* c, const double* b, double* x, double tol, int m, int
     HIPCHK(c, hipEventCreateWithFlags(&c->gev[1], hipEventDisableTiming));
   }
   c->gm.m = m;
-  if (prec == TSGLS_PREC_F32) CHK(ensure_lin32(c));
+  if (prec != TSGLS_PREC_F64) CHK(ensure_lin32(c));
+  if (prec == TSGLS_PREC_BF16) CHK(ensure_tau16(c));
   const tsgls_ctx::GraphKey key{m, jac, prec, dt, b, x};
   const bool same = c->gexec && c->gkey.m == key.m && c->gkey.jac == key.jac &&
                     c->gkey.prec == key.prec && c->gkey.dt == key.dt && c->gkey.b == key.b &&
@@ -1208,7 +1226,7 @@ int tsgls_jv_prec(tsgls_ctx* c, const double* v, double* Jv, int jacobian, doubl
   if (!c) return TSGLS_EINVAL;
   if (!v || !Jv || v == Jv) return fail(c, TSGLS_EINVAL, "bad vectors");
   if (jacobian < 0 || jacobian > 2) return fail(c, TSGLS_EINVAL, "bad tangent variant %d", jacobian);
-  if (precision != TSGLS_PREC_F64 && precision != TSGLS_PREC_F32)
+  if (precision != TSGLS_PREC_F64 && precision != TSGLS_PREC_F32 && precision != TSGLS_PREC_BF16)
     return fail(c, TSGLS_EINVAL, "bad precision %d", precision);
   return jv_impl(c, v, Jv, jacobian, dt_pseudo, nullptr, precision);
 }
@@ -1245,7 +1263,8 @@ int tsgls_solve(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_
   if (!y || !o) return fail(c, TSGLS_EINVAL, "null argument");
   if (o->restart < 1 || o->restart > 1000 || o->max_newton < 0 || o->max_matvec < 1 || !(o->rtol > 0) ||
       !(o->lin_rtol > 0) || o->jacobian < 0 || o->jacobian > 2 ||
-      (o->tangent_precision != TSGLS_PREC_F64 && o->tangent_precision != TSGLS_PREC_F32) ||
+      (o->tangent_precision != TSGLS_PREC_F64 && o->tangent_precision != TSGLS_PREC_F32 &&
+       o->tangent_precision != TSGLS_PREC_BF16) ||
       o->dt_schedule < TSGLS_DT_FIXED || o->dt_schedule > TSGLS_DT_AUTO || !std::isfinite(o->dt_max) ||
       !std::isfinite(o->dt_pseudo))
     return fail(c, TSGLS_EINVAL, "bad solve options");

@@ -40,6 +40,7 @@ enum : int {
   MODE_NEWTON = 2,   // keep the derivative of A (needs frozen tau L(u))
   MODE_NOLS = 4,     // drop least-squares terms of G_i and D_i
   MODE_STOREZ = 8,   // store z = tau L(u) (modal) during a residual pass
+  MODE_TAU16 = 16,   // FP32 operator with tau read as bf16 (v.tau16)
 };
 
 // Device view of one mesh + linearization.  All pointers are device memory.
@@ -56,6 +57,7 @@ struct DevView {
   const float* UT32;         // FP32 copies of UT, tau, Z (mixed-precision tangent) or null
   const float* tau32;
   const float* Z32;
+  const uint16_t* tau16;     // tau rounded to bf16 (bit patterns), same layout, or null
   const int32_t* noff;       // [n_nodes+1] node -> incident element slots
   const int32_t* ninc;       // element*4 + local node, ascending element
   const int32_t* fconn;      // [nf][3] Neumann faces
@@ -110,7 +112,8 @@ hipError_t launch_elem(const DevView& v, int mode, const double* XP,
                        const double* VT, double* Zout, double* out,
                        double shift, int64_t begin, int64_t end, hipStream_t st);
 // Mixed-precision tangent: the same operator in FP32 (modes 0, MODE_NOLS,
-// MODE_NEWTON) on the FP32 copies v.UT32, v.tau32, v.Z32.
+// MODE_NEWTON) on the FP32 copies v.UT32, v.tau32, v.Z32; with MODE_TAU16
+// also set, tau comes from the bf16 copy v.tau16 instead of v.tau32.
 hipError_t launch_elem_f32(const DevView& v, int mode, const float* XP, const float* VT,
                            float* out, double shift, int64_t begin, int64_t end, hipStream_t st);
 hipError_t launch_diag(const DevView& v, double* d, double shift,
@@ -171,6 +174,8 @@ hipError_t launch_cd(const DevView& v, const double* XP, double kappa, double* o
                      int64_t end, hipStream_t st);
 // y = x rounded to FP32
 hipError_t launch_to_f32(const double* x, float* y, int64_t n, hipStream_t st);
+// y = bit pattern of x rounded to bf16 (round to nearest even)
+hipError_t launch_to_bf16(const double* x, uint16_t* y, int64_t n, hipStream_t st);
 // partial[b*J + j] = sum over block b's chunk of V[j]*w; J <= 128.
 hipError_t launch_multidot(const double* V, int64_t ldv, int J, const double* w,
                            double* partial, int nblocks, int64_t n, hipStream_t st);

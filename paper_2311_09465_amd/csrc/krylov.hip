@@ -71,6 +71,22 @@ hipError_t launch_fill(double* x, double a, int64_t n, hipStream_t st) {
   k_fill<<<grid_for(n, 256), 256, 0, st>>>(x, a, n);
   return hipGetLastError();
 }
+// bf16 keeps the top 16 bits of the FP32 value; the low half is rounded to
+// nearest, ties to even (finite inputs).
+__global__ void k_to_bf16(const double* __restrict__ x, uint16_t* __restrict__ y, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t u = __float_as_uint((float)x[i]);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  y[i] = (uint16_t)(u >> 16);
+}
+
+hipError_t launch_to_bf16(const double* x, uint16_t* y, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_to_bf16<<<grid_for(n, 256), 256, 0, st>>>(x, y, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_to_f32(const double* x, float* y, int64_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   k_to_f32<<<grid_for(n, 256), 256, 0, st>>>(x, y, n);

@@ -132,3 +132,57 @@ def test_jv_prec_rejects_bad_precision():
     rc = T.lib().tsgls_jv_prec(s._h, C.c_void_p(y.data_ptr()), C.c_void_p(out.data_ptr()), 0,
                                C.c_double(0.0), 7)
     assert rc == -1
+
+
+# --------------------------------------------------------------- bf16 tau
+# TSGLS_PREC_BF16: the FP32 operator with tau stored and applied in bf16
+# (unit roundoff u_b = 2^-8 = 3.9e-3).  Only the least-squares and PSPG terms
+# see tau: z = tau L carries an error of at most u_b sum_k |tau_pk L_k| per
+# entry, and relative to the largest entry of J v that is a few u_b at most
+# (the Galerkin terms dilute it).  TOLB = 2 u_b = 7.8e-3, max-norm and L2,
+# relative to the largest entry; measured errors are printed per case.
+TOLB = 2.0 * 2.0 ** -8
+
+
+@pytest.mark.parametrize("name", ["tiny1_K2", "cube3_K1", "cube4_K3", "cube3_K6", "junction_K3",
+                                  "cube2_K7", "cube2_K11", "cube2_K15", "cube2_K31"])
+@pytest.mark.parametrize("variant", ["picard", "picard_nols", "newton"])
+def test_jv_bf16_tau_parity(name, variant):
+    log(f"[gpu] jv bf16-tau parity {name} {variant}")
+    prob = cube_problem(2, K=31) if name == "cube2_K31" else _case(name)
+    s = _solver(prob)
+    y = rand_state(prob, 3, 0.5 if prob.K == 31 else 1.0)
+    v = rand_dir(prob, 4)
+    s.linearize(to_dev(y))
+    out = to_dev(np.zeros_like(y))
+    s.jv(to_dev(v), out, variant, 0.0, precision="bf16")
+    jg = to_host(out)
+    jr = _oracle_jv(prob, y, v, variant, 0.0)
+    emax, el2 = _errs(jg, jr)
+    log(f"[gpu]   K={prob.K} max-rel {emax:.2e} = {emax / 2.0 ** -8:.2f} u_b, l2-rel {el2:.2e}")
+    assert emax <= TOLB and el2 <= TOLB
+    # the FP32 product afterwards still reads the FP32 tau
+    s.jv(to_dev(v), out, variant, 0.0, precision="f32")
+    e32, _ = _errs(to_host(out), jr)
+    assert e32 <= TOL32
+
+
+def test_solve_bf16_tau_cross_evaluated_by_oracle():
+    """The bf16 tangent inside Newton-GMRES: the FP64 residual of every
+    Newton step corrects the 1e-3 error of the products, so the solution
+    reaches the same 1e-8 target, judged by the oracle's residual."""
+    log("[gpu] solve with bf16-tau tangent")
+    from workloads import initial_guess
+    prob = womersley_problem(2, 8, K=2)
+    s = _solver(prob)
+    y0 = initial_guess(prob)
+    y = to_dev(y0)
+    st = s.solve(y, rtol=1e-9, jacobian="picard", max_newton=60, restart=100,
+                 tangent_precision="bf16")
+    assert st["status"] == 0, st
+    yg = to_host(y)
+    par = O.Params.from_problem(prob)
+    r0 = np.linalg.norm(O.residual(par, prob.mesh.xyz, prob.mesh.tets, y0))
+    r = np.linalg.norm(O.residual(par, prob.mesh.xyz, prob.mesh.tets, yg))
+    log(f"[gpu]   newton {st['newton_iters']} matvecs {st['matvecs']} oracle rel {r / r0:.2e}")
+    assert r <= 1e-8 * r0, (r / r0, st)
