@@ -23,6 +23,7 @@
 //              PSPG terms; element buffer rows [node][field][position] in
 //              the slot scaling (the node gather maps positions to slots).
 #include <atomic>
+#include <type_traits>
 
 #include "common.cuh"
 #include "internal.h"
@@ -100,6 +101,29 @@ __device__ __forceinline__ T tau_entry(const DevView& v, const T* tau, int64_t i
   if constexpr ((MODE & MODE_TAU16) != 0) return T(bf16_to_f32(v.tau16[idx]));
   else return tau[idx];
 }
+
+// The packed tau block of the next element is held in registers as loaded
+// (bf16 bits for MODE_TAU16) and converted only when it is staged, so the
+// load's latency stays hidden behind the current element.
+template <int MODE, typename T>
+struct TauReg {
+  typedef T type;
+  static __device__ __forceinline__ T load(const DevView&, const T* tau, int64_t idx) { return tau[idx]; }
+  static __device__ __forceinline__ T value(T x) { return x; }
+};
+template <int MODE>
+struct TauReg<MODE, float> {
+  static constexpr bool B16 = (MODE & MODE_TAU16) != 0;
+  typedef typename std::conditional<B16, uint32_t, float>::type type;
+  static __device__ __forceinline__ type load(const DevView& v, const float* tau, int64_t idx) {
+    if constexpr (B16) return v.tau16[idx];
+    else return tau[idx];
+  }
+  static __device__ __forceinline__ float value(type x) {
+    if constexpr (B16) return __uint_as_float(x << 16);
+    else return x;
+  }
+};
 
 // Frozen fields of the linearization in the kernel's arithmetic type.
 template <typename T>
@@ -223,14 +247,15 @@ k_op(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
 
   // packed tau of the next element is loaded one element ahead (it streams
   // from HBM with no reuse, so its latency is hidden behind the current one)
-  T tv[4][NTL];
+  using TR = TauReg<MODE, T>;
+  typename TR::type tv[4][NTL];
   if (lo + jx < hi) {
     const int64_t e0 = lo + jx;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int j = 0; j < NTL; ++j)
-        tv[q][j] = tok[j] ? tau_entry<MODE, T>(v, TAU, (e0 * 4 + q) * P + lane + 64 * j) : T(0);
+        tv[q][j] = tok[j] ? TR::load(v, TAU, (e0 * 4 + q) * P + lane + 64 * j) : typename TR::type(0);
   }
 
   for (int64_t e = lo + jx; e < hi; e += nbx) {
@@ -318,8 +343,9 @@ k_op(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
 #pragma unroll
       for (int j = 0; j < NTL; ++j)
         if (tok[j]) {
-          sT[q * n * n + (tdst[j] & 0xffff)] = tv[q][j];
-          sT[q * n * n + (tdst[j] >> 16)] = tv[q][j];
+          const T tval = TR::value(tv[q][j]);
+          sT[q * n * n + (tdst[j] & 0xffff)] = tval;
+          sT[q * n * n + (tdst[j] >> 16)] = tval;
         }
 #pragma unroll
     for (int b = 0; b < 4; ++b)
@@ -334,7 +360,7 @@ k_op(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int j = 0; j < NTL; ++j)
-          tv[q][j] = tok[j] ? tau_entry<MODE, T>(v, TAU, (en * 4 + q) * P + lane + 64 * j) : T(0);
+          tv[q][j] = tok[j] ? TR::load(v, TAU, (en * 4 + q) * P + lane + 64 * j) : typename TR::type(0);
     }
     __syncthreads();
 
