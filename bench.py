@@ -764,6 +764,69 @@ def tracer(args):
                                        runs=back)}), flush=True)
 
 
+def tracer_junction(args):
+    """Tracer on the 200k-tet junction (h = 0.081, K = 3, Re = 100, Wo = 10)
+    carried by its converged periodic flow (pseudo-time solve to 1e-8):
+    phi = 1 on the larger inlet, 0 on the smaller one, outlets natural with
+    the backflow term (beta = 0.5), walls natural; GLS against Galerkin
+    (tau = 0) for two diffusivities, unpreconditioned GMRES(100) to 1e-8
+    (at most 20,000 products); products, time and the range of phi over the
+    nodes at 3K+1 instants (within [0, 1] for the exact solution).  Prints
+    one JSON line."""
+    import numpy as np
+    import torch
+    import paper_2311_09465_amd as T
+    from workloads import junction_problem, initial_guess
+    prob = junction_problem(h=0.081, K=3, Re=100.0)
+    K = prob.K
+    ns = T.Solver.from_problem(prob)
+    yv = torch.from_numpy(initial_guess(prob)).cuda()
+    stn = ns.solve(yv, tangent_precision="f32", **JUNCTION_SOLVE)
+    print(f"flow: {stn['status']} {stn['rel_residual']:.2e} {stn['seconds']:.1f}s", file=sys.stderr, flush=True)
+
+    def nodes(t):
+        return np.unique(np.asarray(t).ravel())
+
+    wall = nodes(prob.mesh.faces["wall"])
+    in1 = np.setdiff1d(nodes(prob.mesh.faces["in1"]), wall)
+    in2 = np.setdiff1d(nodes(prob.mesh.faces["in2"]), wall)
+    dn = np.union1d(in1, in2).astype(np.int32)
+    M = 3 * K + 1
+    t = 2 * np.pi * np.arange(M) / M
+    runs = []
+    for kappa in (0.005, 0.001):
+        for stab in (True, False):
+            s = T.Solver(prob.mesh.xyz, prob.mesh.tets, K, prob.rho, prob.mu, prob.omega,
+                         backflow_beta=0.5)
+            s.set_dirichlet(dn)
+            s.set_neumann(prob.neumann_tris)
+            s.set_tracer(yv, kappa, stab)
+            y0 = np.zeros((prob.mesh.n_nodes, 4, 2 * K + 2))
+            y0[in1, 0, 0] = 1.0
+            y = torch.from_numpy(y0).cuda()
+            st = s.solve(y, rtol=1e-8, lin_rtol=1e-8, restart=100, max_newton=1, max_matvec=20000)
+            ph = y.cpu().numpy()[:, 0]
+            c = ph[:, 0::2] + 1j * ph[:, 1::2]
+            c[:, 0] = ph[:, 0]
+            vals = c[:, :1].real + 2 * np.real(sum(c[:, k:k + 1] * np.exp(1j * k * t)[None, :]
+                                                   for k in range(1, K + 1)))
+            runs.append(dict(kappa=kappa, method="GLS" if stab else "Galerkin",
+                             converged=st["status"] == 0, gmres_products=st["matvecs"],
+                             rel_residual=float("%.2e" % st["rel_residual"]),
+                             seconds=round(st["seconds"], 3),
+                             phi_min=float("%.3e" % vals.min()), phi_max=float("%.3e" % vals.max())))
+            print(runs[-1], file=sys.stderr, flush=True)
+            s.close()
+    print(json.dumps({"metric": "tracer on the junction: GLS vs Galerkin, GMRES products to 1e-8 and "
+                                "range of phi",
+                      "n_gpus": 1, "data": "synthetic (converged junction flow, Re 100)",
+                      "config": dict(workload="junction_200k_K3_Re100_tracer", n_tets=prob.mesh.n_tets,
+                                     K=K, restart=100, preconditioner="none", backflow_beta=0.5),
+                      "flow": dict(status=stn["status"], rel_residual=stn["rel_residual"],
+                                   seconds=round(stn["seconds"], 3)),
+                      "runs": runs}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -792,6 +855,8 @@ def main():
                     help="pseudo-time step sweep (junction runs MAX_NEWTON Newton steps)")
     ap.add_argument("--tracer", action="store_true",
                     help="tracer equation: GLS against Galerkin on the pipe flow")
+    ap.add_argument("--tracer-junction", action="store_true",
+                    help="tracer equation: GLS against Galerkin on the 200k junction flow")
     ap.add_argument("--learned", type=int, default=0, metavar="N_TRAIN",
                     help="learned warm-start measurement with N_TRAIN training solves")
     ap.add_argument("--learned-test", type=int, default=32)
@@ -834,6 +899,9 @@ def main():
         return
     if args.tracer:
         tracer(args)
+        return
+    if args.tracer_junction:
+        tracer_junction(args)
         return
     prob, cfg = _workload(args.workload)
     s = T.Solver.from_problem(prob)

@@ -167,17 +167,30 @@ typedef struct {
  * out, returns how many exist. */
 int tsgls_supported_K(int* out, int cap);
 
-/* Create a context for one mesh.  xyz: host [n_nodes][3]; tets: host
- * [n_tets][4] 0-based, positively oriented (TSGLS_EMESH otherwise).  The
- * library orders the elements along a Morton curve, builds the node ->
- * element incidence used to sum element contributions deterministically, and
- * computes the element geometry on the device. */
+/* Create a context for one mesh of linear tetrahedra: the P1 shape
+ * functions N_A and the metric G_ij of the parent element (section
+ * "Convection-diffusion in multiple dimensions", eq. 3D-tau1) are formed
+ * here, once per mesh, with the physical parameters of eq. NS-weak (rho, mu;
+ * omega the base frequency of the time-periodic solution, K its harmonics).
+ * xyz: host [n_nodes][3]; tets: host [n_tets][4] 0-based, positively
+ * oriented (TSGLS_EMESH otherwise).  The library orders the elements along a
+ * Morton curve, builds the node -> element incidence used to sum element
+ * contributions deterministically, and computes the element geometry on the
+ * device.  TSGLS_EINVAL for null pointers, non-positive sizes, rho or mu,
+ * beta outside [0, 1] or a K that is not compiled; TSGLS_ENOMEM, TSGLS_EHIP.
+ * The caller owns xyz and tets (copied); *out must be freed with
+ * tsgls_destroy, also after an error (then it may be NULL). */
 int tsgls_create(const double* xyz, int64_t n_nodes, const int32_t* tets,
                  int64_t n_tets, const tsgls_params* params, void* hip_stream,
                  tsgls_ctx** out);
 
-/* Nodes whose three velocity components are prescribed (host, n entries,
- * each in [0, n_nodes)).  Replaces any earlier set. */
+/* Nodes whose three velocity components are prescribed (the Dirichlet part
+ * Gamma_g of the boundary in eq. NS-weak; the test functions vanish there,
+ * so the momentum rows of these nodes are removed from eq. Rmc, as in the
+ * remarks after eq. K_mat).  nodes: host, n entries, each in [0, n_nodes)
+ * (TSGLS_EINVAL otherwise), copied.  The prescribed values are not passed
+ * here: they are the velocity entries of the state y given to the other
+ * calls.  Replaces any earlier set and clears the linearization. */
 int tsgls_set_dirichlet(tsgls_ctx* ctx, const int32_t* nodes, int64_t n);
 
 /* Neumann (outflow) faces: host tris [nf][3] node ids, ordered so that
