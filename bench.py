@@ -143,8 +143,8 @@ def cpu_baseline(prob, jv_per_step, n_sample=1200, repeats=3):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_op_junction_1M_K6_traffic.txt")
-KERNEL_SOURCES = ["paper_2311_09465_amd/csrc/elemop.hip", "paper_2311_09465_amd/csrc/common.cuh",
-                  "paper_2311_09465_amd/csrc/internal.h"]
+KERNEL_SOURCES = ["paper_2311_09465_amd/csrc/elemop.hip", "paper_2311_09465_amd/csrc/elem.hip",
+                  "paper_2311_09465_amd/csrc/common.cuh", "paper_2311_09465_amd/csrc/internal.h"]
 
 
 def kernel_source_hash() -> str:
@@ -154,6 +154,29 @@ def kernel_source_hash() -> str:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def read_tau_counted():
+    """tau's counted FP64 flops per launch, rate and fraction of the FP64 peak
+    (VALU + MFMA counters over the same dispatches' cycles) from the committed
+    instruction-issue summary, or None when it is missing or was taken for
+    other kernel sources."""
+    try:
+        txt = open(ISSUE_FILE).read()
+        if f"kernel_source_hash = {kernel_source_hash()}" not in txt:
+            return None
+        sec = txt.split("[k_tau]", 1)[1].split("\n[", 1)[0]
+        kv = {}
+        for line in sec.splitlines():
+            if "=" in line:
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.split("(")[0].strip()
+        return dict(flops_per_launch=float(kv["fp64_flops_counted_per_dispatch"]),
+                    tflops=float(kv["fp64_tflops_counted"]),
+                    frac=float(kv["frac_fp64_peak_counted"]),
+                    launch_us=float(kv["kernel_cycles"]) / 2.4e3)
+    except (OSError, IndexError, ValueError, KeyError):
+        return None
 
 
 def read_traffic():
@@ -178,15 +201,20 @@ def read_traffic():
 
 
 def probe(args):
-    """Counter-collection workload: linearize, three FP64 and three FP32
-    tangent products, then a plain device copy of 512 MiB (the reference for
-    scaling the counters)."""
+    """Counter-collection workload at the benchmark's state: the warm-up
+    Newton steps of the benchmark (each linearizes: tau at the states the
+    timed steps see), three FP64 and three FP32 tangent products, then a
+    plain device copy of 512 MiB (the reference for scaling the counters)."""
     import torch
     import paper_2311_09465_amd as T
     from workloads import initial_guess
     prob, _ = _workload(args.workload)
     s = T.Solver.from_problem(prob)
     y = torch.from_numpy(initial_guess(prob)).cuda()
+    m = args.jv_per_step
+    if args.warmup > 0:
+        s.solve(y, max_newton=args.warmup, rtol=1e-300, lin_rtol=1e-300, restart=m, max_matvec=m,
+                jacobian=args.jacobian)
     s.linearize(y)
     v = torch.randn_like(y)
     o = torch.zeros_like(y)
@@ -297,10 +325,14 @@ def summarize_issue(csvs):
     ]
     for i, ctr in enumerate(ISSUE_PASSES):
         lines.append(f"#   rocprofv3 --pmc {ctr} --output-format csv -d rocprof_out/issue{'ABC'[i]} "
-                     f"-o {'abc'[i]} -- python -u bench.py --probe")
+                     f"-o {'abc'[i]} -- python -u bench.py --probe --warmup 5")
     lines.append("#   python bench.py --summarize-issue <issueA csv> <issueB csv> <issueC csv>")
+    lines.append("# The probe runs the benchmark's 5 warm-up Newton steps first (6 tau launches at the")
+    lines.append("# states the timed steps see), then 3 FP64 and 3 FP32 tangent products.")
     lines.append("# Values are per dispatch (averaged over the probe's dispatches of the kernel);")
     lines.append("# 'per element' divides by E for every kernel (the gather runs one wave per node).")
+    lines.append("# FP64 flops counted = 64 x SQ_INSTS_VALU_FLOPS_FP64 (flops per wave instruction) +")
+    lines.append("# 512 x SQ_INSTS_VALU_MFMA_MOPS_F64; the rate divides by the same dispatches' cycles.")
     for pat, label in want:
         names = [k for k in tot if pat in k]
         if not names:
@@ -310,6 +342,9 @@ def summarize_issue(csvs):
         c = {n: v / nd for n, v in tot[k].items()}
         cyc = c["GRBM_GUI_ACTIVE"] / 8.0
         simd = 1024.0
+        # SQ_INSTS_VALU_FLOPS_FP64 counts the flops of each wave instruction
+        # (gfx950 counter definition): x 64 lanes; MFMA MOPS count 512 flops
+        f64c = 64.0 * c["SQ_INSTS_VALU_FLOPS_FP64"] + 512.0 * c["SQ_INSTS_VALU_MFMA_MOPS_F64"]
         lines += [
             "",
             f"[{label}]  ({nd} dispatches)",
@@ -329,6 +364,9 @@ def summarize_issue(csvs):
             f"wave_frac_waiting_on_counters = {c['SQ_WAIT_ANY'] / c['SQ_WAVE_CYCLES']:.3f}",
             f"wave_frac_waiting_to_issue = {c['SQ_WAIT_INST_ANY'] / c['SQ_WAVE_CYCLES']:.3f}",
             f"wave_frac_waiting_lds_issue = {c['SQ_WAIT_INST_LDS'] / c['SQ_WAVE_CYCLES']:.3f}",
+            f"fp64_flops_counted_per_dispatch = {f64c:.6g}",
+            f"fp64_tflops_counted = {f64c / (cyc / 2.4e9) / 1e12:.4g}",
+            f"frac_fp64_peak_counted = {f64c / (cyc / 2.4e9) / 1e12 / FP64_PEAK_TFLOPS:.4f}",
         ]
     lines.append("")
     lines.append(f"kernel_source_hash = {kernel_source_hash()}")
@@ -827,6 +865,21 @@ def tracer_junction(args):
                       "runs": runs}), flush=True)
 
 
+def tau_entry(prof, K, E, args):
+    """tau's launch time over the timed steps and its FP64 rate by the
+    60 n^3 per point model; beside it the counted rate (VALU + MFMA flops
+    over the same dispatches' cycles, from the committed counter summary of
+    the probe at the warm-up states) when that summary matches the sources."""
+    ms = prof["tau"][1] / max(prof["tau"][0], 1)
+    model = 60.0 * (2 * K + 1) ** 3 * 4 * E
+    out = dict(ms_per_launch=round(ms, 3), tflops_model=round(model / (ms / 1e3) / 1e12, 3),
+               frac_fp64_peak_model=round(model / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS, 4))
+    cf = read_tau_counted() if (args.workload == "junction_1M_K6" and args.jacobian == "picard") else None
+    out["counted"] = None if cf is None else dict(
+        cf, source="profiles/k_op_junction_1M_K6_issue.txt (probe at the warm-up states)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -871,7 +924,7 @@ def main():
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc,
                       "rocprofv3 --pmc {counter} --output-format csv -d rocprof_out/{d} -o p -- "
-                      "python bench.py --probe")
+                      "python -u bench.py --probe --warmup 5")
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the library runs on one GPU; multi-GPU runs are not implemented "
@@ -957,12 +1010,7 @@ def main():
         "breakdown_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in prof.items()},
         # tau: one launch per Newton step over 4 E points; model ~60 n^3 FP64 flops per point
         # (S, the Jacobi sweeps and Q^T Q), against the FP64 peak
-        "tau": dict(ms_per_launch=round(prof["tau"][1] / max(prof["tau"][0], 1), 3),
-                    tflops_model=round(60.0 * (2 * K + 1) ** 3 * 4 * E
-                                       / (prof["tau"][1] / max(prof["tau"][0], 1) / 1e3) / 1e12, 3),
-                    frac_fp64_peak=round(60.0 * (2 * K + 1) ** 3 * 4 * E
-                                         / (prof["tau"][1] / max(prof["tau"][0], 1) / 1e3) / 1e12
-                                         / FP64_PEAK_TFLOPS, 4)),
+        "tau": tau_entry(prof, K, E, args),
         "newton_rel_residual_after": st["rel_residual"],
     }
     if not args.no_extras:
