@@ -805,8 +805,9 @@ def tracer(args):
 def tracer_junction(args):
     """Tracer on the 200k-tet junction (h = 0.081, K = 3, Re = 100, Wo = 10)
     carried by its converged periodic flow (pseudo-time solve to 1e-8):
-    phi = 1 on the larger inlet, 0 on the smaller one, outlets natural with
-    the backflow term (beta = 0.5), walls natural; GLS against Galerkin
+    phi = 1 on the larger inlet, 0 on the smaller one, walls natural, the
+    outlets either zero Dirichlet (the paper's case: a rapid jump) or natural
+    with the backflow term (beta = 0.5); GLS against Galerkin
     (tau = 0) for two diffusivities, unpreconditioned GMRES(100) to 1e-8
     (at most 20,000 products); products, time and the range of phi over the
     nodes at 3K+1 instants (within [0, 1] for the exact solution).  Prints
@@ -828,16 +829,21 @@ def tracer_junction(args):
     wall = nodes(prob.mesh.faces["wall"])
     in1 = np.setdiff1d(nodes(prob.mesh.faces["in1"]), wall)
     in2 = np.setdiff1d(nodes(prob.mesh.faces["in2"]), wall)
-    dn = np.union1d(in1, in2).astype(np.int32)
+    outl = np.setdiff1d(nodes(prob.neumann_tris), wall)
     M = 3 * K + 1
     t = 2 * np.pi * np.arange(M) / M
     runs = []
-    for kappa in (0.005, 0.001):
+    # outlets: zero Dirichlet (the paper's test of a rapid jump) or natural with the backflow term
+    for outlets in ("dirichlet", "natural"):
+      for kappa in (0.005, 0.001):
         for stab in (True, False):
             s = T.Solver(prob.mesh.xyz, prob.mesh.tets, K, prob.rho, prob.mu, prob.omega,
                          backflow_beta=0.5)
-            s.set_dirichlet(dn)
-            s.set_neumann(prob.neumann_tris)
+            if outlets == "dirichlet":
+                s.set_dirichlet(np.union1d(np.union1d(in1, in2), outl).astype(np.int32))
+            else:
+                s.set_dirichlet(np.union1d(in1, in2).astype(np.int32))
+                s.set_neumann(prob.neumann_tris)
             s.set_tracer(yv, kappa, stab)
             y0 = np.zeros((prob.mesh.n_nodes, 4, 2 * K + 2))
             y0[in1, 0, 0] = 1.0
@@ -848,7 +854,7 @@ def tracer_junction(args):
             c[:, 0] = ph[:, 0]
             vals = c[:, :1].real + 2 * np.real(sum(c[:, k:k + 1] * np.exp(1j * k * t)[None, :]
                                                    for k in range(1, K + 1)))
-            runs.append(dict(kappa=kappa, method="GLS" if stab else "Galerkin",
+            runs.append(dict(outlets=outlets, kappa=kappa, method="GLS" if stab else "Galerkin",
                              converged=st["status"] == 0, gmres_products=st["matvecs"],
                              rel_residual=float("%.2e" % st["rel_residual"]),
                              seconds=round(st["seconds"], 3),
