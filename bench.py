@@ -570,6 +570,9 @@ def learned_run(ntr, nte, r, hidden=4, steps=3000, precision="bf16"):
 
 JUNCTION_SOLVE = dict(rtol=1e-8, lin_rtol=0.1, restart=100, max_newton=150, max_matvec=10000,
                       jacobian="newton", dt_pseudo=0.1, dt_schedule="ser", dt_max=2.0)
+# K = 6: unbounded step, 3,000 products per linear solve (a short solve halves
+# the next step)
+JUNCTION_SOLVE_K6 = dict(JUNCTION_SOLVE, max_newton=250, max_matvec=3000, dt_max=0.0)
 
 
 def junction_time_to_1e8():
@@ -577,7 +580,9 @@ def junction_time_to_1e8():
     Wo = 10) from the initial guess: pseudo-time stepping with one Newton
     iteration per step (Newton tangent, tau frozen), switched-evolution step
     size from 0.1 bounded by 2, GMRES(100) to 0.1; FP64 tangent, FP32
-    tangent and FP32 tangent with tau in bf16 (FP64 residual and Krylov)."""
+    tangent and FP32 tangent with tau in bf16 (FP64 residual and Krylov).
+    Then K = 6 with the FP32 tangent, the step unbounded and 3,000 products
+    per linear solve."""
     import torch
     import paper_2311_09465_amd as T
     from workloads import junction_problem, initial_guess
@@ -595,6 +600,21 @@ def junction_time_to_1e8():
         print(f"junction 200k time to 1e-8 ({prec}): {out[prec]}", file=sys.stderr, flush=True)
     out["f32_speedup"] = round(out["f64"]["seconds"] / out["f32"]["seconds"], 3)
     out["bf16_speedup"] = round(out["f64"]["seconds"] / out["bf16"]["seconds"], 3)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    prob = junction_problem(h=0.081, K=6, Re=100.0)
+    s = T.Solver.from_problem(prob)
+    y = torch.from_numpy(initial_guess(prob)).cuda()
+    torch.cuda.synchronize()
+    st = s.solve(y, tangent_precision="f32", **JUNCTION_SOLVE_K6)
+    out["K6_f32"] = dict(workload="junction_200k_K6_Re100", solver=dict(JUNCTION_SOLVE_K6),
+                         seconds=round(st["seconds"], 3),
+                         status="converged" if st["status"] == 0 else "not converged",
+                         newton_iters=st["newton_iters"], matvecs=st["matvecs"],
+                         rel_residual=float("%.3e" % st["rel_residual"]), rejected=st["rejected"],
+                         short_linear_solves=st["lin_unconverged"])
+    print(f"junction 200k K=6 time to 1e-8 (f32): {out['K6_f32']}", file=sys.stderr, flush=True)
     s.close()
     return out
 

@@ -100,9 +100,11 @@ extern "C" {
  *   TSGLS_DT_FIXED  every step uses dt_pseudo (<= 0: no shift, plain Newton).
  *   TSGLS_DT_SER    the first step uses dt_pseudo > 0; after each step the
  *                   size is multiplied by ||r_old|| / ||r_new|| clipped to
- *                   [0.1, 10] (switched evolution relaxation), and bounded
- *                   by dt_max if dt_max > 0 (else it grows without bound and
- *                   the shift is dropped once dt exceeds 1e12).
+ *                   [0.1, 10] (switched evolution relaxation), or halved if
+ *                   that step's GMRES used max_matvec products without
+ *                   reaching lin_rtol, and bounded by dt_max if dt_max > 0
+ *                   (else it grows without bound and the shift is dropped
+ *                   once dt exceeds 1e12).
  *   TSGLS_DT_AUTO   plain Newton steps while the residual falls; after three
  *                   consecutive steps whose residual ratio exceeds 0.99 (a
  *                   stall) or one rejected step, continues as TSGLS_DT_SER
@@ -161,6 +163,7 @@ typedef struct {
   int rejected;           /* pseudo-time steps rejected (SER / AUTO) */
   int switched_at;        /* AUTO: Newton iteration at which pseudo-time began, -1 if never */
   double dt_last;         /* pseudo-time step of the last iteration (0: no shift) */
+  int lin_unconverged;    /* Newton steps whose GMRES stopped at max_matvec short of lin_rtol */
 } tsgls_solve_stats;
 
 /* Harmonic counts compiled into this library: writes up to cap values into
@@ -226,7 +229,12 @@ int tsgls_set_tracer(tsgls_ctx* ctx, const double* y_velocity, double kappa,
 int tsgls_residual(tsgls_ctx* ctx, const double* y, double* r);
 
 /* Freeze A_i, tau (and, for the Newton tangent, tau L_i(u)) at y.  If r is
- * not NULL the residual at y is written there as a by-product. */
+ * not NULL the residual at y is written there as a by-product.  For
+ * K <= 15 the eigen-iteration that gives tau starts from the eigenvectors
+ * kept from this context's previous linearization (4 E n^2 doubles of device
+ * memory, allocated on first use; without them it starts cold), so tau and
+ * what follows from it depend on that history at the level of rounding.
+ * tsgls_solve starts its first linearization cold. */
 int tsgls_linearize(tsgls_ctx* ctx, const double* y, double* r);
 
 /* Jv = J v with the last linearization; variant TSGLS_JAC_*; dt_pseudo > 0

@@ -40,7 +40,7 @@ class SolveStats(C.Structure):
     _fields_ = [("newton_iters", C.c_int), ("matvecs", C.c_int), ("status", C.c_int),
                 ("rel_residual", C.c_double), ("r0_norm", C.c_double), ("seconds", C.c_double),
                 ("history", C.c_double * 64), ("rejected", C.c_int), ("switched_at", C.c_int),
-                ("dt_last", C.c_double)]
+                ("dt_last", C.c_double), ("lin_unconverged", C.c_int)]
 
 
 class TsglsError(RuntimeError):
@@ -124,7 +124,7 @@ def _stats_dict(rc, st):
     return dict(status=rc, newton_iters=st.newton_iters, matvecs=st.matvecs,
                 rel_residual=st.rel_residual, r0_norm=st.r0_norm, seconds=st.seconds,
                 history=list(st.history[:min(64, st.newton_iters)]), rejected=st.rejected,
-                switched_at=st.switched_at, dt_last=st.dt_last)
+                switched_at=st.switched_at, dt_last=st.dt_last, lin_unconverged=st.lin_unconverged)
 
 
 def solve_batch(solvers, ys, rtol=1e-8, lin_rtol=0.05, restart=100, max_newton=50,

@@ -518,15 +518,17 @@ int ensure_krylov(tsgls_ctx* c, int m) {
 //   update pass: q_j into slot j, u_{j+1} = (w - Q b - q_j h_jj)/sigma.
 // The last column is finalized with one extra reduction (no product).
 int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv, int jac,
-                  double dt, int prec, int* mv_out) {
+                  double dt, int prec, int* mv_out, bool* conv) {
   const int64_t n = ndof(c);
   const int nb = multidot_blocks(n);
+  *conv = false;
   HIPCHK(c, launch_zero(x, n, c->st));
   double bnorm;
   CHK(norm2(c, b, &bnorm));
   if (!std::isfinite(bnorm)) return fail(c, TSGLS_ENONFINITE, "non-finite right-hand side");
   int mv = 0;
   if (bnorm == 0.0) {
+    *conv = true;
     *mv_out = 0;
     return TSGLS_OK;
   }
@@ -577,7 +579,10 @@ int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, i
     double beta;
     CHK(norm2(c, V0, &beta));
     if (!std::isfinite(beta)) return fail(c, TSGLS_ENONFINITE, "non-finite GMRES residual");
-    if (beta <= tol * bnorm) break;
+    if (beta <= tol * bnorm) {
+      *conv = true;
+      break;
+    }
     HIPCHK(c, launch_scal_copy(1.0 / beta, V0, V0, n, c->st));
     std::fill(Hh.begin(), Hh.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
@@ -678,7 +683,10 @@ int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, i
     HIPCHK(c, launch_mul(c->minv, c->kt, c->kt2, n, c->st));
     HIPCHK(c, launch_axpy(1.0, c->kt2, x, n, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
-    if (done) break;
+    if (done) {
+      *conv = true;
+      break;
+    }
   }
   *mv_out = mv;
   return TSGLS_OK;
@@ -693,9 +701,10 @@ int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, i
 // convergence flag.  Cycles always run m steps: after convergence the
 // remaining steps see zero update coefficients and leave zero vectors.
 int gmres_graph(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv, int jac,
-                double dt, int prec, int* mv_out) {
+                double dt, int prec, int* mv_out, bool* conv) {
   const int64_t n = ndof(c);
   const int nb = multidot_blocks(n);
+  *conv = false;
   if (m > 32) return fail(c, TSGLS_EINVAL, "graph GMRES needs restart <= 32");
   if (!c->gmbuf) {
     CHK(dalloc(c, &c->gmbuf, 2400 + 16));
@@ -784,6 +793,7 @@ int gmres_graph(tsgls_ctx* c, const double* b, double* x, double tol, int m, int
   CHK(norm2(c, b, &bnorm));
   if (!std::isfinite(bnorm)) return fail(c, TSGLS_ENONFINITE, "non-finite right-hand side");
   if (bnorm == 0.0) {
+    *conv = true;
     *mv_out = 0;
     return TSGLS_OK;
   }
@@ -816,7 +826,10 @@ int gmres_graph(tsgls_ctx* c, const double* b, double* x, double tol, int m, int
     std::memcpy(stv, c->hp + 3584, sizeof(stv));
     est = c->hp[3586];
     if (!std::isfinite(est)) return fail(c, TSGLS_ENONFINITE, "non-finite Krylov quantity");
-    if (stv[3]) break;
+    if (stv[3]) {
+      *conv = true;
+      break;
+    }
   }
   *mv_out = mv;
   return TSGLS_OK;
@@ -825,14 +838,16 @@ int gmres_graph(tsgls_ctx* c, const double* b, double* x, double tol, int m, int
 // Right-Jacobi-preconditioned restarted GMRES with classical Gram-Schmidt and
 // one reorthogonalization pass; x = J^{-1} b approximately, x zeroed first.
 int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv, int jac,
-          double dt, int prec, int* mv_out) {
+          double dt, int prec, int* mv_out, bool* conv) {
   const int64_t n = ndof(c);
+  *conv = false;
   HIPCHK(c, launch_zero(x, n, c->st));
   double bnorm;
   CHK(norm2(c, b, &bnorm));
   if (!std::isfinite(bnorm)) return fail(c, TSGLS_ENONFINITE, "non-finite right-hand side");
   int mv = 0;
   if (bnorm == 0.0) {
+    *conv = true;
     *mv_out = 0;
     return TSGLS_OK;
   }
@@ -852,7 +867,10 @@ int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv
     double beta;
     CHK(norm2(c, V0, &beta));
     if (!std::isfinite(beta)) return fail(c, TSGLS_ENONFINITE, "non-finite GMRES residual");
-    if (beta <= tol * bnorm) break;
+    if (beta <= tol * bnorm) {
+      *conv = true;
+      break;
+    }
     HIPCHK(c, launch_scal_copy(1.0 / beta, V0, V0, n, c->st));
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
@@ -937,7 +955,10 @@ int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv
     HIPCHK(c, launch_mul(c->minv, c->kt, c->kt2, n, c->st));
     HIPCHK(c, launch_axpy(1.0, c->kt2, x, n, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
-    if (done) break;
+    if (done) {
+      *conv = true;
+      break;
+    }
   }
   *mv_out = mv;
   return TSGLS_OK;
@@ -1276,6 +1297,9 @@ int tsgls_solve(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_
   CHK(ensure_krylov(c, o->restart));
   const int64_t n = ndof(c);
   double* r = c->rs;
+  // the first tau of a solve starts cold, so that the result depends on the
+  // arguments only and not on what the context linearized before
+  c->tauV_ok = false;
   CHK(linearize_impl(c, y, r));
   double r0;
   CHK(norm2(c, r, &r0));
@@ -1304,16 +1328,18 @@ int tsgls_solve(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_
     // b = -r in place (r is recomputed after the update)
     HIPCHK(c, launch_scal_copy(-1.0, r, r, n, c->st));
     int mv = 0;
+    bool lin_ok = false;
     if (o->restart <= 32 && o->gmres_graph)
       CHK(gmres_graph(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, dt,
-                      o->tangent_precision, &mv));
+                      o->tangent_precision, &mv, &lin_ok));
     else if (o->restart <= GS_DELAYED_MAX)
       CHK(gmres_delayed(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, dt,
-                        o->tangent_precision, &mv));
+                        o->tangent_precision, &mv, &lin_ok));
     else
       CHK(gmres(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, dt,
-                o->tangent_precision, &mv));
+                o->tangent_precision, &mv, &lin_ok));
     st.matvecs += mv;
+    if (!lin_ok) ++st.lin_unconverged;
     if (adaptive) HIPCHK(c, launch_copy(y, c->ybak, n, c->st));
     HIPCHK(c, launch_axpy(1.0, c->kx, y, n, c->st));
     CHK(linearize_impl(c, y, r));
@@ -1340,11 +1366,18 @@ int tsgls_solve(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_
     }
     if (!std::isfinite(rnew)) return fail(c, TSGLS_ENONFINITE, "non-finite residual at Newton step %d", it);
     if (o->verbose)
-      fprintf(stderr, "tsgls newton %d: |r|/|r0| = %.3e  gmres %d  dt %.3g\n", it, rnew / r0, mv, dt);
+      fprintf(stderr, "tsgls newton %d: |r|/|r0| = %.3e  gmres %d%s  dt %.3g\n", it, rnew / r0, mv,
+              lin_ok ? "" : " (short of lin_rtol)", dt);
     if (ser) {
-      // switched evolution relaxation: dt grows as the residual falls
+      // switched evolution relaxation: dt grows as the residual falls; a
+      // linear solve that ran out of products before reaching lin_rtol
+      // halves it instead (the shifted system was too hard for the Krylov
+      // budget, and a larger step would only be harder)
       if (dt > 0) {
-        dt *= std::min(10.0, std::max(0.1, rn / rnew));
+        if (lin_ok)
+          dt *= std::min(10.0, std::max(0.1, rn / rnew));
+        else
+          dt *= 0.5;
         if (o->dt_max > 0) dt = std::min(dt, o->dt_max);
         else if (dt > 1e12) dt = 0.0;
       }
