@@ -449,7 +449,72 @@ def batched_run(N, concurrency=8, graph=False):
         "throughput_gain": round(seq_wall / bat_wall, 3),
     }
     del solvers
+    torch.cuda.empty_cache()
+    out["lockstep"] = lockstep_run(probs, Ks, opts)
+    out["lockstep"]["throughput_gain_vs_sequential"] = round(
+        out["lockstep"]["solves_per_s"] / out["sequential"]["solves_per_s"], 3)
     return out
+
+
+def lockstep_run(probs, Ks, opts):
+    """The same problems solved as segments: one context per harmonic count
+    holding all of that count's waveforms (tsgls_solve_segments, graph-
+    captured cycles of `restart` steps, restart <= 32), the four groups run
+    concurrently from four host threads, each on its own stream.  Latency of
+    a solve = time from the common start until its segment finished."""
+    import threading
+    import numpy as np
+    import torch
+    import paper_2311_09465_amd as T
+    from workloads import initial_guess
+    groups = {}
+    for i, K in enumerate(Ks):
+        groups.setdefault(int(K), []).append(i)
+    so = dict(rtol=opts["rtol"], lin_rtol=opts["lin_rtol"], restart=opts["restart"],
+              max_newton=opts["max_newton"])
+    segs, ys = {}, {}
+    for K, idx in groups.items():
+        segs[K] = T.SegmentSolver.from_problems([probs[i] for i in idx], stream=torch.cuda.Stream())
+        ys[K] = torch.from_numpy(np.concatenate([initial_guess(probs[i]) for i in idx])).cuda()
+    # first use of each kernel family and of the graph capture, outside the timing
+    for K in groups:
+        y = ys[K].clone()
+        torch.cuda.synchronize()
+        segs[K].solve_segments(y, **dict(so, max_newton=1))
+    torch.cuda.synchronize()
+    res, errs = {}, []
+
+    def run(K):
+        try:
+            res[K] = segs[K].solve_segments(ys[K], **so)
+        except Exception as e:  # reported below
+            errs.append(repr(e))
+
+    t0 = time.perf_counter()
+    th = [threading.Thread(target=run, args=(K,)) for K in groups]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if errs:
+        raise RuntimeError("; ".join(errs))
+    lat, conv, iters, group_wall = [], 0, [], {}
+    for K, idx in groups.items():
+        rc, stats, fin = res[K]
+        lat += fin
+        conv += sum(s_["status"] == 0 for s_ in stats)
+        iters += [s_["newton_iters"] for s_ in stats]
+        group_wall[K] = round(max(fin), 3)
+    for s_ in segs.values():
+        s_.close()
+    N = len(probs)
+    return dict(wall_s=round(wall, 3), solves_per_s=round(N / wall, 3),
+                latency_p50_s=round(float(np.percentile(lat, 50)), 4),
+                latency_p99_s=round(float(np.percentile(lat, 99)), 4),
+                converged=int(conv), newton_iters_mean=round(float(np.mean(iters)), 2),
+                group_wall_s=group_wall, restart=so["restart"], graph_cycles=True)
 
 
 def learned(args):

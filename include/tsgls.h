@@ -264,9 +264,44 @@ int tsgls_jacobi_diag(tsgls_ctx* ctx, double* d, double dt_pseudo);
 int tsgls_get_tau(tsgls_ctx* ctx, double* tau_out);
 
 /* Newton-GMRES from y (device, in: initial guess, out: solution).  stats is
- * a host pointer (may be NULL). */
+ * a host pointer (may be NULL).  TSGLS_EINVAL on a context with segments. */
 int tsgls_solve(tsgls_ctx* ctx, double* y, const tsgls_solve_opts* opts,
                 tsgls_solve_stats* stats);
+
+/* Segments: one context holding nseg independent problems of the same
+ * harmonic count and physical parameters, for solves in lockstep (many
+ * inflow waveforms on one mesh; an extension for throughput, the paper
+ * solves one problem at a time).  The context's
+ * nodes are nseg equal contiguous blocks (n_nodes / nseg each; problem s
+ * owns nodes [s n_nodes/nseg, (s+1) n_nodes/nseg) and so the same block of
+ * every state vector); no element or Neumann face may join two blocks.
+ * Typically the caller repeats one mesh nseg times with the node numbers
+ * offset, and gives each copy its own Dirichlet values.  TSGLS_EINVAL if
+ * nseg < 1, nseg does not divide n_nodes, an element joins two blocks, or
+ * the context is in tracer mode.  nseg = 1 undoes it.  Residual, tangent,
+ * linearize and the Jacobi diagonal act on all segments at once as on any
+ * context (they are local to elements and nodes). */
+int tsgls_set_segments(tsgls_ctx* ctx, int nseg);
+
+/* Newton-GMRES on every segment at once, in lockstep: each Newton step
+ * linearizes all of them in one pass, and each GMRES cycle is one captured
+ * HIP graph (as with gmres_graph) whose launches cover all segments -- one
+ * tangent product of the whole context per Arnoldi step, and reductions,
+ * Gram-Schmidt updates and the least-squares (Givens) update per segment in
+ * single launches on the device; the host reads one status word per segment
+ * per cycle.  Each segment's reductions use the blocking a lone problem of
+ * its size would use, so segment s follows, bit for bit, the iteration of
+ * tsgls_solve with gmres_graph = 1 on a context holding problem s alone.  A
+ * segment that has converged (or reached max_newton / max_matvec) sits out
+ * the rest with zero updates; its state is no longer changed.  Options as
+ * tsgls_solve with restart <= 32 and the fixed schedule (TSGLS_EINVAL
+ * otherwise); gmres_graph is implied.  stats: host [nseg] (per segment;
+ * seconds = time from the call's start until that segment finished);
+ * finish_s: host [nseg] or NULL, the same times.  Returns TSGLS_OK if every
+ * segment reached rtol, else TSGLS_NOT_CONVERGED, or a negative error
+ * (ENONFINITE names the segment in tsgls_last_error). */
+int tsgls_solve_segments(tsgls_ctx* ctx, double* y, const tsgls_solve_opts* opts,
+                         tsgls_solve_stats* stats, double* finish_s);
 
 /* Batched solves: nb independent problems, ctxs[i] (distinct contexts, each
  * with its own stream for the solves to overlap on the device; any harmonic

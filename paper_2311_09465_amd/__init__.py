@@ -72,6 +72,8 @@ def lib():
         L.tsgls_get_tau.argtypes = [P, P]
         L.tsgls_solve.argtypes = [P, P, C.POINTER(SolveOpts), C.POINTER(SolveStats)]
         L.tsgls_solve_batch.argtypes = [P, P, I32, C.POINTER(SolveOpts), P, P, I32]
+        L.tsgls_set_segments.argtypes = [P, I32]
+        L.tsgls_solve_segments.argtypes = [P, P, C.POINTER(SolveOpts), P, P]
         L.tsgls_info.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]
         L.tsgls_profile.argtypes = [P, I32]
         L.tsgls_profile_get.argtypes = [P, I32, C.POINTER(I64), C.POINTER(D)]
@@ -250,6 +252,27 @@ class Solver:
         rc = self._check(lib().tsgls_solve(self._h, self._vec(y, "y"), C.byref(o), C.byref(st)), "solve")
         return _stats_dict(rc, st)
 
+    def set_segments(self, nseg):
+        """tsgls_set_segments: the context holds nseg independent problems,
+        node blocks of n_nodes / nseg."""
+        self._check(lib().tsgls_set_segments(self._h, int(nseg)), "set_segments")
+        self.nseg = int(nseg)
+
+    def solve_segments(self, y, rtol=1e-8, lin_rtol=0.05, restart=30, max_newton=50, max_matvec=10000,
+                       jacobian="picard", dt_pseudo=0.0, verbose=False, tangent_precision="f64"):
+        """tsgls_solve_segments: lockstep Newton-GMRES on every segment.
+        Returns (status, per-segment stats dicts, per-segment finish times)."""
+        nseg = getattr(self, "nseg", 1)
+        o = _opts(rtol, lin_rtol, restart, max_newton, max_matvec, jacobian, dt_pseudo, verbose,
+                  tangent_precision, True, "fixed", 0.0)
+        st = (SolveStats * nseg)()
+        fin = (C.c_double * nseg)()
+        rc = self._check(lib().tsgls_solve_segments(self._h, self._vec(y, "y"), C.byref(o),
+                                                    C.cast(st, C.c_void_p), C.cast(fin, C.c_void_p)),
+                         "solve_segments")
+        return rc, [_stats_dict(0 if st[i].status == 0 else 1, st[i]) for i in range(nseg)], \
+            [fin[i] for i in range(nseg)]
+
     PROF = {"elem_tangent": 0, "elem_residual": 1, "tau": 2, "diag": 3, "face": 4, "ortho": 5,
             "gather": 6}
 
@@ -277,6 +300,41 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class SegmentSolver(Solver):
+    """Problems that share a mesh, a harmonic count and the physical
+    parameters and differ in their Dirichlet data (e.g. inflow waveforms),
+    held as the segments of one context: the mesh repeated once per problem
+    with node numbers offset by s n_nodes.  State tensors have shape
+    (nseg * n_nodes, 4, 2K+2); problem s is rows [s n_nodes, (s+1) n_nodes)."""
+
+    @classmethod
+    def from_problems(cls, probs, stream=None):
+        p0 = probs[0]
+        nn = p0.mesh.n_nodes
+        for p in probs[1:]:
+            same = (p.K == p0.K and p.rho == p0.rho and p.mu == p0.mu and p.omega == p0.omega
+                    and p.C_I == p0.C_I and p.backflow_beta == p0.backflow_beta
+                    and np.array_equal(p.mesh.xyz, p0.mesh.xyz) and np.array_equal(p.mesh.tets, p0.mesh.tets)
+                    and np.array_equal(p.dirichlet_nodes, p0.dirichlet_nodes)
+                    and np.array_equal(p.neumann_tris, p0.neumann_tris)
+                    and p.neumann_h is None and p0.neumann_h is None)
+            if not same:
+                raise TsglsError("segments need one mesh, K, parameters, Dirichlet node set and "
+                                 "Neumann faces (without traction)")
+        B = len(probs)
+        tets = np.asarray(p0.mesh.tets, dtype=np.int64)
+        xyz = np.tile(np.asarray(p0.mesh.xyz, dtype=np.float64), (B, 1))
+        utets = np.concatenate([tets + s * nn for s in range(B)])
+        s = cls(xyz, utets, p0.K, p0.rho, p0.mu, p0.omega, p0.C_I, p0.backflow_beta, stream=stream)
+        dn = np.asarray(p0.dirichlet_nodes, dtype=np.int64)
+        s.set_dirichlet(np.concatenate([dn + k * nn for k in range(B)]))
+        nt = np.asarray(p0.neumann_tris, dtype=np.int64).reshape(-1, 3)
+        s.set_neumann(np.concatenate([nt + k * nn for k in range(B)]))
+        s.set_segments(B)
+        s.seg_nodes = nn
+        return s
 
 
 # ---------------------------------------------------------------- warm start

@@ -178,9 +178,11 @@ __device__ __forceinline__ double rsq_nr(double x) {
 // rotated to be orthogonal.  Both lanes of a pair evaluate the same rotation
 // bit for bit (same operands in the same order).  nrm is this lane's |w|^2,
 // kept up to date; big is set when (w_c . w_d)^2 > 1e-14 |w_c|^2 |w_d|^2.
+// A lane whose group is done (both lanes of a pair belong to one group)
+// rotates nothing.
 template <int n, int k>
 __device__ __forceinline__ void jacobi_round(double (&w)[n], double& nrm, int c, int& big,
-                                             int& rot) {
+                                             int& rot, int done) {
   double o[n];
 #pragma unroll
   for (int a = 0; a < n; ++a) o[a] = xor_lane<k>(w[a]);
@@ -193,8 +195,8 @@ __device__ __forceinline__ void jacobi_round(double (&w)[n], double& nrm, int c,
   const double al = low ? nrm : onrm, be = low ? onrm : nrm;
   const double ab = al * be;
   const double g2 = ga * ga;
-  if (g2 > 1e-14 * ab) big = 1;
-  if (g2 > 1e-30 * ab) {
+  if (!done && g2 > 1e-14 * ab) big = 1;
+  if (!done && g2 > 1e-30 * ab) {
     // tan(theta) = 2 g sgn(d) / (|d| + sqrt(d^2 + 4 g^2)), d = be - al
     const double d = be - al;
     const double r2 = fma(d, d, 4.0 * g2);
@@ -214,11 +216,19 @@ __device__ __forceinline__ void jacobi_round(double (&w)[n], double& nrm, int c,
 
 template <int n, int k, int NP>
 __device__ __forceinline__ void jacobi_rounds(double (&w)[n], double& nrm, int c, int& big,
-                                              int& rot) {
+                                              int& rot, int done) {
   if constexpr (k < NP) {
-    jacobi_round<n, k>(w, nrm, c, big, rot);
-    jacobi_rounds<n, k + 1, NP>(w, nrm, c, big, rot);
+    jacobi_round<n, k>(w, nrm, c, big, rot, done);
+    jacobi_rounds<n, k + 1, NP>(w, nrm, c, big, rot, done);
   }
+}
+
+// OR of an int over the NP lanes of this lane's group.
+template <int NP>
+__device__ __forceinline__ int group_or(int x) {
+#pragma unroll
+  for (int k = 1; k < NP; k <<= 1) x |= __shfl_xor(x, k);
+  return x;
 }
 
 // One-sided (Hestenes) cyclic Jacobi on the columns held by a group of NP
@@ -226,17 +236,21 @@ __device__ __forceinline__ void jacobi_rounds(double (&w)[n], double& nrm, int c
 // round are (c, c xor k), k = 1..NP-1, which covers every pair once per
 // sweep.  Sweeps stop after the first one whose largest rotation was below
 // 1e-7 in relative terms (convergence is quadratic: the columns are then
-// orthogonal to about 1e-14 relative), or that rotated nothing.  The whole wave
-// sweeps until all its groups are done.
+// orthogonal to about 1e-14 relative), or that rotated nothing.  Each group
+// stops on its own: the wave sweeps until all its groups are done, and a
+// group that is done rotates nothing more, so a group's result does not
+// depend on which other groups share its wave.
 template <int n, int NP>
 __device__ __forceinline__ void jacobi_columns(double (&w)[n], int c) {
+  int done = 0;
   for (int sweep = 0; sweep < 40; ++sweep) {
     double nrm = 0.0;
 #pragma unroll
     for (int a = 0; a < n; ++a) nrm = fma(w[a], w[a], nrm);
     int big = 0, rot = 0;
-    jacobi_rounds<n, 1, NP>(w, nrm, c, big, rot);
-    if (!__any(rot) || !__any(big)) break;
+    jacobi_rounds<n, 1, NP>(w, nrm, c, big, rot, done);
+    if (!group_or<NP>(big) || !group_or<NP>(rot)) done = 1;
+    if (__all(done)) break;
   }
 }
 

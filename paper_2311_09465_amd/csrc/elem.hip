@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(256)
 k_prep_time(const double* __restrict__ Y, const double* __restrict__ Ys,
             const uint8_t* __restrict__ nflag, int masked, const double* __restrict__ F,
             TO* __restrict__ XT, TO* __restrict__ XP, int64_t nn, int64_t nbp, DevView fv,
-            const double* __restrict__ aneg, int fresid) {
+            const double* __restrict__ aneg, int fresid, SegMask mk) {
   constexpr int n = Dim<K>::n, S = Dim<K>::S, M = Dim<K>::M, PW = (n + 15) / 16 * 16;
   constexpr int NPT = PW / 16, NR = (3 * M + 63) / 64;
   constexpr bool HOIST = NR == 1;          // the lane's column of F stays in registers
@@ -102,7 +102,7 @@ k_prep_time(const double* __restrict__ Y, const double* __restrict__ Ys,
   // the trip count is the same for the four waves of a block (barriers below)
   for (int64_t base = (int64_t)blockIdx.x * 4; base < nn; base += stride) {
     const int64_t node = base + wv;
-    const bool act = node < nn;
+    const bool act = node < nn && !(mk.skip && mk.skip[(uint32_t)node / (uint32_t)mk.nodes]);
     const bool zero = act && masked && (nflag[node] & 1);
 #pragma unroll
     for (int pt = 0; pt < NPT; ++pt) {
@@ -191,7 +191,9 @@ k_tau(DevView v, const double* __restrict__ Y, double* __restrict__ tau,
   const int64_t gq = blk * GB + g;
   const int64_t e = gq >> 2;
   const int q = (int)(gq & 3);
-  const bool valid = e < v.n_tets;
+  // points of a segment that sits out are left as they are, like those past the end
+  const bool valid = e < v.n_tets &&
+                     !(v.seg.skip && v.seg.skip[(uint32_t)v.conn[e * 4] / (uint32_t)v.seg.nodes]);
   double dN[4][3];
   int nodes[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -553,12 +555,18 @@ template <int K, typename TE>
 __global__ void __launch_bounds__(256)
 k_gather(const int32_t* __restrict__ noff, const int32_t* __restrict__ ninc,
          const uint8_t* __restrict__ nflag, const TE* __restrict__ ebuf,
-         double* __restrict__ out, int64_t nn, FaceSum fs) {
+         double* __restrict__ out, int64_t nn, FaceSum fs, SegMask mk) {
   constexpr int n = Dim<K>::n, S = Dim<K>::S, S4 = 4 * S, R = 4 * n;
   constexpr int NJ = (S4 + 63) / 64;
   const int64_t node = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (node >= nn) return;
   const int lane = threadIdx.x & 63;
+  if (mk.skip && mk.skip[(uint32_t)node / (uint32_t)mk.nodes]) {   // segment sitting out
+#pragma unroll
+    for (int r = 0; r < NJ; ++r)
+      if (lane + 64 * r < S4) out[node * S4 + lane + 64 * r] = 0.0;
+    return;
+  }
   const int k0 = noff[node], k1 = noff[node + 1];
   const bool dir = (nflag[node] & 1) != 0;
   int src[NJ];        // offset of slot j inside an element row, -1 for Im c_0
@@ -879,7 +887,8 @@ int supported_K_list(int* out, int cap) {
 template <typename TO>
 static hipError_t prep_launch(int K, const double* Y, const double* Ys, const uint8_t* nflag,
                               int masked, const double* F, TO* XT, TO* XP, int64_t nn,
-                              hipStream_t st, const DevView* fv, const double* aneg, int fresid) {
+                              hipStream_t st, const DevView* fv, const double* aneg, int fresid,
+                              const SegMask& mk) {
   if (nn == 0) return hipSuccess;
   int64_t nb = (nn + 3) / 4;
   if (nb > 8192) nb = 8192;
@@ -890,7 +899,7 @@ static hipError_t prep_launch(int K, const double* Y, const double* Ys, const ui
 #define CASE(k)                                                                                  \
   case k:                                                                                        \
     k_prep_time<k, TO><<<grid, 256, 0, st>>>(Y, Ys, nflag, masked, F, XT, XP, nn, nb, dv, aneg,   \
-                                             fresid);                                            \
+                                             fresid, mk);                                        \
     break;
     TSGLS_FOR_EACH_K(CASE)
 #undef CASE
@@ -901,14 +910,16 @@ static hipError_t prep_launch(int K, const double* Y, const double* Ys, const ui
 
 hipError_t launch_prep_time(int K, const double* Y, const double* Ys, const uint8_t* nflag,
                             int masked, const double* F, double* XT, double* XP, int64_t nn,
-                            hipStream_t st, const DevView* fv, const double* aneg, int fresid) {
-  return prep_launch<double>(K, Y, Ys, nflag, masked, F, XT, XP, nn, st, fv, aneg, fresid);
+                            hipStream_t st, const DevView* fv, const double* aneg, int fresid,
+                            const SegMask& mk) {
+  return prep_launch<double>(K, Y, Ys, nflag, masked, F, XT, XP, nn, st, fv, aneg, fresid, mk);
 }
 
 hipError_t launch_prep_time_f32(int K, const double* Y, const double* Ys, const uint8_t* nflag,
                                 int masked, const double* F, float* XT, float* XP, int64_t nn,
-                                hipStream_t st, const DevView* fv, const double* aneg, int fresid) {
-  return prep_launch<float>(K, Y, Ys, nflag, masked, F, XT, XP, nn, st, fv, aneg, fresid);
+                                hipStream_t st, const DevView* fv, const double* aneg, int fresid,
+                                const SegMask& mk) {
+  return prep_launch<float>(K, Y, Ys, nflag, masked, F, XT, XP, nn, st, fv, aneg, fresid, mk);
 }
 
 hipError_t launch_tau(const DevView& v, const double* Y, double* tau, hipStream_t st,
@@ -950,12 +961,12 @@ hipError_t launch_diag(const DevView& v, double* d, double shift, int64_t begin,
 
 hipError_t launch_gather(int K, const int32_t* noff, const int32_t* ninc, const uint8_t* nflag,
                          const double* ebuf, double* out, int64_t nn, hipStream_t st,
-                         const FaceSum& fs) {
+                         const FaceSum& fs, const SegMask& mk) {
   const int64_t tot = nn * 4 * (2 * K + 2);
   if (tot == 0) return hipSuccess;
   const unsigned grid = (unsigned)((nn + 3) / 4);
   switch (K) {
-#define CASE(k) case k: k_gather<k, double><<<grid, 256, 0, st>>>(noff, ninc, nflag, ebuf, out, nn, fs); break;
+#define CASE(k) case k: k_gather<k, double><<<grid, 256, 0, st>>>(noff, ninc, nflag, ebuf, out, nn, fs, mk); break;
     TSGLS_FOR_EACH_K(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -965,12 +976,12 @@ hipError_t launch_gather(int K, const int32_t* noff, const int32_t* ninc, const 
 
 hipError_t launch_gather_f32(int K, const int32_t* noff, const int32_t* ninc, const uint8_t* nflag,
                              const float* ebuf, double* out, int64_t nn, hipStream_t st,
-                             const FaceSum& fs) {
+                             const FaceSum& fs, const SegMask& mk) {
   const int64_t tot = nn * 4 * (2 * K + 2);
   if (tot == 0) return hipSuccess;
   const unsigned grid = (unsigned)((nn + 3) / 4);
   switch (K) {
-#define CASE(k) case k: k_gather<k, float><<<grid, 256, 0, st>>>(noff, ninc, nflag, ebuf, out, nn, fs); break;
+#define CASE(k) case k: k_gather<k, float><<<grid, 256, 0, st>>>(noff, ninc, nflag, ebuf, out, nn, fs, mk); break;
     TSGLS_FOR_EACH_K(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;

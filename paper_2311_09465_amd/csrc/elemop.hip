@@ -249,14 +249,14 @@ k_op(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
   // from HBM with no reuse, so its latency is hidden behind the current one)
   using TR = TauReg<MODE, T>;
   typename TR::type tv[4][NTL];
-  if (lo + jx < hi) {
-    const int64_t e0 = lo + jx;
+  auto load_tau = [&](int64_t en) {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int j = 0; j < NTL; ++j)
-        tv[q][j] = tok[j] ? TR::load(v, TAU, (e0 * 4 + q) * P + lane + 64 * j) : typename TR::type(0);
-  }
+        tv[q][j] = tok[j] ? TR::load(v, TAU, (en * 4 + q) * P + lane + 64 * j) : typename TR::type(0);
+  };
+  if (lo + jx < hi) load_tau(lo + jx);
 
   for (int64_t e = lo + jx; e < hi; e += nbx) {
     int nd[4];
@@ -266,6 +266,11 @@ k_op(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
       nd[b] = v.conn[e * 4 + b];
 #pragma unroll
       for (int j = 0; j < 3; ++j) dN[b][j] = v.geo[e * 16 + b * 3 + j];
+    }
+    if (v.seg.skip && v.seg.skip[(uint32_t)nd[0] / (uint32_t)v.seg.nodes]) {
+      // the element's segment sits out this pass: only the next tau block moves in
+      if (e + nbx < hi) load_tau(e + nbx);
+      continue;
     }
     const T wgt = v.geo[e * 16 + 12];
 
@@ -354,14 +359,7 @@ k_op(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
         const int fp = pt * 64 + lane;   // field * PW + position within the node's block
         sV[(b * 4 + fp / PW) * RP + fp % PW] = xv[b][pt];
       }
-    if (e + nbx < hi) {
-      const int64_t en = e + nbx;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int j = 0; j < NTL; ++j)
-          tv[q][j] = tok[j] ? TR::load(v, TAU, (en * 4 + q) * P + lane + 64 * j) : typename TR::type(0);
-    }
+    if (e + nbx < hi) load_tau(e + nbx);
     __syncthreads();
 
     // ---- conv(t) -> modes: lane (q = g, p), reg i

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <set>
 #include <string>
@@ -93,6 +94,19 @@ struct tsgls_ctx {
   } gkey;
   GmDev gm{};
   double* gmbuf = nullptr;
+  // independent problems held as nseg equal contiguous segments of the nodes
+  // (tsgls_set_segments); 1 = one problem.  The graph cycle keeps per
+  // segment: reductions [nseg][128] (red at 0, |r|^2 at 96), block partials
+  // [nseg][nb * 67], squared norms [nseg]; pinned staging for the status
+  // words and norms.
+  int nseg = 1;
+  bool seg_checked = false;     // elements and faces verified to stay in their segment
+  bool seg_mask_on = false;     // element kernels and gathers skip the segments flagged in gm.skip
+  double* segred = nullptr;
+  double* segpart = nullptr;
+  double* segnrm = nullptr;
+  int* hseg = nullptr;          // [nseg][8] status, [nseg] skip flags
+  double* hsegd = nullptr;      // [nseg] norms, [nseg] tolerances
   // FP32 copies of the linearization for the mixed-precision tangent
   // (allocated on first use; the FP32 modes, samples and element rows reuse
   // the FP64 buffers XP, VT and ebuf, which they fit in half)
@@ -205,6 +219,10 @@ DevView view(const tsgls_ctx* c) {
   v.omega = c->p.omega;
   v.C_I = c->p.C_I;
   v.beta = c->p.backflow_beta;
+  if (c->seg_mask_on && c->nseg > 1 && c->gm.skip) {
+    v.seg.skip = c->gm.skip;
+    v.seg.nodes = (int32_t)(c->nn / c->nseg);
+  }
   return v;
 }
 
@@ -276,7 +294,7 @@ int apply_operator(tsgls_ctx* c, const DevView& v, int mode, const double* Y, co
   {
     ProfScope ps(c, TSGLS_PROF_GATHER);
     HIPCHK(c, launch_gather(c->K, c->noff, c->ninc, c->nflag, c->ebuf, out, c->nn, c->st,
-                            face_sum(c, resid)));
+                            face_sum(c, resid), v.seg));
   }
   return TSGLS_OK;
 }
@@ -404,7 +422,7 @@ int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt, cons
   const DevView* fv = c->nf ? &v : nullptr;   // face points in the same launch as the samples
   if (prec == TSGLS_PREC_F64) {
     HIPCHK(c, launch_prep_time(c->K, x, xs, c->nflag, 1, c->F, c->VT, c->XP, c->nn, c->st, fv,
-                               c->aneg, 0));
+                               c->aneg, 0, v.seg));
     return apply_operator(c, v, mode, x, c->VT, nullptr, out, shift, c->aneg, 0, xs, true);
   }
   CHK(ensure_lin32(c));
@@ -415,7 +433,7 @@ int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt, cons
   float* VT32 = reinterpret_cast<float*>(c->VT);
   float* eb32 = reinterpret_cast<float*>(c->ebuf);
   HIPCHK(c, launch_prep_time_f32(c->K, x, xs, c->nflag, 1, c->F, VT32, XP32, c->nn, c->st,
-                                 c->nf ? &v : nullptr, c->aneg, 0));
+                                 c->nf ? &v : nullptr, c->aneg, 0, v.seg));
   {
     ProfScope ps(c, TSGLS_PROF_ELEM_TANGENT);
     HIPCHK(c, launch_elem_f32(v, mode32, XP32, VT32, eb32, shift, 0, c->E, c->st));
@@ -423,7 +441,7 @@ int jv_impl(tsgls_ctx* c, const double* x, double* out, int jac, double dt, cons
   {
     ProfScope ps(c, TSGLS_PROF_GATHER);
     HIPCHK(c, launch_gather_f32(c->K, c->noff, c->ninc, c->nflag, eb32, out, c->nn, c->st,
-                                face_sum(c, 0)));
+                                face_sum(c, 0), v.seg));
   }
   return TSGLS_OK;
 }
@@ -692,34 +710,96 @@ int gmres_delayed(tsgls_ctx* c, const double* b, double* x, double tol, int m, i
   return TSGLS_OK;
 }
 
+// Device-side least-squares state per segment (doubles), status words per
+// segment, reduction slots per segment.
+constexpr int64_t GM_SEGD = 2400;
+constexpr int GM_ST = 8;
+constexpr int64_t GM_RED = 128;
+constexpr int64_t GM_BB = 96;    // |r|^2 of the cycle's start within a segment's reduction slots
+
+int ensure_gm(tsgls_ctx* c) {
+  if (c->gmbuf) return TSGLS_OK;
+  const int S = c->nseg;
+  const int64_t L = ndof(c) / S;
+  const int nb = multidot_blocks(L);
+  CHK(dalloc(c, &c->gmbuf, (size_t)S * GM_SEGD + ((size_t)S * (GM_ST + 1) + 1) / 2 + 16));
+  CHK(dalloc(c, &c->segred, (size_t)S * GM_RED));
+  CHK(dalloc(c, &c->segpart, (size_t)S * nb * 67));
+  CHK(dalloc(c, &c->segnrm, (size_t)S));
+  HIPCHK(c, hipHostMalloc((void**)&c->hseg, (size_t)S * (GM_ST + 1) * sizeof(int), hipHostMallocDefault));
+  HIPCHK(c, hipHostMalloc((void**)&c->hsegd, (size_t)2 * S * sizeof(double), hipHostMallocDefault));
+  const int ld = 33;
+  double* p = c->gmbuf;
+  c->gm.H = p;
+  c->gm.R = p + ld * 32;
+  c->gm.cs = p + 2 * ld * 32;
+  c->gm.sn = c->gm.cs + 32;
+  c->gm.g = c->gm.sn + 32;
+  c->gm.y = c->gm.g + 33;
+  c->gm.ab = c->gm.y + 32;
+  c->gm.sc = c->gm.ab + 64;
+  c->gm.st = reinterpret_cast<int*>(c->gmbuf + (size_t)S * GM_SEGD);
+  c->gm.sd = GM_SEGD;
+  c->gm.si = GM_ST;
+  c->gm.skip = c->gm.st + (size_t)S * GM_ST;
+  std::fill(c->hseg, c->hseg + (size_t)S * (GM_ST + 1), 0);
+  HIPCHK(c, hipMemcpyAsync(c->gm.st, c->hseg, (size_t)S * (GM_ST + 1) * sizeof(int), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return TSGLS_OK;
+}
+
+void free_gm(tsgls_ctx* c) {
+  drop_graph(c);
+  for (double** q : {&c->gmbuf, &c->segred, &c->segpart, &c->segnrm}) {
+    dfree(c, *q);
+    *q = nullptr;
+  }
+  if (c->hseg) (void)hipHostFree(c->hseg);
+  if (c->hsegd) (void)hipHostFree(c->hsegd);
+  c->hseg = nullptr;
+  c->hsegd = nullptr;
+  c->gm = GmDev{};
+}
+
+// Euclidean norm of each segment of x into out[nseg] (one synchronization);
+// with one segment the same kernels and blocking as norm2.
+int seg_norms(tsgls_ctx* c, const double* x, double* out) {
+  CHK(ensure_gm(c));
+  const int S = c->nseg;
+  const int64_t L = ndof(c) / S;
+  const int nb = multidot_blocks(L);
+  const int64_t ps = (int64_t)nb * 67;
+  const int* sk = S > 1 ? c->gm.skip : nullptr;
+  HIPCHK(c, launch_multidot(x, 0, 1, x, c->segpart, nb, L, c->st, S, L, ps, sk));
+  HIPCHK(c, launch_reduce_partials(c->segpart, nb, 1, c->segnrm, c->st, S, ps, 1, sk));
+  HIPCHK(c, hipMemcpyAsync(c->hsegd, c->segnrm, S * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  for (int s = 0; s < S; ++s) out[s] = std::sqrt(c->hsegd[s]);
+  return TSGLS_OK;
+}
+
 // The same delayed Gram-Schmidt GMRES (m <= 32) with the least-squares
 // update on the device (k_gm_*), so that one cycle -- the residual norm, m
 // Arnoldi steps (tangent product, reduction, update), the final reduction,
 // the triangular solve and the update of x -- is one HIP graph, captured
 // once per (m, tangent, shift, precision) and replayed for every cycle of
 // every Newton step.  The host synchronizes once per cycle to read the
-// convergence flag.  Cycles always run m steps: after convergence the
+// convergence flags.  Cycles always run m steps: after convergence the
 // remaining steps see zero update coefficients and leave zero vectors.
+// With segments every launch of the cycle covers all of them (one GMRES per
+// segment, each segment's reductions over its own entries with the blocking
+// of a lone problem of that size, so each segment follows the iteration its
+// problem would follow alone); a segment that has converged, run out of
+// products, or is frozen (frozen[s] != 0) sits out the remaining cycles with
+// zero updates.  mv_out, conv: per segment.
 int gmres_graph(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv, int jac,
-                double dt, int prec, int* mv_out, bool* conv) {
-  const int64_t n = ndof(c);
-  const int nb = multidot_blocks(n);
-  *conv = false;
+                double dt, int prec, int* mv_out, bool* conv, const char* frozen = nullptr) {
+  const int S = c->nseg;
+  const int64_t n = ndof(c), L = n / S;
+  const int nb = multidot_blocks(L);
+  const int64_t ps = (int64_t)nb * 67;
   if (m > 32) return fail(c, TSGLS_EINVAL, "graph GMRES needs restart <= 32");
-  if (!c->gmbuf) {
-    CHK(dalloc(c, &c->gmbuf, 2400 + 16));
-    const int ld = 33;
-    double* p = c->gmbuf;
-    c->gm.H = p;
-    c->gm.R = p + ld * 32;
-    c->gm.cs = p + 2 * ld * 32;
-    c->gm.sn = c->gm.cs + 32;
-    c->gm.g = c->gm.sn + 32;
-    c->gm.y = c->gm.g + 33;
-    c->gm.ab = c->gm.y + 32;
-    c->gm.sc = c->gm.ab + 64;
-    c->gm.st = reinterpret_cast<int*>(c->gmbuf + 2400);
-  }
+  CHK(ensure_gm(c));
   if (!c->gst) {
     HIPCHK(c, hipStreamCreateWithFlags(&c->gst, hipStreamNonBlocking));
     HIPCHK(c, hipEventCreateWithFlags(&c->gev[0], hipEventDisableTiming));
@@ -741,29 +821,33 @@ int gmres_graph(tsgls_ctx* c, const double* b, double* x, double tol, int m, int
     CHK(jv_impl(c, b, c->kt, jac, dt, c->minv, prec));
     HIPCHK(c, hipStreamSynchronize(c->st));
     const GmDev d = c->gm;
-    double* red = c->dh;
-    double* bb = c->dh + 2040;
+    double* red = c->segred;
+    double* bb = c->segred + GM_BB;
+    // segments that sit out the cycle are skipped by the vector kernels too
+    // (their least-squares state is silenced by k_gm_begin)
+    const int* sk = S > 1 ? d.skip : nullptr;
     auto body = [&]() -> int {
       double* V0 = c->V;
-      HIPCHK(c, launch_multidot(V0, 0, 1, V0, c->partial, nb, n, c->st));
-      HIPCHK(c, launch_reduce_partials(c->partial, nb, 1, bb, c->st));
-      HIPCHK(c, launch_gm_begin(d, bb, tol, 0, c->st));
-      HIPCHK(c, launch_scal_dev(V0, d.sc + 5, n, c->st));
+      HIPCHK(c, launch_multidot(V0, 0, 1, V0, c->segpart, nb, L, c->st, S, L, ps, sk));
+      HIPCHK(c, launch_reduce_partials(c->segpart, nb, 1, bb, c->st, S, ps, GM_RED, sk));
+      HIPCHK(c, launch_gm_begin(d, bb, tol, 0, c->st, S, GM_RED));
+      HIPCHK(c, launch_scal_dev(V0, d.sc + 5, L, c->st, S, L, GM_SEGD, sk));
       for (int j = 0; j < m; ++j) {
         double* u = c->V + (int64_t)j * n;
         double* w = c->V + (int64_t)(j + 1) * n;
         CHK(jv_impl(c, u, w, jac, dt, c->minv, prec));
-        HIPCHK(c, launch_gs_reduce(c->V, n, j, u, w, c->partial, nb, n, c->st));
-        HIPCHK(c, launch_reduce_partials(c->partial, nb, 2 * j + 3, red, c->st));
-        HIPCHK(c, launch_gm_step(d, j, red, c->st));
-        HIPCHK(c, launch_gs_update(c->V, n, j, d.ab, nullptr, 0.0, 0.0, 0.0, d.sc, u, w, n, c->st));
+        HIPCHK(c, launch_gs_reduce(c->V, n, j, u, w, c->segpart, nb, L, c->st, S, L, ps, sk));
+        HIPCHK(c, launch_reduce_partials(c->segpart, nb, 2 * j + 3, red, c->st, S, ps, GM_RED, sk));
+        HIPCHK(c, launch_gm_step(d, j, red, c->st, S, GM_RED));
+        HIPCHK(c, launch_gs_update(c->V, n, j, d.ab, nullptr, 0.0, 0.0, 0.0, d.sc, u, w, L, c->st, S, L,
+                                   GM_SEGD, sk));
       }
       double* um = c->V + (int64_t)m * n;
-      HIPCHK(c, launch_gs_reduce(c->V, n, m, um, um, c->partial, nb, n, c->st));
-      HIPCHK(c, launch_reduce_partials(c->partial, nb, 2 * m + 3, red, c->st));
-      HIPCHK(c, launch_gm_final(d, red, c->st));
+      HIPCHK(c, launch_gs_reduce(c->V, n, m, um, um, c->segpart, nb, L, c->st, S, L, ps, sk));
+      HIPCHK(c, launch_reduce_partials(c->segpart, nb, 2 * m + 3, red, c->st, S, ps, GM_RED, sk));
+      HIPCHK(c, launch_gm_final(d, red, c->st, S, GM_RED));
       HIPCHK(c, launch_zero(c->kt, n, c->st));
-      HIPCHK(c, launch_multiaxpy_add(c->V, n, m, d.y, c->kt, n, c->st));
+      HIPCHK(c, launch_multiaxpy_add(c->V, n, m, d.y, c->kt, L, c->st, S, L, GM_SEGD, sk));
       HIPCHK(c, launch_mul(c->minv, c->kt, c->kt2, n, c->st));
       HIPCHK(c, launch_axpy(1.0, c->kt2, x, n, c->st));
       return TSGLS_OK;
@@ -789,25 +873,35 @@ int gmres_graph(tsgls_ctx* c, const double* b, double* x, double tol, int m, int
     c->gkey = key;
   }
   HIPCHK(c, launch_zero(x, n, c->st));
-  double bnorm;
-  CHK(norm2(c, b, &bnorm));
-  if (!std::isfinite(bnorm)) return fail(c, TSGLS_ENONFINITE, "non-finite right-hand side");
-  if (bnorm == 0.0) {
-    *conv = true;
-    *mv_out = 0;
-    return TSGLS_OK;
+  std::vector<double> bn(S);
+  CHK(seg_norms(c, b, bn.data()));
+  std::vector<char> act(S, 0);
+  int* skip = c->hseg + (size_t)S * GM_ST;
+  int nact = 0;
+  for (int s = 0; s < S; ++s) {
+    mv_out[s] = 0;
+    conv[s] = false;
+    const bool fz = frozen && frozen[s];
+    if (!fz && !std::isfinite(bn[s])) return fail(c, TSGLS_ENONFINITE, "non-finite right-hand side");
+    if (!fz && bn[s] == 0.0) conv[s] = true;
+    act[s] = !fz && bn[s] != 0.0;
+    skip[s] = !act[s];
+    nact += act[s];
+    c->hsegd[S + s] = tol * bn[s];
   }
-  c->hp[3590] = tol * bnorm;
-  HIPCHK(c, hipMemcpyAsync(c->gm.sc + 4, c->hp + 3590, sizeof(double), hipMemcpyHostToDevice, c->st));
-  int mv = 0;
+  if (nact == 0) return TSGLS_OK;
+  for (int s = 0; s < S; ++s)
+    HIPCHK(c, hipMemcpyAsync(c->gm.sc + (size_t)s * GM_SEGD + 4, c->hsegd + S + s, sizeof(double),
+                             hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(const_cast<int*>(c->gm.skip), skip, S * sizeof(int), hipMemcpyHostToDevice, c->st));
   bool first = true;
-  while (mv + m <= maxmv || first) {
+  while (nact > 0) {
     double* V0 = c->V;
     if (first) {
       HIPCHK(c, launch_copy(b, V0, n, c->st));
     } else {
       CHK(jv_impl(c, x, c->kt, jac, dt, nullptr, prec));
-      ++mv;
+      for (int s = 0; s < S; ++s) mv_out[s] += act[s];
       HIPCHK(c, launch_copy(b, V0, n, c->st));
       HIPCHK(c, launch_axpy(-1.0, c->kt, V0, n, c->st));
     }
@@ -817,21 +911,25 @@ int gmres_graph(tsgls_ctx* c, const double* b, double* x, double tol, int m, int
     HIPCHK(c, hipGraphLaunch(c->gexec, c->gst));
     HIPCHK(c, hipEventRecord(c->gev[1], c->gst));
     HIPCHK(c, hipStreamWaitEvent(c->st, c->gev[1], 0));
-    mv += m;
-    int stv[4];
-    double est = 0.0;
-    HIPCHK(c, hipMemcpyAsync(c->hp + 3584, c->gm.st, sizeof(stv), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(c, hipMemcpyAsync(c->hp + 3586, c->gm.sc + 6, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->hseg, c->gm.st, (size_t)S * GM_ST * sizeof(int), hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
-    std::memcpy(stv, c->hp + 3584, sizeof(stv));
-    est = c->hp[3586];
-    if (!std::isfinite(est)) return fail(c, TSGLS_ENONFINITE, "non-finite Krylov quantity");
-    if (stv[3]) {
-      *conv = true;
-      break;
+    bool changed = false;
+    for (int s = 0; s < S; ++s) {
+      if (!act[s]) continue;
+      mv_out[s] += m;
+      const int* stv = c->hseg + (size_t)s * GM_ST;
+      if (stv[4]) return fail(c, TSGLS_ENONFINITE, "non-finite Krylov quantity");
+      if (stv[3]) conv[s] = true;
+      if (stv[3] || mv_out[s] + m > maxmv) {
+        act[s] = 0;
+        skip[s] = 1;
+        --nact;
+        changed = true;
+      }
     }
+    if (changed && nact > 0)
+      HIPCHK(c, hipMemcpyAsync(const_cast<int*>(c->gm.skip), skip, S * sizeof(int), hipMemcpyHostToDevice, c->st));
   }
-  *mv_out = mv;
   return TSGLS_OK;
 }
 
@@ -964,6 +1062,88 @@ int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv
   return TSGLS_OK;
 }
 
+// Processing order: Morton order of the element centroids (locality of the
+// node gathers; contributions are summed per node afterwards in a fixed
+// order).  Returns processing position -> input element.
+std::vector<int32_t> morton_perm(const double* xyz, int64_t n_nodes, const int32_t* tets, int64_t n_tets) {
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t i = 0; i < n_nodes; ++i)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::min(lo[d], xyz[i * 3 + d]);
+      hi[d] = std::max(hi[d], xyz[i * 3 + d]);
+    }
+  std::vector<uint64_t> key(n_tets);
+  for (int64_t e = 0; e < n_tets; ++e) {
+    double cc[3] = {0, 0, 0};
+    for (int b = 0; b < 4; ++b)
+      for (int d = 0; d < 3; ++d) cc[d] += 0.25 * xyz[(int64_t)tets[e * 4 + b] * 3 + d];
+    for (int d = 0; d < 3; ++d) cc[d] = (cc[d] - lo[d]) / std::max(hi[d] - lo[d], 1e-300);
+    key[e] = morton3(cc[0], cc[1], cc[2]);
+  }
+  std::vector<int32_t> perm(n_tets);
+  for (int64_t e = 0; e < n_tets; ++e) perm[e] = (int32_t)e;
+  std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+  return perm;
+}
+
+// Install a processing order (position -> input element) for the input-order
+// tets: connectivity in that order, node -> incident (element, local node)
+// in ascending position, and the element geometry; the linearization is
+// invalidated.
+int set_order(tsgls_ctx* c, const int32_t* tets, const std::vector<int32_t>& perm) {
+  const int64_t n_tets = c->E, n_nodes = c->nn;
+  std::vector<int32_t> sconn(n_tets * 4);
+  for (int64_t e = 0; e < n_tets; ++e)
+    for (int b = 0; b < 4; ++b) sconn[e * 4 + b] = tets[(int64_t)perm[e] * 4 + b];
+  std::vector<int32_t> noff(n_nodes + 1, 0), ninc(n_tets * 4);
+  for (int64_t k = 0; k < n_tets * 4; ++k) noff[sconn[k] + 1]++;
+  for (int64_t i = 0; i < n_nodes; ++i) noff[i + 1] += noff[i];
+  {
+    std::vector<int32_t> fill(noff.begin(), noff.end() - 1);
+    for (int64_t k = 0; k < n_tets * 4; ++k) ninc[fill[sconn[k]]++] = (int32_t)k;
+  }
+  double* dxyz = nullptr;
+  CHK(dalloc(c, &dxyz, n_nodes * 3));
+  HIPCHK(c, hipMemcpyAsync(dxyz, c->hxyz.data(), n_nodes * 3 * sizeof(double), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->conn, sconn.data(), n_tets * 4 * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->noff, noff.data(), noff.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->ninc, ninc.data(), ninc.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, launch_geometry(dxyz, c->conn, c->geo, nullptr, n_tets, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  dfree(c, dxyz);
+  c->dev_bytes -= n_nodes * 3 * sizeof(double);
+  if (&perm != &c->perm) c->perm = perm;
+  c->linearized = false;
+  c->lin32 = false;
+  c->lin16 = false;
+  c->tauV_ok = false;
+  return TSGLS_OK;
+}
+
+// Every element (and Neumann face) must have its nodes in one segment, so
+// that the segments are independent problems.
+int check_segments(tsgls_ctx* c) {
+  if (c->seg_checked || c->nseg == 1) return TSGLS_OK;
+  const int64_t Ln = c->nn / c->nseg;
+  std::vector<int32_t> h((size_t)c->E * 4);
+  HIPCHK(c, hipMemcpy(h.data(), c->conn, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int64_t e = 0; e < c->E; ++e) {
+    const int64_t s0 = h[e * 4] / Ln;
+    for (int b = 1; b < 4; ++b)
+      if (h[e * 4 + b] / Ln != s0)
+        return fail(c, TSGLS_EINVAL, "element %lld has nodes in two segments", (long long)c->perm[e]);
+  }
+  if (c->nf) {
+    std::vector<int32_t> f((size_t)c->nf * 3);
+    HIPCHK(c, hipMemcpy(f.data(), c->fconn, f.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < c->nf; ++i)
+      if (f[i * 3 + 1] / Ln != f[i * 3] / Ln || f[i * 3 + 2] / Ln != f[i * 3] / Ln)
+        return fail(c, TSGLS_EINVAL, "Neumann face %lld has nodes in two segments", (long long)i);
+  }
+  c->seg_checked = true;
+  return TSGLS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1007,41 +1187,8 @@ int tsgls_create(const double* xyz, int64_t n_nodes, const int32_t* tets, int64_
                        d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
     if (!(det > 0)) return fail(c, TSGLS_EMESH, "tet %lld has non-positive volume", (long long)e);
   }
-  // processing order: Morton order of the element centroids (locality of the
-  // node gathers); contributions are summed per node afterwards in a fixed order
-  {
-    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-    for (int64_t i = 0; i < n_nodes; ++i)
-      for (int d = 0; d < 3; ++d) {
-        lo[d] = std::min(lo[d], xyz[i * 3 + d]);
-        hi[d] = std::max(hi[d], xyz[i * 3 + d]);
-      }
-    std::vector<uint64_t> key(n_tets);
-    for (int64_t e = 0; e < n_tets; ++e) {
-      double cc[3] = {0, 0, 0};
-      for (int b = 0; b < 4; ++b)
-        for (int d = 0; d < 3; ++d) cc[d] += 0.25 * xyz[(int64_t)tets[e * 4 + b] * 3 + d];
-      for (int d = 0; d < 3; ++d) cc[d] = (cc[d] - lo[d]) / std::max(hi[d] - lo[d], 1e-300);
-      key[e] = morton3(cc[0], cc[1], cc[2]);
-    }
-    c->perm.resize(n_tets);
-    for (int64_t e = 0; e < n_tets; ++e) c->perm[e] = (int32_t)e;
-    std::stable_sort(c->perm.begin(), c->perm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
-  }
-  std::vector<int32_t> sconn(n_tets * 4);
-  for (int64_t e = 0; e < n_tets; ++e)
-    for (int b = 0; b < 4; ++b) sconn[e * 4 + b] = tets[(int64_t)c->perm[e] * 4 + b];
-  // node -> incident (element, local node) in ascending element order
-  std::vector<int32_t> noff(n_nodes + 1, 0), ninc(n_tets * 4);
-  for (int64_t k = 0; k < n_tets * 4; ++k) noff[sconn[k] + 1]++;
-  for (int64_t i = 0; i < n_nodes; ++i) noff[i + 1] += noff[i];
-  {
-    std::vector<int32_t> fill(noff.begin(), noff.end() - 1);
-    for (int64_t k = 0; k < n_tets * 4; ++k) ninc[fill[sconn[k]]++] = (int32_t)k;
-  }
+  c->perm = morton_perm(xyz, n_nodes, tets, n_tets);
   // device data
-  double* dxyz = nullptr;
-  CHK(dalloc(c, &dxyz, n_nodes * 3));
   CHK(dalloc(c, &c->conn, n_tets * 4));
   CHK(dalloc(c, &c->geo, n_tets * 16));
   CHK(dalloc(c, &c->nflag, n_nodes));
@@ -1055,10 +1202,6 @@ int tsgls_create(const double* xyz, int64_t n_nodes, const int32_t* tets, int64_
   CHK(dalloc(c, &c->ninc, n_tets * 4));
   CHK(dalloc(c, &c->ebuf, (size_t)n_tets * 16 * c->n));
   CHK(dalloc(c, &c->rs, n_nodes * 4 * c->S));
-  HIPCHK(c, hipMemcpyAsync(dxyz, xyz, n_nodes * 3 * sizeof(double), hipMemcpyHostToDevice, c->st));
-  HIPCHK(c, hipMemcpyAsync(c->conn, sconn.data(), n_tets * 4 * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
-  HIPCHK(c, hipMemcpyAsync(c->noff, noff.data(), noff.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
-  HIPCHK(c, hipMemcpyAsync(c->ninc, ninc.data(), ninc.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemsetAsync(c->nflag, 0, n_nodes, c->st));
   std::vector<double> F((size_t)c->n * c->M);
   const double pi = 3.14159265358979323846;
@@ -1071,10 +1214,7 @@ int tsgls_create(const double* xyz, int64_t n_nodes, const int32_t* tets, int64_
     }
   }
   HIPCHK(c, hipMemcpyAsync(c->F, F.data(), F.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
-  HIPCHK(c, launch_geometry(dxyz, c->conn, c->geo, nullptr, n_tets, c->st));
-  HIPCHK(c, hipStreamSynchronize(c->st));
-  dfree(c, dxyz);
-  c->dev_bytes -= n_nodes * 3 * sizeof(double);
+  CHK(set_order(c, tets, c->perm));
   return TSGLS_OK;
 }
 
@@ -1096,6 +1236,7 @@ int tsgls_set_neumann(tsgls_ctx* c, const int32_t* tris, int64_t nf, const doubl
   if (nf < 0 || (nf > 0 && !tris)) return fail(c, TSGLS_EINVAL, "bad Neumann arguments");
   if (c->tracer && h) return fail(c, TSGLS_EINVAL, "the tracer takes no Neumann traction");
   drop_graph(c);
+  c->seg_checked = false;
   dfree(c, c->fconn);
   dfree(c, c->fgeo);
   dfree(c, c->fh);
@@ -1218,6 +1359,7 @@ int tsgls_set_tracer(tsgls_ctx* c, const double* y_velocity, double kappa, int s
   if (!y_velocity || !(kappa > 0) || !std::isfinite(kappa) || (stabilized != 0 && stabilized != 1))
     return fail(c, TSGLS_EINVAL, "bad tracer arguments");
   if (c->fh) return fail(c, TSGLS_EINVAL, "the tracer context must have no Neumann traction");
+  if (c->nseg > 1) return fail(c, TSGLS_EINVAL, "a context with segments takes no tracer");
   const int64_t n = ndof(c);
   drop_graph(c);
   if (!c->yvel) CHK(dalloc(c, &c->yvel, n));
@@ -1291,6 +1433,7 @@ int tsgls_solve(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_
     return fail(c, TSGLS_EINVAL, "bad solve options");
   if (o->dt_schedule != TSGLS_DT_FIXED && !(o->dt_pseudo > 0))
     return fail(c, TSGLS_EINVAL, "an adaptive pseudo-time schedule needs dt_pseudo > 0");
+  if (c->nseg > 1) return fail(c, TSGLS_EINVAL, "a context with segments is solved by tsgls_solve_segments");
   const auto t0 = std::chrono::steady_clock::now();
   tsgls_solve_stats st{};
   st.switched_at = -1;
@@ -1399,6 +1542,133 @@ int tsgls_solve(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_
   return status;
 }
 
+int tsgls_set_segments(tsgls_ctx* c, int nseg) {
+  if (!c) return TSGLS_EINVAL;
+  if (nseg < 1 || c->nn % nseg != 0) return fail(c, TSGLS_EINVAL, "nseg must be >= 1 and divide n_nodes");
+  if (c->tracer && nseg > 1) return fail(c, TSGLS_EINVAL, "a tracer context takes no segments");
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  free_gm(c);
+  const int old = c->nseg;
+  c->nseg = nseg;
+  c->seg_checked = false;
+  const int rc = check_segments(c);
+  if (rc != TSGLS_OK) {
+    c->nseg = old;
+    c->seg_checked = false;
+    return rc;
+  }
+  // The element order stays the Morton order of the whole mesh: copies of
+  // one mesh interleave element by element, so every XCD's range and every
+  // wave's elements spread over all segments, and segments that sit out
+  // thin the work evenly.  Within a segment the relative order is that of
+  // its mesh alone (stable sort on equal keys), so sums over a node's
+  // elements run in the same order.
+  return TSGLS_OK;
+}
+
+int tsgls_solve_segments(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_stats* stats,
+                         double* finish_s) {
+  if (!c) return TSGLS_EINVAL;
+  if (!y || !o || !stats) return fail(c, TSGLS_EINVAL, "null argument");
+  if (o->restart < 1 || o->restart > 32 || o->max_newton < 0 || o->max_matvec < 1 || !(o->rtol > 0) ||
+      !(o->lin_rtol > 0) || o->jacobian < 0 || o->jacobian > 2 ||
+      (o->tangent_precision != TSGLS_PREC_F64 && o->tangent_precision != TSGLS_PREC_F32 &&
+       o->tangent_precision != TSGLS_PREC_BF16) ||
+      o->dt_schedule != TSGLS_DT_FIXED || !std::isfinite(o->dt_pseudo))
+    return fail(c, TSGLS_EINVAL, "bad options for a segmented solve (restart <= 32, fixed pseudo-time step)");
+  if (c->tracer) return fail(c, TSGLS_EINVAL, "segmented solves take the flow operator");
+  CHK(check_segments(c));
+  const auto t0 = std::chrono::steady_clock::now();
+  auto now = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+  const int S = c->nseg;
+  CHK(ensure_krylov(c, o->restart));
+  CHK(ensure_gm(c));
+  const int64_t n = ndof(c);
+  double* r = c->rs;
+  // Segments that have finished sit out the element kernels and gathers:
+  // gm.skip flags them (frozen ones during linearization, and during GMRES
+  // also those whose linear solve of this step is over).
+  struct MaskOn {
+    tsgls_ctx* c;
+    explicit MaskOn(tsgls_ctx* x) : c(x) { c->seg_mask_on = true; }
+    ~MaskOn() { c->seg_mask_on = false; }
+  } mask_on(c);
+  std::vector<char> frozen(S, 0);
+  auto write_skip = [&]() -> int {
+    int* skip = c->hseg + (size_t)S * GM_ST;
+    for (int s = 0; s < S; ++s) skip[s] = frozen[s];
+    HIPCHK(c, hipMemcpyAsync(const_cast<int*>(c->gm.skip), skip, S * sizeof(int), hipMemcpyHostToDevice, c->st));
+    return TSGLS_OK;
+  };
+  CHK(write_skip());
+  c->tauV_ok = false;   // the first tau starts cold, as in tsgls_solve
+  CHK(linearize_impl(c, y, r));
+  std::vector<double> r0(S), rn(S), rnew(S), fin(S, 0.0);
+  CHK(seg_norms(c, r, r0.data()));
+  for (int s = 0; s < S; ++s)
+    if (!std::isfinite(r0[s])) return fail(c, TSGLS_ENONFINITE, "non-finite initial residual (segment %d)", s);
+  std::vector<tsgls_solve_stats> st(S);
+  for (int s = 0; s < S; ++s) {
+    st[s] = tsgls_solve_stats{};
+    st[s].switched_at = -1;
+    st[s].status = TSGLS_NOT_CONVERGED;
+    st[s].r0_norm = r0[s];
+    rn[s] = r0[s];
+  }
+  std::vector<int> it(S, 0), mv(S, 0);
+  std::unique_ptr<bool[]> lin_ok(new bool[S]);
+  const double dt = o->dt_pseudo;
+  for (;;) {
+    int nact = 0;
+    for (int s = 0; s < S; ++s) {
+      if (frozen[s]) continue;
+      const double rel = r0[s] > 0 ? rn[s] / r0[s] : 0.0;
+      st[s].rel_residual = rel;
+      if (it[s] > 0 && it[s] <= 64) st[s].history[it[s] - 1] = rel;
+      if (rel <= o->rtol || r0[s] == 0.0) st[s].status = TSGLS_OK;
+      if (st[s].status == TSGLS_OK || it[s] >= o->max_newton) {
+        frozen[s] = 1;
+        fin[s] = now();
+        continue;
+      }
+      ++nact;
+    }
+    if (nact == 0) break;
+    CHK(diag_impl(c, c->minv, dt));
+    HIPCHK(c, launch_recip(c->minv, n, c->st));
+    HIPCHK(c, launch_scal_copy(-1.0, r, r, n, c->st));
+    CHK(gmres_graph(c, r, c->kx, o->lin_rtol, o->restart, o->max_matvec, o->jacobian, dt,
+                    o->tangent_precision, mv.data(), lin_ok.get(), frozen.data()));
+    HIPCHK(c, launch_axpy(1.0, c->kx, y, n, c->st));
+    CHK(write_skip());
+    CHK(linearize_impl(c, y, r));
+    CHK(seg_norms(c, r, rnew.data()));
+    for (int s = 0; s < S; ++s) {
+      if (frozen[s]) continue;
+      st[s].matvecs += mv[s];
+      if (!lin_ok[s]) ++st[s].lin_unconverged;
+      ++it[s];
+      st[s].dt_last = dt;
+      if (!std::isfinite(rnew[s]))
+        return fail(c, TSGLS_ENONFINITE, "non-finite residual at Newton step %d (segment %d)", it[s], s);
+      if (o->verbose)
+        fprintf(stderr, "tsgls segment %d newton %d: |r|/|r0| = %.3e  gmres %d\n", s, it[s],
+                rnew[s] / r0[s], mv[s]);
+      rn[s] = rnew[s];
+    }
+  }
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  int status = TSGLS_OK;
+  for (int s = 0; s < S; ++s) {
+    st[s].newton_iters = it[s];
+    st[s].seconds = fin[s];
+    stats[s] = st[s];
+    if (finish_s) finish_s[s] = fin[s];
+    if (st[s].status != TSGLS_OK) status = TSGLS_NOT_CONVERGED;
+  }
+  return status;
+}
+
 int tsgls_solve_batch(tsgls_ctx* const* ctxs, double* const* ys, int nb, const tsgls_solve_opts* o,
                       tsgls_solve_stats* stats, double* finish_s, int max_concurrent) {
   if (nb < 0) return TSGLS_EINVAL;
@@ -1494,6 +1764,8 @@ void tsgls_destroy(tsgls_ctx* c) {
     if (e) (void)hipEventDestroy(e);
   if (c->gst) (void)hipStreamDestroy(c->gst);
   if (c->hp) (void)hipHostFree(c->hp);
+  if (c->hseg) (void)hipHostFree(c->hseg);
+  if (c->hsegd) (void)hipHostFree(c->hsegd);
   for (void* p : c->allocs) (void)hipFree(p);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;

@@ -44,6 +44,15 @@ enum : int {
 };
 
 // Device view of one mesh + linearization.  All pointers are device memory.
+// Segments that sit out a pass (segmented contexts): skip[s] != 0 for the
+// segment of node blocks [s nodes, (s+1) nodes).  The element kernels of the
+// small harmonic counts leave such a segment's elements untouched, and the
+// node gather writes zero rows for its nodes.  skip == nullptr: none.
+struct SegMask {
+  const int* skip = nullptr;
+  int32_t nodes = 1;
+};
+
 struct DevView {
   int K;
   int64_t n_nodes, n_tets, n_faces;
@@ -70,6 +79,7 @@ struct DevView {
   const double* aneg;        // [nf][3][P] |A_n|_- packed per face point
   double* fy;                // [nf][3][3][n] scratch: |A_n|_- u per face point
   double rho, mu, omega, C_I, beta;
+  SegMask seg;               // segments skipped by k_op and k_tau (small K)
 };
 
 // Launchers (return hipError_t of the launch).  Element ranges [begin, end)
@@ -84,17 +94,18 @@ hipError_t launch_geometry(const double* xyz, const int32_t* conn, double* geo,
 // input is Y, or Y * Ys entrywise when Ys is not null.
 // When fv is not null, the same launch also forms the Neumann face points of
 // the input (as launch_face_point(*fv, Y, Ys, fresid, aneg)) in extra blocks.
+// Nodes of segments flagged in mk are left as they are.
 hipError_t launch_prep_time(int K, const double* Y, const double* Ys,
                             const uint8_t* nflag, int masked, const double* F,
                             double* XT, double* XP, int64_t n_nodes, hipStream_t st,
                             const DevView* fv = nullptr, const double* aneg = nullptr,
-                            int fresid = 0);
+                            int fresid = 0, const SegMask& mk = SegMask());
 // The same with FP32 outputs (the sums are formed in FP64).
 hipError_t launch_prep_time_f32(int K, const double* Y, const double* Ys,
                                 const uint8_t* nflag, int masked, const double* F,
                                 float* XT, float* XP, int64_t n_nodes, hipStream_t st,
                                 const DevView* fv = nullptr, const double* aneg = nullptr,
-                                int fresid = 0);
+                                int fresid = 0, const SegMask& mk = SegMask());
 // Positions per field row of XP (16 or 32).
 int pos_width(int K);
 // tau at every quadrature point.  Vin / Vout (optional, K <= 15 only):
@@ -140,11 +151,13 @@ struct FaceSum {
 // bit 0) are written as zero.
 hipError_t launch_gather(int K, const int32_t* noff, const int32_t* ninc,
                          const uint8_t* nflag, const double* ebuf, double* out,
-                         int64_t n_nodes, hipStream_t st, const FaceSum& fs = FaceSum());
+                         int64_t n_nodes, hipStream_t st, const FaceSum& fs = FaceSum(),
+                         const SegMask& mk = SegMask());
 // The same from FP32 element rows (accumulated in FP64).
 hipError_t launch_gather_f32(int K, const int32_t* noff, const int32_t* ninc,
                              const uint8_t* nflag, const float* ebuf, double* out,
-                             int64_t n_nodes, hipStream_t st, const FaceSum& fs = FaceSum());
+                             int64_t n_nodes, hipStream_t st, const FaceSum& fs = FaceSum(),
+                             const SegMask& mk = SegMask());
 hipError_t launch_face_lin(const DevView& v, const double* Y, double* aneg,
                            hipStream_t st);
 // Per Neumann face point: fy = -(rho beta / 2)(area / 3) |A_n|_- u with u the
@@ -176,12 +189,21 @@ hipError_t launch_cd(const DevView& v, const double* XP, double kappa, double* o
 hipError_t launch_to_f32(const double* x, float* y, int64_t n, hipStream_t st);
 // y = bit pattern of x rounded to bf16 (round to nearest even)
 hipError_t launch_to_bf16(const double* x, uint16_t* y, int64_t n, hipStream_t st);
+// Segmented launches.  A context may hold nseg independent problems whose
+// unknowns are nseg contiguous equal segments of every vector.  Launchers
+// that take (nseg, strides) run the same computation on each segment in one
+// launch (the segment on a grid dimension); segment s reads and writes its
+// operands offset by s times the stated stride.  nseg = 1 with zero strides
+// is the unsegmented computation.  skip (device, per segment, may be null):
+// segments flagged there are left untouched.
 // partial[b*J + j] = sum over block b's chunk of V[j]*w; J <= 128.
 hipError_t launch_multidot(const double* V, int64_t ldv, int J, const double* w,
-                           double* partial, int nblocks, int64_t n, hipStream_t st);
+                           double* partial, int nblocks, int64_t n, hipStream_t st,
+                           int nseg = 1, int64_t sv = 0, int64_t sp = 0, const int* skip = nullptr);
 // out[j] = sum_b partial[b*J + j] (fixed order)
 hipError_t launch_reduce_partials(const double* partial, int nblocks, int J,
-                                  double* out, hipStream_t st);
+                                  double* out, hipStream_t st, int nseg = 1, int64_t sp = 0,
+                                  int64_t so = 0, const int* skip = nullptr);
 // w += sign sum_j V[j] h[j] (J <= 32; no update when h is null), then block partials [nblocks][Jo] of
 // V[j] . w for j < Jd and, if self, w . w in slot Jd (Jo = Jd + self).
 hipError_t launch_axpy_dot(const double* V, int64_t ldv, int J, const double* h, double sign,
@@ -193,34 +215,48 @@ hipError_t launch_axpy_dot(const double* V, int64_t ldv, int J, const double* h,
 // w <- (w - Q b - u h) inv_sigma with ab = [a (J); b (J)] on the device.
 constexpr int GS_DELAYED_MAX = 128;
 hipError_t launch_gs_reduce(const double* Q, int64_t ldq, int J, const double* u, const double* w,
-                            double* partial, int nblocks, int64_t n, hipStream_t st);
+                            double* partial, int nblocks, int64_t n, hipStream_t st, int nseg = 1,
+                            int64_t sv = 0, int64_t sp = 0, const int* skip = nullptr);
 // The coefficients ab = [a (J); b (J)] come either from device memory (ab) or
 // from host memory (ab_host, passed by value as a kernel argument); exactly
 // one of the two is not null.  (inv_nu, h, inv_sigma) are read from sc[0..2]
-// on the device when sc is not null.
+// on the device when sc is not null.  Segmented launches read ab and sc from
+// the device (offset by s sd).
 hipError_t launch_gs_update(const double* Q, int64_t ldq, int J, const double* ab,
                             const double* ab_host, double inv_nu, double h, double inv_sigma,
-                            const double* sc, double* u, double* w, int64_t n, hipStream_t st);
+                            const double* sc, double* u, double* w, int64_t n, hipStream_t st,
+                            int nseg = 1, int64_t sv = 0, int64_t sd = 0, const int* skip = nullptr);
 // Device-side least-squares state of one GMRES(m) cycle (m <= 32), all device
 // pointers: H, R [(m+1) m] column-major; cs, sn, y [m]; g [m+1]; ab [64];
 // sc [8] = {1/nu, h, 1/sigma, beta, tol |r0|, 1/beta, |g_k|, -};
-// st [4] = {k, cycle over, finalize pending, converged}.
+// st [5] = {k, cycle over, finalize pending, converged, non-finite estimate}.
+// Segmented: segment s's doubles are offset by s sd and its st by s si;
+// skip (device, per segment, may be null) marks segments that take no part
+// in the cycle.
 struct GmDev {
   double *H, *R, *cs, *sn, *g, *y, *ab, *sc;
   int* st;
   int m;
+  int64_t sd = 0;
+  int si = 0;
+  const int* skip = nullptr;
 };
-hipError_t launch_gm_begin(const GmDev& d, const double* bb, double tol, int first, hipStream_t st);
-hipError_t launch_gm_step(const GmDev& d, int j, const double* red, hipStream_t st);
-hipError_t launch_gm_final(const GmDev& d, const double* red, hipStream_t st);
+hipError_t launch_gm_begin(const GmDev& d, const double* bb, double tol, int first, hipStream_t st,
+                           int nseg = 1, int64_t sbb = 0);
+hipError_t launch_gm_step(const GmDev& d, int j, const double* red, hipStream_t st, int nseg = 1,
+                          int64_t sred = 0);
+hipError_t launch_gm_final(const GmDev& d, const double* red, hipStream_t st, int nseg = 1,
+                           int64_t sred = 0);
 // x *= s[0]
-hipError_t launch_scal_dev(double* x, const double* s, int64_t n, hipStream_t st);
+hipError_t launch_scal_dev(double* x, const double* s, int64_t n, hipStream_t st, int nseg = 1,
+                           int64_t sx = 0, int64_t ss = 0, const int* skip = nullptr);
 // w -= sum_j V[j] h[j]
 hipError_t launch_multiaxpy(const double* V, int64_t ldv, int J, const double* h,
                             double* w, int64_t n, hipStream_t st);
-// y += sum_j V[j] c[j]  (c on device)
+// y += sum_j V[j] c[j]  (c on device; segmented: c offset by s sc)
 hipError_t launch_multiaxpy_add(const double* V, int64_t ldv, int J, const double* c,
-                                double* y, int64_t n, hipStream_t st);
+                                double* y, int64_t n, hipStream_t st, int nseg = 1, int64_t sv = 0,
+                                int64_t sc = 0, const int* skip = nullptr);
 int multidot_blocks(int64_t n);
 
 // Warm-start network (mlp.hip).  C[i][j] (ldc) = epilogue(sum_k A(i,k) B(k,j))

@@ -144,11 +144,17 @@ __device__ __forceinline__ double block_sum_tile(double (&x)[NT], double* red, i
   return s;
 }
 
-// grid (nblocks, ceil(J / 8)): block (b, y) handles vectors 8y .. 8y+7.
+// grid (nblocks, ceil(J / 8), segments): block (b, y, z) handles vectors
+// 8y .. 8y+7 of segment z (V and w offset by z sv, partial by z sp).
 __global__ void __launch_bounds__(MD_BS)
 k_multidot(const double* __restrict__ V, int64_t ldv, int J, const double* __restrict__ w,
-           double* __restrict__ partial, int64_t n, int64_t chunk) {
+           double* __restrict__ partial, int64_t n, int64_t chunk, int64_t sv, int64_t sp,
+           const int* __restrict__ skip) {
   __shared__ double red[4 * MD_TILE];
+  if (skip && skip[blockIdx.z]) return;   // a segment sitting out
+  V += blockIdx.z * sv;
+  w += blockIdx.z * sv;
+  partial += blockIdx.z * sp;
   const int b = blockIdx.x, t = threadIdx.x, j0 = blockIdx.y * MD_TILE;
   const int64_t lo = (int64_t)b * chunk;
   const int64_t hi = lo + chunk < n ? lo + chunk : n;
@@ -173,19 +179,24 @@ int multidot_blocks(int64_t n) {
 }
 
 hipError_t launch_multidot(const double* V, int64_t ldv, int J, const double* w, double* partial,
-                           int nblocks, int64_t n, hipStream_t st) {
-  if (J <= 0) return hipSuccess;
+                           int nblocks, int64_t n, hipStream_t st, int nseg, int64_t sv, int64_t sp,
+                           const int* skip) {
+  if (J <= 0 || nseg <= 0) return hipSuccess;
   const int64_t chunk = (n + nblocks - 1) / nblocks;
-  k_multidot<<<dim3(nblocks, (J + MD_TILE - 1) / MD_TILE), MD_BS, 0, st>>>(V, ldv, J, w, partial, n,
-                                                                           chunk);
+  k_multidot<<<dim3(nblocks, (J + MD_TILE - 1) / MD_TILE, nseg), MD_BS, 0, st>>>(V, ldv, J, w, partial,
+                                                                                 n, chunk, sv, sp, skip);
   return hipGetLastError();
 }
 
-// One block per output j: strided partial sums over the blocks' partials in
-// a fixed assignment, then the fixed-order block sum.
+// One block per output j (and segment y): strided partial sums over the
+// blocks' partials in a fixed assignment, then the fixed-order block sum.
 __global__ void __launch_bounds__(256)
-k_reduce_partials(const double* __restrict__ partial, int nb, int J, double* __restrict__ out) {
+k_reduce_partials(const double* __restrict__ partial, int nb, int J, double* __restrict__ out,
+                  int64_t sp, int64_t so, const int* __restrict__ skip) {
   __shared__ double red[4];
+  if (skip && skip[blockIdx.y]) return;
+  partial += blockIdx.y * sp;
+  out += blockIdx.y * so;
   const int j = blockIdx.x, t = threadIdx.x;
   double x[1] = {0.0};
   for (int b = t; b < nb; b += 256) x[0] += partial[(int64_t)b * J + j];
@@ -193,8 +204,10 @@ k_reduce_partials(const double* __restrict__ partial, int nb, int J, double* __r
   if (t == 0) out[j] = sum;
 }
 
-hipError_t launch_reduce_partials(const double* partial, int nblocks, int J, double* out, hipStream_t st) {
-  k_reduce_partials<<<J, 256, 0, st>>>(partial, nblocks, J, out);
+hipError_t launch_reduce_partials(const double* partial, int nblocks, int J, double* out, hipStream_t st,
+                                  int nseg, int64_t sp, int64_t so, const int* skip) {
+  if (nseg <= 0) return hipSuccess;
+  k_reduce_partials<<<dim3(J, nseg), 256, 0, st>>>(partial, nblocks, J, out, sp, so, skip);
   return hipGetLastError();
 }
 
@@ -276,8 +289,14 @@ hipError_t launch_axpy_dot(const double* V, int64_t ldv, int J, const double* h,
 template <int JT>
 __global__ void __launch_bounds__(MD_BS)
 k_gs_reduce(const double* __restrict__ Q, int64_t ldq, int J, const double* __restrict__ u,
-            const double* __restrict__ w, double* __restrict__ partial, int64_t n, int64_t chunk) {
+            const double* __restrict__ w, double* __restrict__ partial, int64_t n, int64_t chunk,
+            int64_t sv, int64_t sp, const int* __restrict__ skip) {
   __shared__ double red[4 * MD_TILE];
+  if (skip && skip[blockIdx.z]) return;
+  Q += blockIdx.z * sv;
+  u += blockIdx.z * sv;
+  w += blockIdx.z * sv;
+  partial += blockIdx.z * sp;
   const int b = blockIdx.x, t = threadIdx.x;
   const int jb = blockIdx.y * JT;                  // first basis vector of this tile
   const int Jt = J - jb < JT ? J - jb : JT;        // vectors in this tile (0 when J = 0)
@@ -330,12 +349,20 @@ struct GsCoef {
 };
 
 // Coefficients come from ab (device memory) when it is not null, else from cf.
+// Segment blockIdx.y: Q, u, w offset by y sv; ab and sc (device) by y sd.
 template <int JT>
 __global__ void __launch_bounds__(MD_BS)
 k_gs_update(const double* __restrict__ Q, int64_t ldq, int J, const double* __restrict__ ab,
             GsCoef<JT> cf, double inv_nu, double h, double inv_sigma, const double* __restrict__ sc,
-            double* __restrict__ u, double* __restrict__ w, int64_t n) {
+            double* __restrict__ u, double* __restrict__ w, int64_t n, int64_t sv, int64_t sd,
+            const int* __restrict__ skip) {
   __shared__ double sa[JT], sb[JT];
+  if (skip && skip[blockIdx.y]) return;
+  Q += blockIdx.y * sv;
+  u += blockIdx.y * sv;
+  w += blockIdx.y * sv;
+  if (ab) ab += blockIdx.y * sd;
+  if (sc) sc += blockIdx.y * sd;
   if (sc) {   // scalars from the device-side least-squares update
     inv_nu = sc[0];
     h = sc[1];
@@ -369,9 +396,15 @@ __global__ void __launch_bounds__(MD_BS)
 k_gs_update_wide(const double* __restrict__ Q, int64_t ldq, int J, const double* __restrict__ ab,
                  GsCoef<GS_DELAYED_MAX> cf, double inv_nu, double h, double inv_sigma,
                  const double* __restrict__ sc, double* __restrict__ u, double* __restrict__ w,
-                 int64_t n) {
+                 int64_t n, int64_t sv, int64_t sd, const int* __restrict__ skip) {
   __shared__ double sa[GS_DELAYED_MAX], sb[GS_DELAYED_MAX];
   __shared__ double spa[4][64], spb[4][64];
+  if (skip && skip[blockIdx.y]) return;
+  Q += blockIdx.y * sv;
+  u += blockIdx.y * sv;
+  w += blockIdx.y * sv;
+  if (ab) ab += blockIdx.y * sd;
+  if (sc) sc += blockIdx.y * sd;
   if (sc) {
     inv_nu = sc[0];
     h = sc[1];
@@ -420,15 +453,17 @@ k_gs_update_wide(const double* __restrict__ Q, int64_t ldq, int J, const double*
 }
 
 hipError_t launch_gs_reduce(const double* Q, int64_t ldq, int J, const double* u, const double* w,
-                            double* partial, int nblocks, int64_t n, hipStream_t st) {
+                            double* partial, int nblocks, int64_t n, hipStream_t st, int nseg,
+                            int64_t sv, int64_t sp, const int* skip) {
   if (J < 0 || J > GS_DELAYED_MAX) return hipErrorInvalidValue;
+  if (nseg <= 0) return hipSuccess;
   const int64_t chunk = (n + nblocks - 1) / nblocks;
   // Tiles of eight vectors when there are few chunks (short vectors: more
   // blocks, and a shorter block reduction per block); every output sums the
   // same terms in the same order whatever the tile width.
   const int jt = (J <= 8 || nblocks < 512) ? 8 : J <= 16 ? 16 : 32;
-  const dim3 grid((unsigned)nblocks, J == 0 ? 1u : (unsigned)((J + jt - 1) / jt));
-#define L(JT) k_gs_reduce<JT><<<grid, MD_BS, 0, st>>>(Q, ldq, J, u, w, partial, n, chunk)
+  const dim3 grid((unsigned)nblocks, J == 0 ? 1u : (unsigned)((J + jt - 1) / jt), (unsigned)nseg);
+#define L(JT) k_gs_reduce<JT><<<grid, MD_BS, 0, st>>>(Q, ldq, J, u, w, partial, n, chunk, sv, sp, skip)
   if (jt == 8) L(8);
   else if (jt == 16) L(16);
   else L(32);
@@ -446,15 +481,17 @@ static GsCoef<JT> gs_coef(const double* ab_host, int J) {
 
 hipError_t launch_gs_update(const double* Q, int64_t ldq, int J, const double* ab,
                             const double* ab_host, double inv_nu, double h, double inv_sigma,
-                            const double* sc, double* u, double* w, int64_t n, hipStream_t st) {
+                            const double* sc, double* u, double* w, int64_t n, hipStream_t st,
+                            int nseg, int64_t sv, int64_t sd, const int* skip) {
   if (J < 0 || J > GS_DELAYED_MAX) return hipErrorInvalidValue;
   if ((ab == nullptr) == (ab_host == nullptr) && J > 0) return hipErrorInvalidValue;
-  if (n == 0) return hipSuccess;
+  if (nseg > 1 && (ab_host || (!sc && J > 0))) return hipErrorInvalidValue;   // segments: device coefficients
+  if (n == 0 || nseg <= 0) return hipSuccess;
   int64_t g = (n + MD_BS - 1) / MD_BS;
   if (g > 8192) g = 8192;
-#define L(JT)                                                                                  \
-  k_gs_update<JT><<<(unsigned)g, MD_BS, 0, st>>>(Q, ldq, J, ab, gs_coef<JT>(ab_host, J), inv_nu, \
-                                                  h, inv_sigma, sc, u, w, n)
+#define L(JT)                                                                                     \
+  k_gs_update<JT><<<dim3((unsigned)g, nseg), MD_BS, 0, st>>>(Q, ldq, J, ab, gs_coef<JT>(ab_host, J), \
+                                                             inv_nu, h, inv_sigma, sc, u, w, n, sv, sd, skip)
   if (J <= 8) L(8);
   else if (J <= 16) L(16);
   else if (J <= 32) L(32);
@@ -462,16 +499,22 @@ hipError_t launch_gs_update(const double* Q, int64_t ldq, int J, const double* a
   else {
     int64_t gw = (n + 63) / 64;
     if (gw > 16384) gw = 16384;
-    k_gs_update_wide<<<(unsigned)gw, MD_BS, 0, st>>>(Q, ldq, J, ab, gs_coef<GS_DELAYED_MAX>(ab_host, J),
-                                                     inv_nu, h, inv_sigma, sc, u, w, n);
+    k_gs_update_wide<<<dim3((unsigned)gw, nseg), MD_BS, 0, st>>>(
+        Q, ldq, J, ab, gs_coef<GS_DELAYED_MAX>(ab_host, J), inv_nu, h, inv_sigma, sc, u, w, n, sv, sd, skip);
   }
   return hipGetLastError();
 }
 
-// w -= sum_j V[j] h[j]   (h on device, J <= 1024)
+// w -= sum_j V[j] h[j]   (h on device, J <= 1024); segment blockIdx.y: V and
+// w offset by y sv, h by y sh.
 __global__ void k_multiaxpy(const double* __restrict__ V, int64_t ldv, int J, const double* __restrict__ h,
-                            double* __restrict__ w, int64_t n, double sign) {
+                            double* __restrict__ w, int64_t n, double sign, int64_t sv, int64_t shs,
+                            const int* __restrict__ skip) {
   __shared__ double sh[1024];
+  if (skip && skip[blockIdx.y]) return;
+  V += blockIdx.y * sv;
+  w += blockIdx.y * sv;
+  h += blockIdx.y * shs;
   for (int j = threadIdx.x; j < J; j += blockDim.x) sh[j] = h[j];
   __syncthreads();
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -484,14 +527,14 @@ __global__ void k_multiaxpy(const double* __restrict__ V, int64_t ldv, int J, co
 hipError_t launch_multiaxpy(const double* V, int64_t ldv, int J, const double* h, double* w, int64_t n,
                             hipStream_t st) {
   if (n == 0 || J == 0) return hipSuccess;
-  k_multiaxpy<<<grid_for(n, 256), 256, 0, st>>>(V, ldv, J, h, w, n, -1.0);
+  k_multiaxpy<<<grid_for(n, 256), 256, 0, st>>>(V, ldv, J, h, w, n, -1.0, 0, 0, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_multiaxpy_add(const double* V, int64_t ldv, int J, const double* c, double* y, int64_t n,
-                                hipStream_t st) {
-  if (n == 0 || J == 0) return hipSuccess;
-  k_multiaxpy<<<grid_for(n, 256), 256, 0, st>>>(V, ldv, J, c, y, n, 1.0);
+                                hipStream_t st, int nseg, int64_t sv, int64_t sc, const int* skip) {
+  if (n == 0 || J == 0 || nseg <= 0) return hipSuccess;
+  k_multiaxpy<<<dim3(grid_for(n, 256), nseg), 256, 0, st>>>(V, ldv, J, c, y, n, 1.0, sv, sc, skip);
   return hipGetLastError();
 }
 
@@ -528,12 +571,32 @@ __device__ void gm_silence(const GmDev& d, int j) {   // updates that leave u, w
   d.sc[0] = d.sc[1] = d.sc[2] = 0.0;
 }
 
+// State of segment s (block s of a segmented launch).
+__device__ GmDev gm_seg(GmDev d, int s) {
+  const int64_t o = s * d.sd;
+  d.H += o;
+  d.R += o;
+  d.cs += o;
+  d.sn += o;
+  d.g += o;
+  d.y += o;
+  d.ab += o;
+  d.sc += o;
+  d.st += (int64_t)s * d.si;
+  return d;
+}
+
 }  // namespace
 
 // Cycle start: bb[0] = |r|^2 of the cycle's residual r (already in slot 0).
-// first != 0 fixes the absolute tolerance tol |r| for the whole solve.
-__global__ void k_gm_begin(GmDev d, const double* __restrict__ bb, double tol, int first) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// first != 0 fixes the absolute tolerance tol |r| for the whole solve.  One
+// block per segment (bb offset by s sbb); a segment flagged in d.skip takes
+// no part in the cycle (it ends at once with zero updates).
+__global__ void k_gm_begin(GmDev d0, const double* __restrict__ bb, double tol, int first, int64_t sbb) {
+  if (threadIdx.x != 0) return;
+  const GmDev d = gm_seg(d0, blockIdx.x);
+  bb += blockIdx.x * sbb;
+  const bool skip = d0.skip && d0.skip[blockIdx.x];
   const int ld = d.m + 1;
   const double beta = sqrt(fmax(bb[0], 0.0));
   if (first) d.sc[4] = tol * beta;
@@ -542,18 +605,22 @@ __global__ void k_gm_begin(GmDev d, const double* __restrict__ bb, double tol, i
   for (int i = 0; i < d.m; ++i) d.y[i] = 0.0;
   d.g[0] = beta;
   d.sc[3] = beta;
-  d.sc[5] = beta > 0 ? 1.0 / beta : 0.0;
-  const int conv = !(beta > d.sc[4]) || !isfinite(beta);
+  d.sc[5] = (beta > 0 && !skip) ? 1.0 / beta : 0.0;
+  const int conv = !(beta > d.sc[4]) || !isfinite(beta) || skip;
   d.st[0] = 0;
   d.st[1] = conv;
   d.st[2] = 0;
   d.st[3] = conv;
+  d.st[4] = 0;
   if (conv) gm_silence(d, 0);
 }
 
-// Step j after the reduction red = [Q^T u (j); Q^T w (j); u.u; u.w; w.w].
-__global__ void k_gm_step(GmDev d, int j, const double* __restrict__ red) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Step j after the reduction red = [Q^T u (j); Q^T w (j); u.u; u.w; w.w]
+// (one block per segment, red offset by s sred).
+__global__ void k_gm_step(GmDev d0, int j, const double* __restrict__ red, int64_t sred) {
+  if (threadIdx.x != 0) return;
+  const GmDev d = gm_seg(d0, blockIdx.x);
+  red += blockIdx.x * sred;
   if (d.st[1]) {
     gm_silence(d, j);
     return;
@@ -620,9 +687,11 @@ __global__ void k_gm_step(GmDev d, int j, const double* __restrict__ red) {
 
 // After the last step: red = [Q^T u_m (m); ...; u_m.u_m at 2m] finalizes
 // column m-1 (unless the cycle ended earlier); then R y = g over the k
-// committed columns, y zero beyond k.
-__global__ void k_gm_final(GmDev d, const double* __restrict__ red) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// committed columns, y zero beyond k (one block per segment).
+__global__ void k_gm_final(GmDev d0, const double* __restrict__ red, int64_t sred) {
+  if (threadIdx.x != 0) return;
+  const GmDev d = gm_seg(d0, blockIdx.x);
+  red += blockIdx.x * sred;
   const int ld = d.m + 1, m = d.m;
   if (!d.st[1]) {
     double a2 = 0.0;
@@ -648,30 +717,39 @@ __global__ void k_gm_final(GmDev d, const double* __restrict__ red) {
     d.y[i] = s / d.R[(int64_t)i * ld + i];
   }
   d.sc[6] = fabs(d.g[k]);   // least-squares residual estimate of the cycle
+  d.st[4] = !isfinite(d.sc[6]);
 }
 
-// x *= s[0] (device scalar)
-__global__ void k_scal_dev(double* __restrict__ x, const double* __restrict__ s, int64_t n) {
-  const double a = s[0];
+// x *= s[0] (device scalar); segment blockIdx.y: x offset by y sx, s by y ss
+__global__ void k_scal_dev(double* __restrict__ x, const double* __restrict__ s, int64_t n, int64_t sx,
+                           int64_t ss, const int* __restrict__ skip) {
+  if (skip && skip[blockIdx.y]) return;
+  x += blockIdx.y * sx;
+  const double a = s[blockIdx.y * ss];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] *= a;
 }
 
-hipError_t launch_gm_begin(const GmDev& d, const double* bb, double tol, int first, hipStream_t st) {
-  k_gm_begin<<<1, 64, 0, st>>>(d, bb, tol, first);
+hipError_t launch_gm_begin(const GmDev& d, const double* bb, double tol, int first, hipStream_t st,
+                           int nseg, int64_t sbb) {
+  if (nseg <= 0) return hipSuccess;
+  k_gm_begin<<<nseg, 64, 0, st>>>(d, bb, tol, first, sbb);
   return hipGetLastError();
 }
-hipError_t launch_gm_step(const GmDev& d, int j, const double* red, hipStream_t st) {
+hipError_t launch_gm_step(const GmDev& d, int j, const double* red, hipStream_t st, int nseg, int64_t sred) {
   if (j < 0 || j >= d.m || d.m > 32) return hipErrorInvalidValue;
-  k_gm_step<<<1, 64, 0, st>>>(d, j, red);
+  if (nseg <= 0) return hipSuccess;
+  k_gm_step<<<nseg, 64, 0, st>>>(d, j, red, sred);
   return hipGetLastError();
 }
-hipError_t launch_gm_final(const GmDev& d, const double* red, hipStream_t st) {
-  k_gm_final<<<1, 64, 0, st>>>(d, red);
+hipError_t launch_gm_final(const GmDev& d, const double* red, hipStream_t st, int nseg, int64_t sred) {
+  if (nseg <= 0) return hipSuccess;
+  k_gm_final<<<nseg, 64, 0, st>>>(d, red, sred);
   return hipGetLastError();
 }
-hipError_t launch_scal_dev(double* x, const double* s, int64_t n, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  k_scal_dev<<<grid_for(n, 256), 256, 0, st>>>(x, s, n);
+hipError_t launch_scal_dev(double* x, const double* s, int64_t n, hipStream_t st, int nseg, int64_t sx,
+                           int64_t ss, const int* skip) {
+  if (n == 0 || nseg <= 0) return hipSuccess;
+  k_scal_dev<<<dim3(grid_for(n, 256), nseg), 256, 0, st>>>(x, s, n, sx, ss, skip);
   return hipGetLastError();
 }
 

@@ -58,6 +58,10 @@ def test_extension_entry_points_reject_bad_arguments_without_gpu():
     assert lib.tsgls_solve_batch(None, None, 2, None, None, None, 0) == -1
     lib.tsgls_set_tracer.argtypes = [P, P, ctypes.c_double, ctypes.c_int]
     assert lib.tsgls_set_tracer(None, None, 1.0, 1) == -1
+    lib.tsgls_set_segments.argtypes = [P, ctypes.c_int]
+    assert lib.tsgls_set_segments(None, 2) == -1
+    lib.tsgls_solve_segments.argtypes = [P, P, P, P, P]
+    assert lib.tsgls_solve_segments(None, None, None, None, None) == -1
     lib.tsgls_jv_prec.argtypes = [P, P, P, ctypes.c_int, ctypes.c_double, ctypes.c_int]
     assert lib.tsgls_jv_prec(None, None, None, 0, 0.0, 0) == -1
     lib.tsgls_rb_greedy.argtypes = [P, ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int, P, P, P]
