@@ -590,19 +590,22 @@ __device__ GmDev gm_seg(GmDev d, int s) {
 
 // Cycle start: bb[0] = |r|^2 of the cycle's residual r (already in slot 0).
 // first != 0 fixes the absolute tolerance tol |r| for the whole solve.  One
-// block per segment (bb offset by s sbb); a segment flagged in d.skip takes
-// no part in the cycle (it ends at once with zero updates).
-__global__ void k_gm_begin(GmDev d0, const double* __restrict__ bb, double tol, int first, int64_t sbb) {
-  if (threadIdx.x != 0) return;
+// block (one wave) per segment (bb offset by s sbb); a segment flagged in
+// d.skip takes no part in the cycle (it ends at once with zero updates).
+__global__ void __launch_bounds__(64)
+k_gm_begin(GmDev d0, const double* __restrict__ bb, double tol, int first, int64_t sbb) {
+  const int lane = threadIdx.x;
   const GmDev d = gm_seg(d0, blockIdx.x);
   bb += blockIdx.x * sbb;
   const bool skip = d0.skip && d0.skip[blockIdx.x];
   const int ld = d.m + 1;
+  for (int i = lane; i < ld * d.m; i += 64) d.H[i] = d.R[i] = 0.0;
+  for (int i = lane; i <= d.m; i += 64) d.g[i] = 0.0;
+  for (int i = lane; i < d.m; i += 64) d.y[i] = 0.0;
+  __syncthreads();
+  if (lane != 0) return;
   const double beta = sqrt(fmax(bb[0], 0.0));
   if (first) d.sc[4] = tol * beta;
-  for (int i = 0; i < ld * d.m; ++i) d.H[i] = d.R[i] = 0.0;
-  for (int i = 0; i <= d.m; ++i) d.g[i] = 0.0;
-  for (int i = 0; i < d.m; ++i) d.y[i] = 0.0;
   d.g[0] = beta;
   d.sc[3] = beta;
   d.sc[5] = (beta > 0 && !skip) ? 1.0 / beta : 0.0;
@@ -616,20 +619,30 @@ __global__ void k_gm_begin(GmDev d0, const double* __restrict__ bb, double tol, 
 }
 
 // Step j after the reduction red = [Q^T u (j); Q^T w (j); u.u; u.w; w.w]
-// (one block per segment, red offset by s sred).
-__global__ void k_gm_step(GmDev d0, int j, const double* __restrict__ red, int64_t sred) {
-  if (threadIdx.x != 0) return;
+// (one wave per segment, red offset by s sred).  The rows of the new
+// Hessenberg column are formed by the lanes in parallel, each with the
+// sequential sum of the one-thread form; the Givens rotations stay on lane 0.
+__global__ void __launch_bounds__(64)
+k_gm_step(GmDev d0, int j, const double* __restrict__ red, int64_t sred) {
+  const int lane = threadIdx.x;
   const GmDev d = gm_seg(d0, blockIdx.x);
   red += blockIdx.x * sred;
+  __shared__ double sr[2 * 32 + 3];
+  auto silence = [&]() {
+    for (int i = lane; i < 2 * j; i += 64) d.ab[i] = 0.0;
+    if (lane == 0) d.sc[0] = d.sc[1] = d.sc[2] = 0.0;
+  };
   if (d.st[1]) {
-    gm_silence(d, j);
+    silence();
     return;
   }
+  for (int i = lane; i < 2 * j + 3; i += 64) sr[i] = red[i];
+  __syncthreads();
   const int ld = d.m + 1;
-  const double* a = red;
-  const double* bq = red + j;
-  const double uu = red[2 * j], uw = red[2 * j + 1], ww = red[2 * j + 2];
-  double aa = 0.0, abq = 0.0, bbq = 0.0;
+  const double* a = sr;
+  const double* bq = sr + j;
+  const double uu = sr[2 * j], uw = sr[2 * j + 1], ww = sr[2 * j + 2];
+  double aa = 0.0, abq = 0.0, bbq = 0.0;   // the same on every lane
   for (int i = 0; i < j; ++i) {
     aa += a[i] * a[i];
     abq += a[i] * bq[i];
@@ -639,34 +652,47 @@ __global__ void k_gm_step(GmDev d0, int j, const double* __restrict__ red, int64
   auto H = [&](int i, int c) -> double& { return d.H[(int64_t)c * ld + i]; };
   if (j >= 1) {          // column j-1 for u_j = Q a + nu q_j; now final
     const double sj = H(j, j - 1);
-    for (int i = 0; i < j; ++i) H(i, j - 1) += sj * a[i];
-    H(j, j - 1) = sj * nu;
-    gm_commit(d, j - 1);
-    d.st[0] = j;
+    __syncthreads();     // every lane has read H(j, j-1) before lane 0 rewrites it
+    for (int i = lane; i < j; i += 64) H(i, j - 1) += sj * a[i];
+    if (lane == 0) H(j, j - 1) = sj * nu;
+    __syncthreads();
+    if (lane == 0) {
+      gm_commit(d, j - 1);
+      d.st[0] = j;
+    }
+    __syncthreads();
   }
   if (d.st[2] || !(nu > 0.0) || !isfinite(uu) || !isfinite(ww)) {
-    d.st[1] = 1;          // converged last step, or u_j in span(Q): the cycle ends here
-    d.st[3] = fabs(d.g[d.st[0]]) <= d.sc[4];
-    gm_silence(d, j);
+    // converged last step, or u_j in span(Q): the cycle ends here
+    __syncthreads();     // every lane has read st[2] before lane 0 changes st
+    if (lane == 0) {
+      d.st[1] = 1;
+      d.st[3] = fabs(d.g[d.st[0]]) <= d.sc[4];
+    }
+    silence();
     return;
   }
-  // provisional column j: A q_j = (w - A Q a) / nu, A Q a = Q (H a)
+  // provisional column j: A q_j = (w - A Q a) / nu, A Q a = Q (H a); lane i, row i
   const double hj = (uw - abq) / nu;
-  for (int i = 0; i <= j; ++i) {
+  for (int i = lane; i <= j; i += 64) {
     double ha = 0.0;
     for (int l = (i > 0 ? i - 1 : 0); l < j; ++l) ha += H(i, l) * a[l];
     H(i, j) = ((i < j ? bq[i] : hj) - ha) / nu;
   }
   const double s2 = ww - bbq - hj * hj;
   const double sigma = sqrt(fmax(s2, 1e-30 * ww));
-  H(j + 1, j) = sigma / nu;
-  for (int i = 0; i < j; ++i) {
+  if (lane == 0) H(j + 1, j) = sigma / nu;
+  for (int i = lane; i < j; i += 64) {
     d.ab[i] = a[i];
     d.ab[j + i] = bq[i];
   }
-  d.sc[0] = 1.0 / nu;
-  d.sc[1] = hj;
-  d.sc[2] = 1.0 / sigma;
+  if (lane == 0) {
+    d.sc[0] = 1.0 / nu;
+    d.sc[1] = hj;
+    d.sc[2] = 1.0 / sigma;
+  }
+  __syncthreads();       // column j complete
+  if (lane != 0) return;
   // provisional least-squares residual with column j as it stands
   double c0 = 0.0, c1 = 0.0;
   {
