@@ -456,6 +456,37 @@ def batched_run(N, concurrency=8, graph=False):
     return out
 
 
+def lockstep_one_k(N, K):
+    """N pipe waveforms (6,144 tets) of one harmonic count K, seeded as in
+    batched_run, solved to 1e-8 as the segments of one context (no other
+    leg: the workload of the lockstep kernel profile)."""
+    import numpy as np
+    import torch
+    import paper_2311_09465_amd as T
+    from workloads import womersley_problem, initial_guess
+    from workloads.problems import inlet_waveforms
+    from workloads.meshgen import pipe
+    rng = np.random.default_rng(7)
+    mesh = pipe(4, 16)
+    amps = rng.uniform(0.1, 1.0, size=N)
+    probs = [womersley_problem(K=K, mesh=mesh, waveform=inlet_waveforms(K, 500 + i, amps[i], n_inlets=1)[0])
+             for i in range(N)]
+    seg = T.SegmentSolver.from_problems(probs)
+    y = torch.from_numpy(np.concatenate([initial_guess(p) for p in probs])).cuda()
+    torch.cuda.synchronize()
+    opts = dict(rtol=1e-8, lin_rtol=0.05, restart=30, max_newton=40)
+    t0 = time.perf_counter()
+    rc, stats, fin = seg.solve_segments(y, **opts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    seg.close()
+    return dict(workload=f"womersley_6k_K{K}_lockstep{N}", n_solves=N, wall_s=round(wall, 3),
+                solves_per_s=round(N / wall, 3), converged=int(sum(s_["status"] == 0 for s_ in stats)),
+                products=int(sum(s_["matvecs"] for s_ in stats)),
+                latency_p50_s=round(float(np.percentile(fin, 50)), 4),
+                latency_p99_s=round(float(np.percentile(fin, 99)), 4), solver=opts)
+
+
 def lockstep_run(probs, Ks, opts):
     """The same problems solved as segments: one context per harmonic count
     holding all of that count's waveforms (tsgls_solve_segments, graph-
@@ -999,6 +1030,10 @@ def main():
     ap.add_argument("--batch-concurrency", type=int, default=8)
     ap.add_argument("--batch-graph", action="store_true",
                     help="batched solves with graph-captured GMRES cycles")
+    ap.add_argument("--lockstep", type=int, default=0, metavar="N",
+                    help="lockstep measurement only: N pipe waveforms of one harmonic count "
+                         "(--lockstep-k) as the segments of one context")
+    ap.add_argument("--lockstep-k", type=int, default=7)
     ap.add_argument("--dt-sweep", type=int, default=0, metavar="MAX_NEWTON",
                     help="pseudo-time step sweep (junction runs MAX_NEWTON Newton steps)")
     ap.add_argument("--tracer", action="store_true",
@@ -1038,6 +1073,9 @@ def main():
         return
     if args.batched:
         batched(args)
+        return
+    if args.lockstep:
+        print(json.dumps(lockstep_one_k(args.lockstep, args.lockstep_k)), flush=True)
         return
     if args.learned:
         learned(args)

@@ -90,7 +90,7 @@ __device__ __forceinline__ float swap_pair(float x) {
 // (the launch repeated inside GMRES) fits three without spilling in FP64,
 // four in FP32.
 template <int MODE, typename T>
-constexpr int op_waves() { return (MODE & ~MODE_TAU16) == 0 ? (sizeof(T) == 4 ? 4 : 3) : 1; }
+constexpr int op_waves() { return (MODE & ~(MODE_TAU16 | MODE_SEG)) == 0 ? (sizeof(T) == 4 ? 4 : 3) : 1; }
 
 // bf16 bit pattern -> FP32 (bf16 is the top half of an FP32 word)
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -240,7 +240,21 @@ k_op(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
     for (int i = lane; i < 16 * RP; i += 64) sZf[i] = 0.0;
   __syncthreads();
 
-  // ---- contiguous element range of this block's XCD
+  // ---- contiguous element range of this block's XCD.  With a work list
+  // (segmented context) the range runs over the positions of the listed
+  // segments' elements only: position p is element list[p / elems] * elems
+  // + p % elems.
+  constexpr bool SEG = (MODE & MODE_SEG) != 0;
+  const bool listed = SEG && v.seg.list != nullptr;
+  if (listed) {
+    begin = 0;
+    end = (int64_t)v.seg.count[0] * v.seg.elems;
+  }
+  auto elem = [&](int64_t p) -> int64_t {
+    if (!listed) return p;
+    const uint32_t q = (uint32_t)p / (uint32_t)v.seg.elems;
+    return (int64_t)v.seg.list[q] * v.seg.elems + (p - (int64_t)q * v.seg.elems);
+  };
   const int64_t nbx = gridDim.x >> 3, xcd = blockIdx.x & 7, jx = blockIdx.x >> 3;
   const int64_t cnt = end - begin;
   const int64_t lo = begin + cnt * xcd / 8, hi = begin + cnt * (xcd + 1) / 8;
@@ -256,9 +270,10 @@ k_op(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
       for (int j = 0; j < NTL; ++j)
         tv[q][j] = tok[j] ? TR::load(v, TAU, (en * 4 + q) * P + lane + 64 * j) : typename TR::type(0);
   };
-  if (lo + jx < hi) load_tau(lo + jx);
+  if (lo + jx < hi) load_tau(elem(lo + jx));
 
-  for (int64_t e = lo + jx; e < hi; e += nbx) {
+  for (int64_t pe = lo + jx; pe < hi; pe += nbx) {
+    const int64_t e = elem(pe);
     int nd[4];
     T dN[4][3];
 #pragma unroll
@@ -266,11 +281,6 @@ k_op(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
       nd[b] = v.conn[e * 4 + b];
 #pragma unroll
       for (int j = 0; j < 3; ++j) dN[b][j] = v.geo[e * 16 + b * 3 + j];
-    }
-    if (v.seg.skip && v.seg.skip[(uint32_t)nd[0] / (uint32_t)v.seg.nodes]) {
-      // the element's segment sits out this pass: only the next tau block moves in
-      if (e + nbx < hi) load_tau(e + nbx);
-      continue;
     }
     const T wgt = v.geo[e * 16 + 12];
 
@@ -359,7 +369,7 @@ k_op(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
         const int fp = pt * 64 + lane;   // field * PW + position within the node's block
         sV[(b * 4 + fp / PW) * RP + fp % PW] = xv[b][pt];
       }
-    if (e + nbx < hi) load_tau(e + nbx);
+    if (pe + nbx < hi) load_tau(elem(pe + nbx));
     __syncthreads();
 
     // ---- conv(t) -> modes: lane (q = g, p), reg i
@@ -990,9 +1000,22 @@ static hipError_t op_launch(const DevView& v, const OpArgs<T>& a, double shift, 
   return hipGetLastError();
 }
 
+// With a work list of segments (v.seg.list set) the MODE_SEG instantiations
+// run over the listed segments' elements, so that the plain kernels carry
+// none of that logic; otherwise (and for a mode without one) the plain
+// kernel computes every element, and the node gather still writes zero rows
+// for segments sitting out.
 template <int K>
 static hipError_t op_dispatch(const DevView& v, int mode, const OpArgs<double>& a, double shift,
                               int64_t begin, int64_t end, hipStream_t st) {
+  if (v.seg.list) {
+    switch (mode) {
+#define CASE(md) case md: return op_launch<K, md | MODE_SEG>(v, a, shift, begin, end, st);
+      CASE(MODE_RESID | MODE_STOREZ) CASE(0) CASE(MODE_NOLS) CASE(MODE_NEWTON)
+#undef CASE
+      default: break;
+    }
+  }
   switch (mode) {
     case MODE_RESID: return op_launch<K, MODE_RESID>(v, a, shift, begin, end, st);
     case MODE_RESID | MODE_STOREZ: return op_launch<K, MODE_RESID | MODE_STOREZ>(v, a, shift, begin, end, st);
@@ -1007,6 +1030,14 @@ static hipError_t op_dispatch(const DevView& v, int mode, const OpArgs<double>& 
 template <int K>
 static hipError_t op_dispatch(const DevView& v, int mode, const OpArgs<float>& a, double shift,
                               int64_t begin, int64_t end, hipStream_t st) {
+  if (v.seg.list) {
+    switch (mode) {
+#define CASE(md) case md: return op_launch<K, md | MODE_SEG>(v, a, shift, begin, end, st);
+      CASE(0) CASE(MODE_NOLS) CASE(MODE_NEWTON)
+#undef CASE
+      default: break;
+    }
+  }
   switch (mode) {
 #define CASE(md) case md: return op_launch<K, md>(v, a, shift, begin, end, st);
     CASE(0) CASE(MODE_NOLS) CASE(MODE_NEWTON)

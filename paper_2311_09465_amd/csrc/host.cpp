@@ -105,7 +105,10 @@ struct tsgls_ctx {
   double* segred = nullptr;
   double* segpart = nullptr;
   double* segnrm = nullptr;
-  int* hseg = nullptr;          // [nseg][8] status, [nseg] skip flags
+  int* hseg = nullptr;          // [nseg][8] status, then the mask: [nseg] skip flags,
+                                // [nseg] list of the segments taking part, their count
+  int32_t seg_elems = 0;        // elements per segment when all segments have the same
+                                // number (then stored segment-major), else 0
   double* hsegd = nullptr;      // [nseg] norms, [nseg] tolerances
   // FP32 copies of the linearization for the mixed-precision tangent
   // (allocated on first use; the FP32 modes, samples and element rows reuse
@@ -222,6 +225,11 @@ DevView view(const tsgls_ctx* c) {
   if (c->seg_mask_on && c->nseg > 1 && c->gm.skip) {
     v.seg.skip = c->gm.skip;
     v.seg.nodes = (int32_t)(c->nn / c->nseg);
+    if (c->seg_elems > 0) {
+      v.seg.list = c->gm.skip + c->nseg;
+      v.seg.count = c->gm.skip + 2 * c->nseg;
+      v.seg.elems = c->seg_elems;
+    }
   }
   return v;
 }
@@ -722,11 +730,11 @@ int ensure_gm(tsgls_ctx* c) {
   const int S = c->nseg;
   const int64_t L = ndof(c) / S;
   const int nb = multidot_blocks(L);
-  CHK(dalloc(c, &c->gmbuf, (size_t)S * GM_SEGD + ((size_t)S * (GM_ST + 1) + 1) / 2 + 16));
+  CHK(dalloc(c, &c->gmbuf, (size_t)S * GM_SEGD + ((size_t)S * (GM_ST + 2) + 2) / 2 + 16));
   CHK(dalloc(c, &c->segred, (size_t)S * GM_RED));
   CHK(dalloc(c, &c->segpart, (size_t)S * nb * 67));
   CHK(dalloc(c, &c->segnrm, (size_t)S));
-  HIPCHK(c, hipHostMalloc((void**)&c->hseg, (size_t)S * (GM_ST + 1) * sizeof(int), hipHostMallocDefault));
+  HIPCHK(c, hipHostMalloc((void**)&c->hseg, ((size_t)S * (GM_ST + 2) + 1) * sizeof(int), hipHostMallocDefault));
   HIPCHK(c, hipHostMalloc((void**)&c->hsegd, (size_t)2 * S * sizeof(double), hipHostMallocDefault));
   const int ld = 33;
   double* p = c->gmbuf;
@@ -742,9 +750,27 @@ int ensure_gm(tsgls_ctx* c) {
   c->gm.sd = GM_SEGD;
   c->gm.si = GM_ST;
   c->gm.skip = c->gm.st + (size_t)S * GM_ST;
-  std::fill(c->hseg, c->hseg + (size_t)S * (GM_ST + 1), 0);
-  HIPCHK(c, hipMemcpyAsync(c->gm.st, c->hseg, (size_t)S * (GM_ST + 1) * sizeof(int), hipMemcpyHostToDevice, c->st));
+  std::fill(c->hseg, c->hseg + (size_t)S * (GM_ST + 2) + 1, 0);
+  HIPCHK(c, hipMemcpyAsync(c->gm.st, c->hseg, ((size_t)S * (GM_ST + 2) + 1) * sizeof(int), hipMemcpyHostToDevice,
+                           c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
+  return TSGLS_OK;
+}
+
+// Copy the skip flags staged at hseg + nseg * GM_ST to the device, with the
+// list of the segments taking part and its length (one copy).  The caller
+// has synchronized since the staging area was last copied.
+int write_mask(tsgls_ctx* c) {
+  const int S = c->nseg;
+  int* skip = c->hseg + (size_t)S * GM_ST;
+  int* list = skip + S;
+  int n = 0;
+  for (int s = 0; s < S; ++s)
+    if (!skip[s]) list[n++] = s;
+  for (int s = n; s < S; ++s) list[s] = 0;
+  list[S] = n;
+  HIPCHK(c, hipMemcpyAsync(const_cast<int*>(c->gm.skip), skip, (2 * (size_t)S + 1) * sizeof(int),
+                           hipMemcpyHostToDevice, c->st));
   return TSGLS_OK;
 }
 
@@ -893,7 +919,7 @@ int gmres_graph(tsgls_ctx* c, const double* b, double* x, double tol, int m, int
   for (int s = 0; s < S; ++s)
     HIPCHK(c, hipMemcpyAsync(c->gm.sc + (size_t)s * GM_SEGD + 4, c->hsegd + S + s, sizeof(double),
                              hipMemcpyHostToDevice, c->st));
-  HIPCHK(c, hipMemcpyAsync(const_cast<int*>(c->gm.skip), skip, S * sizeof(int), hipMemcpyHostToDevice, c->st));
+  CHK(write_mask(c));
   bool first = true;
   while (nact > 0) {
     double* V0 = c->V;
@@ -927,8 +953,7 @@ int gmres_graph(tsgls_ctx* c, const double* b, double* x, double tol, int m, int
         changed = true;
       }
     }
-    if (changed && nact > 0)
-      HIPCHK(c, hipMemcpyAsync(const_cast<int*>(c->gm.skip), skip, S * sizeof(int), hipMemcpyHostToDevice, c->st));
+    if (changed && nact > 0) CHK(write_mask(c));
   }
   return TSGLS_OK;
 }
@@ -1065,7 +1090,7 @@ int gmres(tsgls_ctx* c, const double* b, double* x, double tol, int m, int maxmv
 // Processing order: Morton order of the element centroids (locality of the
 // node gathers; contributions are summed per node afterwards in a fixed
 // order).  Returns processing position -> input element.
-std::vector<int32_t> morton_perm(const double* xyz, int64_t n_nodes, const int32_t* tets, int64_t n_tets) {
+std::vector<uint64_t> morton_keys(const double* xyz, int64_t n_nodes, const int32_t* tets, int64_t n_tets) {
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int64_t i = 0; i < n_nodes; ++i)
     for (int d = 0; d < 3; ++d) {
@@ -1080,6 +1105,11 @@ std::vector<int32_t> morton_perm(const double* xyz, int64_t n_nodes, const int32
     for (int d = 0; d < 3; ++d) cc[d] = (cc[d] - lo[d]) / std::max(hi[d] - lo[d], 1e-300);
     key[e] = morton3(cc[0], cc[1], cc[2]);
   }
+  return key;
+}
+
+std::vector<int32_t> morton_perm(const double* xyz, int64_t n_nodes, const int32_t* tets, int64_t n_tets) {
+  const std::vector<uint64_t> key = morton_keys(xyz, n_nodes, tets, n_tets);
   std::vector<int32_t> perm(n_tets);
   for (int64_t e = 0; e < n_tets; ++e) perm[e] = (int32_t)e;
   std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
@@ -1557,13 +1587,50 @@ int tsgls_set_segments(tsgls_ctx* c, int nseg) {
     c->seg_checked = false;
     return rc;
   }
-  // The element order stays the Morton order of the whole mesh: copies of
-  // one mesh interleave element by element, so every XCD's range and every
-  // wave's elements spread over all segments, and segments that sit out
-  // thin the work evenly.  Within a segment the relative order is that of
-  // its mesh alone (stable sort on equal keys), so sums over a node's
-  // elements run in the same order.
-  return TSGLS_OK;
+  // Element order.  Within a segment it is always that of its mesh alone
+  // (Morton key, then input order), so sums over a node's elements run in
+  // the same order as for the lone problem.  Segments of equal element
+  // counts are stored segment-major, and the element operator runs over the
+  // elements of the segments taking part only (a list on the device).
+  // Otherwise the whole mesh is in Morton order with copies of equal keys
+  // ordered by a segment index rotated by a hash of the key: a wave of the
+  // element kernel takes every nbx-th element, and with copy s at a fixed
+  // offset in every group of nseg it would meet a single segment whenever
+  // nbx is a multiple of nseg, leaving whole waves idle while others do
+  // their full share when segments sit out.
+  std::vector<int32_t> conn((size_t)c->E * 4), tin((size_t)c->E * 4);
+  HIPCHK(c, hipMemcpy(conn.data(), c->conn, conn.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int64_t e = 0; e < c->E; ++e)
+    for (int b = 0; b < 4; ++b) tin[(size_t)c->perm[e] * 4 + b] = conn[(size_t)e * 4 + b];
+  const std::vector<uint64_t> key = morton_keys(c->hxyz.data(), c->nn, tin.data(), c->E);
+  std::vector<int32_t> perm(c->E);
+  for (int64_t e = 0; e < c->E; ++e) perm[e] = (int32_t)e;
+  c->seg_elems = 0;
+  std::vector<int64_t> per(nseg, 0);
+  const int64_t Ln = c->nn / nseg;
+  for (int64_t e = 0; e < c->E; ++e) ++per[tin[(size_t)e * 4] / Ln];
+  const bool equal = nseg > 1 && std::all_of(per.begin(), per.end(), [&](int64_t k) { return k == per[0]; });
+  if (equal) {
+    // segment-major: segment s owns positions [s E/nseg, (s+1) E/nseg), Morton
+    // order inside; the element operator then runs over a list of the
+    // segments taking part
+    c->seg_elems = (int32_t)per[0];
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
+      const int64_t sa = tin[(size_t)a * 4] / Ln, sb = tin[(size_t)b * 4] / Ln;
+      return sa != sb ? sa < sb : key[a] < key[b];
+    });
+  } else if (nseg > 1) {
+    auto rot = [&](int32_t e) {
+      const uint64_t h = (key[e] * 0x9E3779B97F4A7C15ull) >> 32;
+      return (uint64_t)(tin[(size_t)e * 4] / Ln + h) % (uint64_t)nseg;
+    };
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
+      return key[a] != key[b] ? key[a] < key[b] : rot(a) < rot(b);
+    });
+  } else {
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+  }
+  return set_order(c, tin.data(), perm);
 }
 
 int tsgls_solve_segments(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsgls_solve_stats* stats,
@@ -1597,8 +1664,7 @@ int tsgls_solve_segments(tsgls_ctx* c, double* y, const tsgls_solve_opts* o, tsg
   auto write_skip = [&]() -> int {
     int* skip = c->hseg + (size_t)S * GM_ST;
     for (int s = 0; s < S; ++s) skip[s] = frozen[s];
-    HIPCHK(c, hipMemcpyAsync(const_cast<int*>(c->gm.skip), skip, S * sizeof(int), hipMemcpyHostToDevice, c->st));
-    return TSGLS_OK;
+    return write_mask(c);
   };
   CHK(write_skip());
   c->tauV_ok = false;   // the first tau starts cold, as in tsgls_solve

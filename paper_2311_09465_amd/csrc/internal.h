@@ -41,16 +41,25 @@ enum : int {
   MODE_NOLS = 4,     // drop least-squares terms of G_i and D_i
   MODE_STOREZ = 8,   // store z = tau L(u) (modal) during a residual pass
   MODE_TAU16 = 16,   // FP32 operator with tau read as bf16 (v.tau16)
+  MODE_SEG = 32,     // element operator over the work list of segments in v.seg
 };
 
 // Device view of one mesh + linearization.  All pointers are device memory.
 // Segments that sit out a pass (segmented contexts): skip[s] != 0 for the
-// segment of node blocks [s nodes, (s+1) nodes).  The element kernels of the
-// small harmonic counts leave such a segment's elements untouched, and the
-// node gather writes zero rows for its nodes.  skip == nullptr: none.
+// segment of node blocks [s nodes, (s+1) nodes).  tau (small harmonic
+// counts) leaves such a segment's points untouched, the nodal-sample kernel
+// its nodes, and the node gather writes zero rows for its nodes.  skip ==
+// nullptr: none.  When the segments' elements are contiguous blocks of
+// `elems` (segment s owns processing positions [s elems, (s+1) elems)),
+// list / count (device) hold the segments taking part, and the element
+// operator's launch runs over their elements only (its range is count *
+// elems positions); without a list it computes every element.
 struct SegMask {
   const int* skip = nullptr;
   int32_t nodes = 1;
+  const int* list = nullptr;
+  const int* count = nullptr;
+  int32_t elems = 0;
 };
 
 struct DevView {
