@@ -278,9 +278,12 @@ int tsgls_solve(tsgls_ctx* ctx, double* y, const tsgls_solve_opts* opts,
  * Typically the caller repeats one mesh nseg times with the node numbers
  * offset, and gives each copy its own Dirichlet values.  TSGLS_EINVAL if
  * nseg < 1, nseg does not divide n_nodes, an element joins two blocks, or
- * the context is in tracer mode.  nseg = 1 undoes it.  Residual, tangent,
- * linearize and the Jacobi diagonal act on all segments at once as on any
- * context (they are local to elements and nodes). */
+ * the context is in tracer mode.  nseg = 1 undoes it.  The elements are
+ * put in a new processing order (segment by segment when all segments have
+ * as many elements, each in its own Morton order), which invalidates the
+ * linearization (TSGLS_ESTATE from tsgls_jv until the next linearize).
+ * Residual, tangent, linearize and the Jacobi diagonal act on all segments
+ * at once as on any context (they are local to elements and nodes). */
 int tsgls_set_segments(tsgls_ctx* ctx, int nseg);
 
 /* Newton-GMRES on every segment at once, in lockstep: each Newton step
@@ -293,7 +296,9 @@ int tsgls_set_segments(tsgls_ctx* ctx, int nseg);
  * its size would use, so segment s follows, bit for bit, the iteration of
  * tsgls_solve with gmres_graph = 1 on a context holding problem s alone.  A
  * segment that has converged (or reached max_newton / max_matvec) sits out
- * the rest with zero updates; its state is no longer changed.  Options as
+ * the rest with zero updates; its state is no longer changed, and the
+ * kernels skip it (the element operator runs over a device list of the
+ * segments taking part when the segments have equal element counts).  Options as
  * tsgls_solve with restart <= 32 and the fixed schedule (TSGLS_EINVAL
  * otherwise); gmres_graph is implied.  stats: host [nseg] (per segment;
  * seconds = time from the call's start until that segment finished);

@@ -540,8 +540,9 @@ hipError_t launch_multiaxpy_add(const double* V, int64_t ldv, int J, const doubl
 
 // ------------------------------------------- device-side GMRES least squares
 // The host-side update of the delayed Gram-Schmidt GMRES (host.cpp,
-// gmres_delayed) on one thread, so that a whole cycle runs without the host
-// and can be captured as a graph.  State (GmDev): unrotated Hessenberg H and
+// gmres_delayed) on the device, one wave per GMRES (rows of a Hessenberg
+// column in parallel, the Givens rotations on one lane), so that a whole
+// cycle runs without the host and can be captured as a graph.  State (GmDev): unrotated Hessenberg H and
 // its rotated finalized columns R (column-major, leading dimension m+1),
 // rotations, the rotated right-hand side g, the update scalars sc and the
 // status st = {k committed columns, cycle over, finalize pending, converged}.
