@@ -579,6 +579,25 @@ k_gather(const int32_t* __restrict__ noff, const int32_t* __restrict__ ninc,
 #pragma unroll
   for (int r = 0; r < NJ; ++r) acc[r] = 0.0;
   int k = k0;
+  // eight rows in flight, then four, then one: the sum runs over the rows in
+  // ascending order whatever the blocking
+  for (; k + 8 <= k1; k += 8) {
+    int64_t ii[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ii[u] = (int64_t)ninc[k + u] * R;
+#pragma unroll
+    for (int r = 0; r < NJ; ++r) {
+      if (src[r] >= 0) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = ebuf[ii[u] + src[r]];   // FP64 sum
+        double t = acc[r];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t = t + a[u];
+        acc[r] = t;
+      }
+    }
+  }
   for (; k + 4 <= k1; k += 4) {
     const int64_t i0 = (int64_t)ninc[k] * R, i1 = (int64_t)ninc[k + 1] * R;
     const int64_t i2 = (int64_t)ninc[k + 2] * R, i3 = (int64_t)ninc[k + 3] * R;
