@@ -678,7 +678,9 @@ def junction_time_to_1e8():
     size from 0.1 bounded by 2, GMRES(100) to 0.1; FP64 tangent, FP32
     tangent and FP32 tangent with tau in bf16 (FP64 residual and Krylov).
     Then K = 6 with the FP32 tangent, the step unbounded and 3,000 products
-    per linear solve."""
+    per linear solve.  Returns the summary and, when the FP64 solve
+    converged, (problem, its converged state, flow summary) for the tracer
+    leg, else None."""
     import torch
     import paper_2311_09465_amd as T
     from workloads import junction_problem, initial_guess
@@ -686,10 +688,14 @@ def junction_time_to_1e8():
     s = T.Solver.from_problem(prob)
     out = dict(workload="junction_200k_K3_Re100", n_tets=prob.mesh.n_tets, n_nodes=prob.mesh.n_nodes,
                solver={k: v for k, v in JUNCTION_SOLVE.items()})
+    flow = None
     for prec in ("f64", "f32", "bf16"):
         y = torch.from_numpy(initial_guess(prob)).cuda()
         torch.cuda.synchronize()
         st = s.solve(y, tangent_precision=prec, **JUNCTION_SOLVE)
+        if prec == "f64" and st["status"] == 0:
+            flow = (prob, y, dict(status=st["status"], rel_residual=st["rel_residual"],
+                                  seconds=round(st["seconds"], 3), tangent="f64"))
         out[prec] = dict(seconds=round(st["seconds"], 3), status="converged" if st["status"] == 0
                          else "not converged", newton_iters=st["newton_iters"], matvecs=st["matvecs"],
                          rel_residual=float("%.3e" % st["rel_residual"]), rejected=st["rejected"])
@@ -712,7 +718,7 @@ def junction_time_to_1e8():
                          short_linear_solves=st["lin_unconverged"])
     print(f"junction 200k K=6 time to 1e-8 (f32): {out['K6_f32']}", file=sys.stderr, flush=True)
     s.close()
-    return out
+    return out, flow
 
 
 def mode_sweep_200k(ks=(3, 7, 15, 31), reps=20):
@@ -932,16 +938,24 @@ def tracer_junction(args):
     (at most 20,000 products); products, time and the range of phi over the
     nodes at 3K+1 instants (within [0, 1] for the exact solution).  Prints
     one JSON line."""
-    import numpy as np
     import torch
     import paper_2311_09465_amd as T
     from workloads import junction_problem, initial_guess
     prob = junction_problem(h=0.081, K=3, Re=100.0)
-    K = prob.K
     ns = T.Solver.from_problem(prob)
     yv = torch.from_numpy(initial_guess(prob)).cuda()
     stn = ns.solve(yv, tangent_precision="f32", **JUNCTION_SOLVE)
     print(f"flow: {stn['status']} {stn['rel_residual']:.2e} {stn['seconds']:.1f}s", file=sys.stderr, flush=True)
+    flow = dict(status=stn["status"], rel_residual=stn["rel_residual"], seconds=round(stn["seconds"], 3))
+    print(json.dumps(tracer_junction_run(prob, yv, flow)), flush=True)
+
+
+def tracer_junction_run(prob, yv, flow, outlet_cases=("dirichlet", "natural")):
+    """The tracer runs of tracer_junction on the converged flow yv of prob."""
+    import numpy as np
+    import torch
+    import paper_2311_09465_amd as T
+    K = prob.K
 
     def nodes(t):
         return np.unique(np.asarray(t).ravel())
@@ -954,7 +968,7 @@ def tracer_junction(args):
     t = 2 * np.pi * np.arange(M) / M
     runs = []
     # outlets: zero Dirichlet (the paper's test of a rapid jump) or natural with the backflow term
-    for outlets in ("dirichlet", "natural"):
+    for outlets in outlet_cases:
       for kappa in (0.005, 0.001):
         for stab in (True, False):
             s = T.Solver(prob.mesh.xyz, prob.mesh.tets, K, prob.rho, prob.mu, prob.omega,
@@ -981,14 +995,11 @@ def tracer_junction(args):
                              phi_min=float("%.3e" % vals.min()), phi_max=float("%.3e" % vals.max())))
             print(runs[-1], file=sys.stderr, flush=True)
             s.close()
-    print(json.dumps({"metric": "tracer on the junction: GLS vs Galerkin, GMRES products to 1e-8 and "
-                                "range of phi",
-                      "n_gpus": 1, "data": "synthetic (converged junction flow, Re 100)",
-                      "config": dict(workload="junction_200k_K3_Re100_tracer", n_tets=prob.mesh.n_tets,
-                                     K=K, restart=100, preconditioner="none", backflow_beta=0.5),
-                      "flow": dict(status=stn["status"], rel_residual=stn["rel_residual"],
-                                   seconds=round(stn["seconds"], 3)),
-                      "runs": runs}), flush=True)
+    return {"metric": "tracer on the junction: GLS vs Galerkin, GMRES products to 1e-8 and range of phi",
+            "n_gpus": 1, "data": "synthetic (converged junction flow, Re 100)",
+            "config": dict(workload="junction_200k_K3_Re100_tracer", n_tets=prob.mesh.n_tets,
+                           K=K, restart=100, preconditioner="none", backflow_beta=0.5),
+            "flow": flow, "runs": runs}
 
 
 def tau_entry(prof, K, E, args):
@@ -1241,7 +1252,12 @@ def main():
             time_to_1e8_womersley_6k_K3_status=stw["status"])
         del sw
         if not args.no_solves:
-            out["time_to_1e8_junction"] = junction_time_to_1e8()
+            out["time_to_1e8_junction"], flow = junction_time_to_1e8()
+            if flow is not None:
+                # the tracer carried by the converged flow, outlets held at zero
+                # (the paper's case): GLS against Galerkin
+                print("tracer on the junction", file=sys.stderr, flush=True)
+                out["tracer_junction"] = tracer_junction_run(*flow, outlet_cases=("dirichlet",))
             out["junction_re500_pseudo_time"] = junction_re500_attempt(prob)
             out["mode_sweep"] = mode_sweep_200k()
             print("batched solves", file=sys.stderr, flush=True)
