@@ -666,9 +666,9 @@ def learned_run(ntr, nte, r, hidden=4, steps=3000, precision="bf16"):
 
 JUNCTION_SOLVE = dict(rtol=1e-8, lin_rtol=0.1, restart=100, max_newton=150, max_matvec=10000,
                       jacobian="newton", dt_pseudo=0.1, dt_schedule="ser", dt_max=2.0)
-# K = 6: unbounded step, 3,000 products per linear solve (a short solve halves
-# the next step)
-JUNCTION_SOLVE_K6 = dict(JUNCTION_SOLVE, max_newton=250, max_matvec=3000, dt_max=0.0)
+# K = 6: unbounded step, GMRES(60), 3,000 products per linear solve (a short
+# solve halves the next step)
+JUNCTION_SOLVE_K6 = dict(JUNCTION_SOLVE, max_newton=250, max_matvec=3000, dt_max=0.0, restart=60)
 
 
 def junction_time_to_1e8():
@@ -677,8 +677,8 @@ def junction_time_to_1e8():
     iteration per step (Newton tangent, tau frozen), switched-evolution step
     size from 0.1 bounded by 2, GMRES(100) to 0.1; FP64 tangent, FP32
     tangent and FP32 tangent with tau in bf16 (FP64 residual and Krylov).
-    Then K = 6 with the FP32 tangent, the step unbounded and 3,000 products
-    per linear solve.  Returns the summary and, when the FP64 solve
+    Then K = 6 with the FP32 tangent, the step unbounded, GMRES(60) and
+    3,000 products per linear solve.  Returns the summary and, when the FP64 solve
     converged, (problem, its converged state, flow summary) for the tracer
     leg, else None."""
     import torch
