@@ -928,6 +928,27 @@ def tracer(args):
                                        runs=back)}), flush=True)
 
 
+def junction_solve(args):
+    """One leg of time_to_1e8_junction alone: the 200k-tet junction (h =
+    0.081, K = 3, Re = 100, Wo = 10) from the initial guess to 1e-8 with the
+    same pseudo-time settings and the given tangent precision, printing each
+    pseudo-time step (so that a kernel trace of the whole solve can be taken).
+    Prints one JSON line."""
+    import torch
+    import paper_2311_09465_amd as T
+    from workloads import junction_problem, initial_guess
+    prob = junction_problem(h=0.081, K=3, Re=100.0)
+    s = T.Solver.from_problem(prob)
+    y = torch.from_numpy(initial_guess(prob)).cuda()
+    torch.cuda.synchronize()
+    st = s.solve(y, tangent_precision=args.junction_solve, verbose=True, **JUNCTION_SOLVE)
+    print(json.dumps(dict(workload="junction_200k_K3_Re100", tangent=args.junction_solve,
+                          solver=dict(JUNCTION_SOLVE), seconds=round(st["seconds"], 3),
+                          status="converged" if st["status"] == 0 else "not converged",
+                          newton_iters=st["newton_iters"], matvecs=st["matvecs"],
+                          rel_residual=float("%.3e" % st["rel_residual"]))), flush=True)
+
+
 def tracer_junction(args):
     """Tracer on the 200k-tet junction (h = 0.081, K = 3, Re = 100, Wo = 10)
     carried by its converged periodic flow (pseudo-time solve to 1e-8):
@@ -1051,6 +1072,8 @@ def main():
                     help="tracer equation: GLS against Galerkin on the pipe flow")
     ap.add_argument("--tracer-junction", action="store_true",
                     help="tracer equation: GLS against Galerkin on the 200k junction flow")
+    ap.add_argument("--junction-solve", default=None, choices=["f64", "f32", "bf16"],
+                    help="one solve of the 200k junction to 1e-8 (K = 3) with this tangent, steps printed")
     ap.add_argument("--learned", type=int, default=0, metavar="N_TRAIN",
                     help="learned warm-start measurement with N_TRAIN training solves")
     ap.add_argument("--learned-test", type=int, default=32)
@@ -1099,6 +1122,9 @@ def main():
         return
     if args.tracer_junction:
         tracer_junction(args)
+        return
+    if args.junction_solve:
+        junction_solve(args)
         return
     prob, cfg = _workload(args.workload)
     s = T.Solver.from_problem(prob)
