@@ -88,9 +88,16 @@ __device__ __forceinline__ float swap_pair(float x) {
 
 // Waves per SIMD the register allocation must allow: the Picard tangent
 // (the launch repeated inside GMRES) fits three without spilling in FP64,
-// four in FP32.
-template <int MODE, typename T>
-constexpr int op_waves() { return (MODE & ~(MODE_TAU16 | MODE_SEG)) == 0 ? (sizeof(T) == 4 ? 4 : 3) : 1; }
+// four in FP32; so does the Newton tangent in FP32 up to K = 4 (at most 126
+// VGPRs; from K = 5 on four would spill).  The FP64 Newton tangent keeps what
+// it needs (198 registers at K = 3, two waves: three spill and run slower).
+template <int K, int MODE, typename T>
+constexpr int op_waves() {
+  constexpr int m = MODE & ~(MODE_TAU16 | MODE_SEG);
+  if (m == 0) return sizeof(T) == 4 ? 4 : 3;
+  if (m == MODE_NEWTON && sizeof(T) == 4 && K <= 4) return 4;
+  return 1;
+}
 
 // bf16 bit pattern -> FP32 (bf16 is the top half of an FP32 word)
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -142,7 +149,7 @@ __device__ __forceinline__ Frozen<T> frozen(const DevView& v) {
 // direction samples (tangent modes); out: [E][4][4][n] element rows; Zout
 // (MODE_STOREZ, FP64 only): tau L(u) [E][4][3][n].
 template <int K, int MODE, typename T>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(op_waves<MODE, T>())))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(op_waves<K, MODE, T>())))
 k_op(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
      double* __restrict__ Zout, T* __restrict__ out, T shift, int64_t begin, int64_t end) {
   using C = OpCfg<K>;
