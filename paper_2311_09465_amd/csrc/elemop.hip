@@ -89,13 +89,14 @@ __device__ __forceinline__ float swap_pair(float x) {
 // Waves per SIMD the register allocation must allow: the Picard tangent
 // (the launch repeated inside GMRES) fits three without spilling in FP64,
 // four in FP32; so does the Newton tangent in FP32 up to K = 4 (at most 126
-// VGPRs; from K = 5 on four would spill).  The FP64 Newton tangent keeps what
-// it needs (198 registers at K = 3, two waves: three spill and run slower).
+// VGPRs; from K = 5 on four would spill), and in FP64 up to K = 3 three
+// (at most 164 VGPRs) once it re-reads the velocity samples for the
+// least-squares products instead of keeping them (see KEEPU in k_op).
 template <int K, int MODE, typename T>
 constexpr int op_waves() {
   constexpr int m = MODE & ~(MODE_TAU16 | MODE_SEG);
   if (m == 0) return sizeof(T) == 4 ? 4 : 3;
-  if (m == MODE_NEWTON && sizeof(T) == 4 && K <= 4) return 4;
+  if (m == MODE_NEWTON && K <= (sizeof(T) == 4 ? 4 : 3)) return sizeof(T) == 4 ? 4 : 3;
   return 1;
 }
 
@@ -160,7 +161,11 @@ k_op(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
   constexpr bool NEWTON = (MODE & MODE_NEWTON) != 0;
   constexpr bool NOLS = (MODE & MODE_NOLS) != 0;
   constexpr bool STOREZ = (MODE & MODE_STOREZ) != 0;
-  constexpr bool KEEPU = C::KEEPU;
+  // u_q(t_s) of the products phase is kept in registers for the
+  // least-squares phase, except in the FP64 Newton tangent at K <= 3, where
+  // its 24 VGPRs stand between two and three waves per SIMD: there the
+  // samples are read again (the same arithmetic on the same values).
+  constexpr bool KEEPU = C::KEEPU && !(NEWTON && sizeof(T) == 8 && K <= 3);
   constexpr int NL = NOLS ? 2 : 1;
   using R = Mma<T>;
   typedef typename R::v4 T4;
