@@ -89,14 +89,16 @@ __device__ __forceinline__ float swap_pair(float x) {
 // Waves per SIMD the register allocation must allow: the Picard tangent
 // (the launch repeated inside GMRES) fits three without spilling in FP64,
 // four in FP32; so does the Newton tangent in FP32 up to K = 4 (at most 126
-// VGPRs; from K = 5 on four would spill), and in FP64 up to K = 3 three
-// (at most 164 VGPRs) once it re-reads the velocity samples for the
-// least-squares products instead of keeping them (see KEEPU in k_op).
+// VGPRs; from K = 5 on four would spill).  In FP64 the Newton tangent fits
+// three up to K = 3 (at most 164 VGPRs) and two up to K = 7 (at most 254)
+// once it re-reads the velocity samples for the least-squares products
+// instead of keeping them (see KEEPU in k_op).
 template <int K, int MODE, typename T>
 constexpr int op_waves() {
   constexpr int m = MODE & ~(MODE_TAU16 | MODE_SEG);
   if (m == 0) return sizeof(T) == 4 ? 4 : 3;
   if (m == MODE_NEWTON && K <= (sizeof(T) == 4 ? 4 : 3)) return sizeof(T) == 4 ? 4 : 3;
+  if (m == MODE_NEWTON && sizeof(T) == 8 && K <= 7) return 2;
   return 1;
 }
 
@@ -162,10 +164,11 @@ k_op(DevView v, const T* __restrict__ XP, const T* __restrict__ VT,
   constexpr bool NOLS = (MODE & MODE_NOLS) != 0;
   constexpr bool STOREZ = (MODE & MODE_STOREZ) != 0;
   // u_q(t_s) of the products phase is kept in registers for the
-  // least-squares phase, except in the FP64 Newton tangent at K <= 3, where
-  // its 24 VGPRs stand between two and three waves per SIMD: there the
-  // samples are read again (the same arithmetic on the same values).
-  constexpr bool KEEPU = C::KEEPU && !(NEWTON && sizeof(T) == 8 && K <= 3);
+  // least-squares phase, except in the FP64 Newton tangent, where its 24
+  // VGPRs cost a wave per SIMD (two against three at K = 3, one against two
+  // at K = 6): there the samples are read again (the same arithmetic on the
+  // same values).
+  constexpr bool KEEPU = C::KEEPU && !(NEWTON && sizeof(T) == 8 && K <= 7);
   constexpr int NL = NOLS ? 2 : 1;
   using R = Mma<T>;
   typedef typename R::v4 T4;
